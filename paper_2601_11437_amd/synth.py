@@ -1,0 +1,115 @@
+"""Seeded synthetic inputs: locations and zero-mean Gaussian random field draws.
+
+This module is shared by the tests, the benchmark and the oracle-side checks.
+It holds none of the likelihood, score or Fisher arithmetic; it only *draws*
+data.  Field draws use third-party routines (numpy exp, SciPy's Bessel K,
+LAPACK Cholesky via numpy), never the oracle or the HIP library.
+
+Recipe (every stream is numpy Generator(PCG64(seed))):
+  * uniform design: n locations iid U([0,1]^2), drawn first;
+  * jittered grid: m x m cell centres (i + 1/2)/m plus independent
+    U(-jitter, jitter)/m per coordinate;
+  * field: w ~ N(0, I_n) drawn after the locations from the same stream,
+    Z = L w with L L^T = Sigma(theta_true) the Matern covariance of Section 2.1
+    (no nugget).  If Sigma(theta_true) fails the Cholesky factorisation, the
+    draw is repeated with seed + 1, + 2, ... and the number of redraws is
+    reported.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(int(seed)))
+
+
+def uniform_locations(n: int, gen: np.random.Generator) -> np.ndarray:
+    return gen.random((int(n), 2))
+
+
+def jittered_grid(m: int, gen: np.random.Generator, jitter: float = 0.4) -> np.ndarray:
+    i, j = np.meshgrid(np.arange(m), np.arange(m), indexing="ij")
+    centres = np.stack([(i.ravel() + 0.5) / m, (j.ravel() + 0.5) / m], axis=1)
+    return centres + gen.uniform(-jitter, jitter, size=centres.shape) / m
+
+
+def _matern_for_simulation(h: np.ndarray, theta) -> np.ndarray:
+    """Matern covariance used only to simulate data (library routines)."""
+    from scipy.special import gamma, kv
+
+    s2, a, nu = (float(t) for t in theta)
+    x = h / a
+    if nu == 0.5:
+        return s2 * np.exp(-x)
+    if nu == 1.5:
+        return s2 * (1.0 + x) * np.exp(-x)
+    if nu == 2.5:
+        return s2 * (1.0 + x + x * x / 3.0) * np.exp(-x)
+    out = np.full_like(x, s2)
+    pos = x > 0
+    xp = x[pos]
+    out[pos] = s2 * (2.0 ** (1.0 - nu) / gamma(nu)) * xp ** nu * kv(nu, xp)
+    return out
+
+
+def grf(locs: np.ndarray, theta, gen: np.random.Generator) -> np.ndarray:
+    """One realisation Z ~ N(0, Sigma(theta)); raises LinAlgError if not PD."""
+    n = locs.shape[0]
+    S = np.empty((n, n))
+    blk = 2048
+    for r0 in range(0, n, blk):       # bounded temporaries at large n
+        d = locs[r0:r0 + blk, None, :] - locs[None, :, :]
+        S[r0:r0 + blk] = _matern_for_simulation(np.sqrt(np.einsum("ijk,ijk->ij", d, d)), theta)
+    L = np.linalg.cholesky(S)
+    del S
+    w = gen.standard_normal(n)
+    return L @ w
+
+
+def dataset(n: int, theta_true, seed: int, design: str = "uniform", max_redraws: int = 20):
+    """(locs, z, info) for a uniform or jittered-grid design."""
+    for redraw in range(max_redraws + 1):
+        gen = rng(seed + redraw)
+        if design == "uniform":
+            locs = uniform_locations(n, gen)
+        elif design == "grid":
+            m = int(round(np.sqrt(n)))
+            if m * m != n:
+                raise ValueError("grid design needs a square n")
+            locs = jittered_grid(m, gen)
+        else:
+            raise ValueError(design)
+        try:
+            z = grf(locs, theta_true, gen)
+        except np.linalg.LinAlgError:
+            continue
+        return locs, z, {"seed": seed, "redraws": redraw, "design": design,
+                         "theta_true": tuple(float(t) for t in theta_true), "n": n}
+    raise RuntimeError("no positive-definite draw within %d redraws" % max_redraws)
+
+
+def random_thetas(k: int, seed: int, s2=(0.5, 2.0), alpha=(0.02, 0.3), nu=(0.3, 3.0)):
+    """k parameter vectors drawn uniformly from a box."""
+    gen = rng(seed)
+    return np.stack([gen.uniform(*s2, k), gen.uniform(*alpha, k), gen.uniform(*nu, k)], axis=1)
+
+
+# Named workloads (sizes of the paper's simulation settings and of the
+# benchmark): n, theta_true, design, seed.
+WORKLOADS = {
+    # Fisher-BT from theta0 = (0.5, 0.05, 1.0) on 400 uniform points.
+    "n400": dict(n=400, theta_true=(1.0, 0.1, 0.5), design="uniform", seed=1),
+    # Headline evaluation size: 20,000 uniform points, theta = (1, 0.1, 0.5).
+    "n20k": dict(n=20000, theta_true=(1.0, 0.1, 0.5), design="uniform", seed=20000),
+    # Differentiation check: 10,000 uniform points, theta = (1, 0.1, 1.5).
+    "n10k_diff": dict(n=10000, theta_true=(1.0, 0.1, 1.5), design="uniform", seed=3000),
+}
+
+
+def grid_workload(i_beta: int, i_nu: int):
+    """The 3 x 3 jittered-grid settings on a 100 x 100 grid."""
+    betas = (0.03, 0.1, 0.3)
+    nus = (0.5, 1.0, 2.5)
+    return dict(n=10000, theta_true=(1.0, betas[i_beta], nus[i_nu]), design="grid",
+                seed=1000 + 3 * i_beta + i_nu)
