@@ -1,0 +1,141 @@
+#!/usr/bin/env python3
+"""Throughput of the exact Matern log-likelihood + score + Fisher evaluation
+(Algorithm 3) on one MI355X.
+
+One step = one evaluation of (l, grad l, I) over the full n x n covariance at
+the workload's theta: covariance and derivative generation, tiled FP64
+Cholesky, log-determinant and solve, the two triangular solves forming
+W_i = L^{-1} Sigma_i L^{-T} and the trace reductions.  Inputs are resident on
+the device before timing starts.  Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "loglik+score+Fisher evals/s at n=20k, FP64 vs mixed; % of MFMA peak"
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(n_full, n_sample, theta, seed):
+    """The oracle as it stands, one evaluation on a smaller instance of the
+    same workload, scaled by n^3 (the evaluation is O(n^3))."""
+    import oracle
+    from paper_2601_11437_amd import synth
+
+    oracle.build(force=False)
+    locs, z, _ = synth.dataset(n_sample, theta, seed)
+    t0 = time.perf_counter()
+    oracle.evaluate(locs, z, theta)
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": (1.0 / dt) * (n_sample / n_full) ** 3, "unit": "evals/s",
+            "cores": threads, "kind": "oracle",
+            "sample": "one oracle evaluation at n=%d (uniform locations, theta=%s) took %.2f s; "
+                      "scaled by (%d/%d)^3 to n=%d" % (n_sample, list(theta), dt, n_sample, n_full,
+                                                       n_full)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=20000)
+    ap.add_argument("--cpu-sample-n", type=int, default=4000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the single-field evaluation is not sharded "
+              "across GPUs in this build (see the design notes); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+
+    import paper_2601_11437_amd as fbt
+    from paper_2601_11437_amd import synth
+
+    w = dict(synth.WORKLOADS["n20k"])
+    n = args.n
+    theta = w["theta_true"]
+    t0 = time.perf_counter()
+    locs, z, info = synth.dataset(n, theta, w["seed"])
+    log("data: n=%d generated in %.1f s" % (n, time.perf_counter() - t0))
+
+    ctx = fbt.Context(0)
+    ctx.set_data(locs, z)
+    for i in range(args.warmup):
+        ctx.eval(theta)
+        log("warmup step %d done" % i)
+    ctx.set_timing(True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ll, score, fisher = ctx.eval(theta)
+        log("step %d done (loglik %.6f)" % (i, ll))
+    dt = time.perf_counter() - t0
+    tim = ctx.timing()
+    ctx.set_timing(False)
+    # loglik-only rate (Algorithm 2), for context
+    t1 = time.perf_counter()
+    for i in range(max(1, args.steps)):
+        ctx.loglik(theta)
+    dt_ll = (time.perf_counter() - t1) / max(1, args.steps)
+
+    evals_per_s = args.steps / dt
+    phases = {}
+    for name, v in tim.items():
+        if v["launches"]:
+            phases[name] = {"launches_per_step": v["launches"] / args.steps,
+                            "ms_per_step": v["ms"] / args.steps,
+                            "tflops": (v["flops"] / (v["ms"] * 1e-3) / 1e12) if v["flops"] and v["ms"] else None}
+    # dominant kernel: the one with the most time
+    dom = max((k for k in tim if tim[k]["flops"] > 0), key=lambda k: tim[k]["ms"])
+    d = tim[dom]
+    achieved = d["flops"] / (d["ms"] * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                "launches": d["launches"], "avg_launch_ms": d["ms"] / d["launches"],
+                "flops_per_launch": d["flops"] / d["launches"]}
+    total_fl = sum(v["flops"] for v in tim.values())
+    total_ms = sum(v["ms"] for v in tim.values())
+    out = {
+        "metric": METRIC,
+        "value": evals_per_s,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "Matern GRF, n=%d uniform on [0,1]^2, theta=(sigma2, alpha, nu)=%s, "
+                               "one loglik+score+Fisher evaluation per step" % (n, list(theta)),
+                   "n": n, "theta": list(theta), "precision": "fp64", "tile": 256},
+        "roofline": roofline,
+        "whole_eval_tflops": total_fl / (total_ms * 1e-3) / 1e12 if total_ms else None,
+        "fp64_frac_whole_eval": total_fl / dt / 1e12 / PEAK_FP64_TFLOPS,
+        "loglik_only_evals_per_s": 1.0 / dt_ll,
+        "phases": phases,
+        "result": {"loglik": ll, "score": score.tolist(), "fisher_diag": np.diag(fisher).tolist()},
+    }
+    ctx.close()
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) at n=%d ..." % args.cpu_sample_n)
+        out["cpu_baseline"] = cpu_baseline(n, args.cpu_sample_n, theta, w["seed"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,188 @@
+/*
+ * fisherbt.h -- C ABI of the MI355X (gfx950) library for exact Matern
+ * maximum-likelihood estimation by Fisher scoring with backtracking
+ * (Fisher-BT).
+ *
+ * Model (Section 2.1): a zero-mean Gaussian random field on R^2 observed at
+ * locations s_1..s_n, with Matern covariance
+ *     C(h; theta) = sigma2 2^(1-nu) / Gamma(nu) (h/alpha)^nu K_nu(h/alpha),
+ * theta = (sigma2, alpha, nu), h the Euclidean distance.  (alpha is the range
+ * parameter, sometimes written beta.)
+ *
+ * Conventions shared by every call:
+ *   - theta is always double[3] = {sigma2, alpha, nu}; each must be finite and
+ *     > 0, otherwise the call returns FBT_EINVAL and writes nothing.
+ *   - Output pointers are host memory owned by the caller and are written only
+ *     when the call returns FBT_OK.  Matrices are returned column-major.
+ *   - Every call is synchronous with respect to the host; device work is
+ *     ordered on the context's HIP stream, so other work on that stream (for
+ *     example PyTorch's) is ordered with it.
+ *   - One context per host thread; contexts share nothing.
+ *   - Errors are negative.  FBT_ENOTPD is recoverable (Sigma(theta) is not
+ *     numerically positive definite); FBT_EDEVICE and FBT_ENOMEM are not.
+ *   - All arithmetic on the evaluation path is IEEE FP64.
+ */
+#ifndef FISHERBT_H
+#define FISHERBT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fbt_ctx fbt_ctx; /* opaque; owns its device buffers */
+
+typedef enum {
+    FBT_OK = 0,
+    FBT_EINVAL = -1,     /* bad argument (NULL, n < 1, non-finite input, theta <= 0, ...) */
+    FBT_ENOTPD = -2,     /* Cholesky met a pivot <= 0 or NaN; see fbt_last_notpd_pivot */
+    FBT_ENOMEM = -3,     /* device or pinned-host allocation failed */
+    FBT_EDEVICE = -4,    /* HIP runtime error or no gfx950 device */
+    FBT_ENONFINITE = -5, /* a result came out non-finite */
+    FBT_EBUDGET = -6,    /* fit: call budget exhausted with the Nelder-Mead fallback off */
+    FBT_ENODATA = -7     /* no data set on the context */
+} fbt_status;
+
+typedef struct {
+    int32_t device;   /* HIP device ordinal */
+    int32_t tile;     /* block size of the tiled factorisation; 0 = default (256); only 256 */
+    int32_t reserved; /* must be 0 */
+    void *hip_stream; /* hipStream_t to order work on; NULL = the library creates its own */
+} fbt_config;
+
+/* Create a context on cfg->device.  On success *out owns a stream (unless one
+ * was given) and no data.  Errors: FBT_EINVAL (NULL args, unsupported tile),
+ * FBT_EDEVICE (no such device, or not gfx950). */
+fbt_status fbt_create(const fbt_config *cfg, fbt_ctx **out);
+
+/* Release every resource of ctx.  NULL is a no-op. */
+void fbt_destroy(fbt_ctx *ctx);
+
+/* Observations (Section 2.1): n locations as an n x 2 row-major array
+ * (x_i, y_i) and the n observations Z.  Both host arrays are copied; the
+ * caller keeps ownership.  Device buffers are (re)allocated for n: about
+ * 3 n_pad^2 doubles with n_pad = 256 ceil((n + 1) / 256).
+ * Errors: FBT_EINVAL (NULL, n < 1, non-finite input), FBT_ENOMEM. */
+fbt_status fbt_set_data(fbt_ctx *ctx, int64_t n, const double *locs_xy, const double *z);
+
+/* Same as fbt_set_data with device pointers (on ctx's device).  The arrays
+ * are copied on the context's stream before the call returns, so the caller
+ * may free them afterwards. */
+fbt_status fbt_set_data_device(fbt_ctx *ctx, int64_t n, const double *d_locs_xy, const double *d_z);
+
+/* Algorithm 2: exact log-likelihood, Eq. (1),
+ *     l(theta) = -n/2 log(2 pi) - 1/2 log det Sigma - 1/2 Z^T Sigma^{-1} Z,
+ * by a tiled Cholesky factorisation of Sigma(theta).  The factor is kept, so a
+ * following fbt_eval at the same theta reuses it.
+ * Errors: FBT_EINVAL, FBT_ENODATA, FBT_ENOTPD, FBT_EDEVICE. */
+fbt_status fbt_loglik(fbt_ctx *ctx, const double theta[3], double *loglik);
+
+/* Algorithm 3: log-likelihood, score (Eq. (2)) and expected Fisher information
+ * (Eq. (3)) over theta = (sigma2, alpha, nu).  The traces are formed as
+ * Frobenius products of W_i = L^{-1} Sigma_i L^{-T} (Eq. (5) is the same
+ * identity); dSigma/dnu is the exact derivative of the Matern covariance.
+ * score[3]; fisher[9] is the full symmetric 3 x 3 matrix, row-major.
+ * Errors: as fbt_loglik. */
+fbt_status fbt_eval(fbt_ctx *ctx, const double theta[3], double *loglik, double score[3],
+                    double fisher[9]);
+
+/* The intermediate scalars of Algorithm 3 at theta (for checking): terms[9] =
+ * { log det Sigma, Z^T Sigma^{-1} Z, tr(Sigma^{-1} Sigma_alpha),
+ *   tr(Sigma^{-1} Sigma_nu), w^T Sigma_alpha w, w^T Sigma_nu w,
+ *   tr(Sigma^{-1} Sigma_a Sigma^{-1} Sigma_a), tr(.. a .. nu), tr(.. nu .. nu) }
+ * with w = Sigma^{-1} Z.  Errors: as fbt_loglik. */
+fbt_status fbt_eval_terms(fbt_ctx *ctx, const double theta[3], double terms[9]);
+
+/* Covariance generation (Section 2.1, and Section 2.2 for the derivatives):
+ * writes the n x n matrix Sigma (which = 0), Sigma_alpha (1) or Sigma_nu (2)
+ * at theta into out (host, column-major, leading dimension ld >= n).
+ * Errors: FBT_EINVAL, FBT_ENODATA, FBT_EDEVICE. */
+fbt_status fbt_covariance(fbt_ctx *ctx, const double theta[3], int32_t which, double *out,
+                          int64_t ld);
+
+/* The lower Cholesky factor L of Sigma(theta) (Algorithm 2, second step) into
+ * out (host, column-major, ld >= n); the strict upper triangle is zeroed.
+ * Errors: as fbt_loglik. */
+fbt_status fbt_factor(fbt_ctx *ctx, const double theta[3], double *out, int64_t ld);
+
+/* ---------------------------------------------------------------- fit ---- */
+
+/* Called after every accepted Fisher-scoring iterate (iter 0 is the start). */
+typedef void (*fbt_iter_cb)(void *user, int32_t iter, const double theta[3], double loglik,
+                            const double score[3], const double fisher[9]);
+
+/* Options of Algorithm 1; fbt_fit_options_default fills the paper's values. */
+typedef struct {
+    const double *theta0;     /* NULL: L9 start of Table 1 from [lo, hi] */
+    double lo[3], hi[3];      /* (0.01, 0.01, 0.01), (5, 5, 2) */
+    double armijo_c;          /* 1e-3   Eq. (4) */
+    double armijo_relax;      /* 1e-3   relaxation of Eq. (4) */
+    double backtrack_rho;     /* 0.5 */
+    double grad_tol;          /* 1e-3   stop when ||grad l||_2 <= grad_tol */
+    int32_t max_loglik_calls; /* 60     shift beyond this many l calls (L9 included) */
+    int32_t max_grad_calls;   /* 20     shift beyond this many grad calls */
+    int32_t max_iter;         /* 0 = no limit on accepted steps */
+    int32_t nelder_mead;      /* 1: Nelder-Mead fallback on shift; 0: return FBT_EBUDGET */
+    double nm_ftol;           /* 1e-9   Nelder-Mead stop: spread of l over the simplex */
+    int32_t nm_max_evals;     /* 500 */
+    fbt_iter_cb cb;           /* may be NULL */
+    void *cb_user;
+} fbt_fit_options;
+
+typedef struct {
+    double theta[3], loglik, score[3], fisher[9];
+    int32_t n_loglik_calls, n_grad_calls, n_iter, used_nelder_mead, converged, n_nm_evals;
+} fbt_fit_result;
+
+void fbt_fit_options_default(fbt_fit_options *o);
+
+/* Algorithm 1 (Fisher-BT): L9 start, Fisher scoring phi = I^{-1} grad with the
+ * relaxed Armijo backtracking of Eq. (4), stop at ||grad|| <= grad_tol, shift
+ * to Nelder-Mead when a call budget is exceeded, then one Fisher evaluation
+ * at the result.  Every l and derivative evaluation runs on the GPU.
+ * Errors: FBT_EINVAL, FBT_ENODATA, FBT_ENOTPD (every L9 candidate failed),
+ * FBT_EBUDGET (budget exhausted with nelder_mead = 0; *out still holds the
+ * last iterate), FBT_EDEVICE. */
+fbt_status fbt_fit(fbt_ctx *ctx, const fbt_fit_options *opt, fbt_fit_result *out);
+
+/* Algorithm 1 over any evaluator.  fbt_fit runs this with the GPU evaluator
+ * of ctx; other evaluators (a CPU model, a test double) use the same driver.
+ * loglik/eval return FBT_OK, FBT_ENOTPD (the trial counts as l = -inf) or
+ * another error (the fit stops and returns it).  No device is touched here. */
+typedef struct {
+    void *user;
+    fbt_status (*loglik)(void *user, const double theta[3], double *loglik);
+    fbt_status (*eval)(void *user, const double theta[3], double *loglik, double score[3],
+                       double fisher[9]);
+} fbt_evaluator;
+
+fbt_status fbt_fit_evaluator(const fbt_evaluator *ev, const fbt_fit_options *opt,
+                             fbt_fit_result *out);
+
+/* The nine L9 starting candidates of Table 1 for the cube [lo, hi], row-major 9 x 3. */
+void fbt_l9_design(const double lo[3], const double hi[3], double out[27]);
+
+/* ---------------------------------------------------------- diagnostics -- */
+
+const char *fbt_status_string(fbt_status s);
+/* Detail of the last error on ctx (static storage in ctx; valid until the next call). */
+const char *fbt_last_error(const fbt_ctx *ctx);
+/* 0-based index of the first failing pivot of the last FBT_ENOTPD, else -1. */
+int64_t fbt_last_notpd_pivot(const fbt_ctx *ctx);
+
+/* Per-kernel-class timing with HIP events recorded on the context's stream.
+ * enable != 0 starts recording (and clears the counters); 0 stops it. */
+fbt_status fbt_set_timing(fbt_ctx *ctx, int32_t enable);
+/* Kernel classes: 0 generation, 1 diagonal factor+inverse, 2 panel solve,
+ * 3 trailing Cholesky update, 4 left-solve diagonal apply, 5 left-solve update,
+ * 6 right-solve panel with trace reductions, 7 right-solve update, 8 reductions.
+ * Returns launches, summed milliseconds and summed algorithmic flops of the
+ * class since timing was enabled (timing must have been enabled). */
+fbt_status fbt_get_timing(fbt_ctx *ctx, int32_t kernel_class, int64_t *launches, double *ms,
+                          double *flops);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FISHERBT_H */

@@ -1,0 +1,317 @@
+"""Python binding of libfisherbt (C ABI in include/fisherbt.h).
+
+Exact Matern maximum likelihood by Fisher scoring with backtracking
+(Fisher-BT): log-likelihood (Algorithm 2), score and Fisher information
+(Algorithm 3) and the fit (Algorithm 1), all evaluated by HIP kernels on an
+MI355X.  This module only marshals arguments; every step of an evaluation runs
+in the library.  It raises if the library is missing: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfisherbt.so")
+
+OK, EINVAL, ENOTPD, ENOMEM, EDEVICE, ENONFINITE, EBUDGET, ENODATA = 0, -1, -2, -3, -4, -5, -6, -7
+
+# kernel classes of fbt_get_timing
+KERNEL_CLASSES = ("generation", "diag_factor_inverse", "panel_solve", "cholesky_update",
+                  "left_diag_apply", "left_update", "right_panel_reduce", "right_update",
+                  "reductions")
+
+_lib = None
+_d = ctypes.c_double
+_p = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_dp = ctypes.POINTER(ctypes.c_double)
+
+LOGLIK_FN = ctypes.CFUNCTYPE(ctypes.c_int, _p, _dp, _dp)
+EVAL_FN = ctypes.CFUNCTYPE(ctypes.c_int, _p, _dp, _dp, _dp, _dp)
+ITER_CB = ctypes.CFUNCTYPE(None, _p, _i32, _dp, _d, _dp, _dp)
+
+
+class FitOptions(ctypes.Structure):
+    _fields_ = [("theta0", _dp), ("lo", _d * 3), ("hi", _d * 3), ("armijo_c", _d),
+                ("armijo_relax", _d), ("backtrack_rho", _d), ("grad_tol", _d),
+                ("max_loglik_calls", _i32), ("max_grad_calls", _i32), ("max_iter", _i32),
+                ("nelder_mead", _i32), ("nm_ftol", _d), ("nm_max_evals", _i32),
+                ("cb", ITER_CB), ("cb_user", _p)]
+
+
+class FitResult(ctypes.Structure):
+    _fields_ = [("theta", _d * 3), ("loglik", _d), ("score", _d * 3), ("fisher", _d * 9),
+                ("n_loglik_calls", _i32), ("n_grad_calls", _i32), ("n_iter", _i32),
+                ("used_nelder_mead", _i32), ("converged", _i32), ("n_nm_evals", _i32)]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("device", _i32), ("tile", _i32), ("reserved", _i32), ("hip_stream", _p)]
+
+
+class Evaluator(ctypes.Structure):
+    _fields_ = [("user", _p), ("loglik", LOGLIK_FN), ("eval", EVAL_FN)]
+
+
+# name -> (restype, argtypes): every symbol the header declares
+SIGNATURES = {
+    "fbt_create": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.POINTER(_p)]),
+    "fbt_destroy": (None, [_p]),
+    "fbt_set_data": (ctypes.c_int, [_p, _i64, _p, _p]),
+    "fbt_set_data_device": (ctypes.c_int, [_p, _i64, _p, _p]),
+    "fbt_loglik": (ctypes.c_int, [_p, _p, _p]),
+    "fbt_eval": (ctypes.c_int, [_p, _p, _p, _p, _p]),
+    "fbt_eval_terms": (ctypes.c_int, [_p, _p, _p]),
+    "fbt_covariance": (ctypes.c_int, [_p, _p, _i32, _p, _i64]),
+    "fbt_factor": (ctypes.c_int, [_p, _p, _p, _i64]),
+    "fbt_fit_options_default": (None, [ctypes.POINTER(FitOptions)]),
+    "fbt_fit": (ctypes.c_int, [_p, ctypes.POINTER(FitOptions), ctypes.POINTER(FitResult)]),
+    "fbt_fit_evaluator": (ctypes.c_int, [ctypes.POINTER(Evaluator), ctypes.POINTER(FitOptions),
+                                         ctypes.POINTER(FitResult)]),
+    "fbt_l9_design": (None, [_p, _p, _p]),
+    "fbt_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "fbt_last_error": (ctypes.c_char_p, [_p]),
+    "fbt_last_notpd_pivot": (_i64, [_p]),
+    "fbt_set_timing": (ctypes.c_int, [_p, _i32]),
+    "fbt_get_timing": (ctypes.c_int, [_p, _i32, ctypes.POINTER(_i64), _dp, _dp]),
+}
+
+
+def _share_torch_hip_runtime():
+    """PyTorch ships its own HIP runtime with the same soname as the system one.
+    Two runtimes in one process cannot both open the GPU, so when PyTorch is
+    installed its copy is loaded first and libfisherbt binds to it."""
+    import importlib.util
+
+    spec = importlib.util.find_spec("torch")
+    if spec is None or not spec.origin:
+        return
+    path = os.path.join(os.path.dirname(spec.origin), "lib", "libamdhip64.so")
+    if os.path.exists(path):
+        ctypes.CDLL(path, mode=ctypes.RTLD_GLOBAL)
+
+
+def lib() -> ctypes.CDLL:
+    """Load libfisherbt.so (built by ``paper_2601_11437_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libfisherbt.so is not built; run `python -m paper_2601_11437_amd.build`")
+        _share_torch_hip_runtime()
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class FisherBTError(RuntimeError):
+    def __init__(self, status: int, detail: str = "", pivot: int = -1):
+        self.status = status
+        self.pivot = pivot
+        msg = lib().fbt_status_string(status).decode()
+        super().__init__("%s (%d)%s" % (msg, status, (": " + detail) if detail else ""))
+
+
+def _arr(x, n=None):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    if n is not None and a.size != n:
+        raise ValueError("expected %d values" % n)
+    return a
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_p)
+
+
+def l9_design(lo, hi) -> np.ndarray:
+    """The nine starting candidates of Table 1 (9 x 3)."""
+    lo, hi = _arr(lo, 3), _arr(hi, 3)
+    out = np.empty(27)
+    lib().fbt_l9_design(_ptr(lo), _ptr(hi), _ptr(out))
+    return out.reshape(9, 3)
+
+
+def _options(theta0=None, lo=None, hi=None, callback=None, **kw):
+    o = FitOptions()
+    lib().fbt_fit_options_default(ctypes.byref(o))
+    keep = []
+    if theta0 is not None:
+        t0 = (_d * 3)(*[float(v) for v in theta0])
+        keep.append(t0)
+        o.theta0 = ctypes.cast(t0, _dp)
+    if lo is not None:
+        o.lo = (_d * 3)(*[float(v) for v in lo])
+    if hi is not None:
+        o.hi = (_d * 3)(*[float(v) for v in hi])
+    for k, v in kw.items():
+        if not hasattr(o, k) or k in ("theta0", "cb", "cb_user"):
+            raise TypeError("unknown fit option %r" % k)
+        setattr(o, k, v)
+    if callback is not None:
+        def _cb(user, it, th, ll, sc, fi):
+            callback(int(it), np.array(th[:3]), float(ll), np.array(sc[:3]),
+                     np.array(fi[:9]).reshape(3, 3))
+        cb = ITER_CB(_cb)
+        keep.append(cb)
+        o.cb = cb
+    return o, keep
+
+
+def _result(r: FitResult) -> dict:
+    return {"theta": np.array(r.theta[:]), "loglik": r.loglik, "score": np.array(r.score[:]),
+            "fisher": np.array(r.fisher[:]).reshape(3, 3), "n_loglik_calls": r.n_loglik_calls,
+            "n_grad_calls": r.n_grad_calls, "n_iter": r.n_iter,
+            "used_nelder_mead": bool(r.used_nelder_mead), "converged": bool(r.converged),
+            "n_nm_evals": r.n_nm_evals}
+
+
+def fit_with(loglik, evaluate, **opts) -> dict:
+    """Algorithm 1 (the library's driver) over Python callables:
+    loglik(theta) -> float (raise ArithmeticError for a non-positive-definite
+    covariance) and evaluate(theta) -> (l, grad[3], fisher[3, 3])."""
+    def _ll(user, th, out):
+        try:
+            out[0] = float(loglik(np.array(th[:3])))
+            return OK
+        except ArithmeticError:
+            return ENOTPD
+
+    def _ev(user, th, ll, sc, fi):
+        try:
+            v, g, f = evaluate(np.array(th[:3]))
+        except ArithmeticError:
+            return ENOTPD
+        ll[0] = float(v)
+        for i in range(3):
+            sc[i] = float(g[i])
+        f = np.asarray(f, dtype=np.float64).ravel()
+        for i in range(9):
+            fi[i] = float(f[i])
+        return OK
+
+    ev = Evaluator(None, LOGLIK_FN(_ll), EVAL_FN(_ev))
+    o, keep = _options(**opts)
+    r = FitResult()
+    st = lib().fbt_fit_evaluator(ctypes.byref(ev), ctypes.byref(o), ctypes.byref(r))
+    if st not in (OK, EBUDGET):
+        raise FisherBTError(st)
+    out = _result(r)
+    out["status"] = st
+    return out
+
+
+class Context:
+    """One device context: data on the GPU and the evaluation calls."""
+
+    def __init__(self, device: int = 0, stream=None):
+        cfg = Config(int(device), 0, 0, None)
+        if stream is not None:
+            cfg.hip_stream = int(getattr(stream, "cuda_stream", stream))
+        h = _p()
+        st = lib().fbt_create(ctypes.byref(cfg), ctypes.byref(h))
+        if st != OK:
+            raise FisherBTError(st, "fbt_create(device=%d)" % device)
+        self._h = h
+        self.n = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fbt_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, st):
+        if st != OK:
+            L = lib()
+            raise FisherBTError(st, L.fbt_last_error(self._h).decode(),
+                                int(L.fbt_last_notpd_pivot(self._h)))
+
+    def set_data(self, locs, z):
+        """Locations (n x 2) and observations (n): numpy arrays, or torch tensors
+        (device tensors are passed by pointer)."""
+        if hasattr(locs, "is_cuda") and locs.is_cuda:
+            import torch
+
+            lt = locs.detach().to(torch.float64).contiguous()
+            zt = z.detach().to(device=lt.device, dtype=torch.float64).contiguous()
+            torch.cuda.current_stream(lt.device).synchronize()   # producer stream -> library stream
+            n = int(zt.numel())
+            if lt.numel() != 2 * n:
+                raise ValueError("locs must be n x 2")
+            self._check(lib().fbt_set_data_device(self._h, n, _p(lt.data_ptr()), _p(zt.data_ptr())))
+        else:
+            locs = _arr(np.asarray(locs.cpu() if hasattr(locs, "cpu") else locs))
+            z = _arr(np.asarray(z.cpu() if hasattr(z, "cpu") else z))
+            n = z.size
+            if locs.size != 2 * n:
+                raise ValueError("locs must be n x 2")
+            self._check(lib().fbt_set_data(self._h, n, _ptr(locs), _ptr(z)))
+        self.n = n
+
+    def loglik(self, theta) -> float:
+        th = _arr(theta, 3)
+        out = np.zeros(1)
+        self._check(lib().fbt_loglik(self._h, _ptr(th), _ptr(out)))
+        return float(out[0])
+
+    def eval(self, theta):
+        """(loglik, score[3], fisher[3, 3]) by Algorithm 3."""
+        th = _arr(theta, 3)
+        ll, sc, fi = np.zeros(1), np.zeros(3), np.zeros(9)
+        self._check(lib().fbt_eval(self._h, _ptr(th), _ptr(ll), _ptr(sc), _ptr(fi)))
+        return float(ll[0]), sc, fi.reshape(3, 3)
+
+    def eval_terms(self, theta) -> np.ndarray:
+        th = _arr(theta, 3)
+        t = np.zeros(9)
+        self._check(lib().fbt_eval_terms(self._h, _ptr(th), _ptr(t)))
+        return t
+
+    def covariance(self, theta, which: int = 0) -> np.ndarray:
+        th = _arr(theta, 3)
+        out = np.empty((self.n, self.n), order="F")
+        self._check(lib().fbt_covariance(self._h, _ptr(th), int(which), _ptr(out), self.n))
+        return out
+
+    def factor(self, theta) -> np.ndarray:
+        th = _arr(theta, 3)
+        out = np.empty((self.n, self.n), order="F")
+        self._check(lib().fbt_factor(self._h, _ptr(th), _ptr(out), self.n))
+        return out
+
+    def fit(self, **opts) -> dict:
+        o, keep = _options(**opts)
+        r = FitResult()
+        st = lib().fbt_fit(self._h, ctypes.byref(o), ctypes.byref(r))
+        if st not in (OK, EBUDGET):
+            self._check(st)
+        out = _result(r)
+        out["status"] = st
+        return out
+
+    def set_timing(self, enable: bool):
+        self._check(lib().fbt_set_timing(self._h, 1 if enable else 0))
+
+    def timing(self) -> dict:
+        out = {}
+        for k, name in enumerate(KERNEL_CLASSES):
+            n, ms, fl = _i64(), _d(), _d()
+            self._check(lib().fbt_get_timing(self._h, k, ctypes.byref(n), ctypes.byref(ms),
+                                             ctypes.byref(fl)))
+            out[name] = {"launches": n.value, "ms": ms.value, "flops": fl.value}
+        return out

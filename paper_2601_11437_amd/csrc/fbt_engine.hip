@@ -1,0 +1,642 @@
+// Host engine and C ABI: context and device buffers, per-theta setup of the
+// Bessel quadrature tables, and the launch sequences of Algorithm 2
+// (log-likelihood) and Algorithm 3 (log-likelihood, score, Fisher).
+#include "fisherbt.h"
+#include "fbt_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace fbt;
+
+namespace {
+
+constexpr int NCLASS = 9;
+enum KClass { KC_GEN, KC_DIAG, KC_PANEL, KC_SYRK, KC_LAPPLY, KC_LUPD, KC_RPANEL, KC_RUPD, KC_RED };
+
+struct Timed {
+    int cls;
+    double flops;
+    hipEvent_t a, b;
+};
+
+} // namespace
+
+struct fbt_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    int64_t notpd = -1;
+
+    int64_t n = 0, npad = 0, ld = 0, ncols = 0;
+    int T = 0;
+    double *x = nullptr, *y = nullptr, *z = nullptr;
+    double *A = nullptr;  // Sigma' -> bordered factor L' (lower)
+    double *S2 = nullptr; // [Sigma_alpha' | Sigma_nu'] -> X -> W (npad x 2 npad)
+    double *Linv = nullptr, *logdet = nullptr, *partials = nullptr, *out = nullptr;
+    int *info = nullptr;
+    Node *tab = nullptr;
+    Node *h_tab = nullptr; // pinned staging
+    double *h_out = nullptr;
+    int *h_info = nullptr;
+    size_t alloc_npad = 0;
+
+    bool factor_valid = false;
+    double factor_theta[3] = {0, 0, 0};
+    double factor_out[2] = {0, 0};
+
+    bool timing = false;
+    std::vector<Timed> pending;
+    std::vector<hipEvent_t> pool;
+    size_t pool_used = 0;
+    int64_t cls_n[NCLASS] = {0};
+    double cls_ms[NCLASS] = {0}, cls_flops[NCLASS] = {0};
+};
+
+namespace {
+
+fbt_status fail(fbt_ctx *c, fbt_status s, const std::string &m)
+{
+    if (c)
+        c->err = m;
+    return s;
+}
+
+#define HIPCHK(ctx, expr)                                                                          \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail(ctx, FBT_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_));       \
+    } while (0)
+
+bool theta_ok(const double *th)
+{
+    return th && std::isfinite(th[0]) && std::isfinite(th[1]) && std::isfinite(th[2]) &&
+           th[0] > 0 && th[1] > 0 && th[2] > 0;
+}
+
+// psi(v), v > 0: recurrence psi(v) = psi(v + 1) - 1/v up to v >= 12, then the
+// asymptotic expansion log v - 1/(2v) - sum_{k=1..6} B_2k / (2k v^2k).
+double digamma(double v)
+{
+    double acc = 0.0;
+    for (; v < 12.0; v += 1.0)
+        acc -= 1.0 / v;
+    const double f = 1.0 / (v * v);
+    const double tail =
+        f * (0.083333333333333333 -
+             f * (0.0083333333333333333 -
+                  f * (0.0039682539682539683 -
+                       f * (0.0041666666666666667 - f * (0.0075757575757575758 - f * 0.021092796092796093)))));
+    return acc + std::log(v) - 0.5 / v - tail;
+}
+
+// Quadrature tables and prefactors for theta (see the generation kernel).
+GenParams setup_theta(fbt_ctx *c, const double *th)
+{
+    GenParams gp;
+    std::memset(&gp, 0, sizeof(gp));
+    gp.sigma2 = th[0];
+    gp.alpha = th[1];
+    gp.nu = th[2];
+    gp.abs_nu = std::fabs(th[2]);
+    gp.cnu = std::exp((1.0 - gp.nu) * std::log(2.0) - std::lgamma(gp.nu));
+    gp.log2_psi = std::log(2.0) + digamma(gp.nu);
+    gp.n = c->n;
+    gp.npad = c->npad;
+    gp.ld = c->ld;
+    int off = 0;
+    const double tcap = 700.0 / (gp.abs_nu + 1.0); // keeps cosh(nu t) finite
+    for (int L = 0; L < NLEV; ++L) {
+        const double h = 0.2 / double(1 << L);
+        const int maxlen = (L == 0) ? TAB_L0 : TAB_LN;
+        const int len = std::min(maxlen, int(tcap / h) + 1);
+        gp.h[L] = h;
+        gp.xtop[L] = 9.0 * double(1 << (2 * L));
+        gp.off[L] = off;
+        gp.len[L] = len;
+        for (int j = 0; j < len; ++j) {
+            const double t = j * h, w = (j == 0) ? 0.5 * h : h;
+            const double sh = std::sinh(0.5 * t);
+            Node &nd = c->h_tab[off + j];
+            nd.cm1 = 2.0 * sh * sh;
+            nd.wk = w * std::cosh(gp.nu * t);
+            nd.wk1 = w * std::cosh((gp.nu - 1.0) * t);
+            nd.wd = w * t * std::sinh(gp.nu * t);
+        }
+        off += maxlen;
+    }
+    return gp;
+}
+
+// ---- timing helpers ----
+void tbegin(fbt_ctx *c, hipEvent_t *a, hipEvent_t *b)
+{
+    if (!c->timing)
+        return;
+    while (c->pool.size() < c->pool_used + 2) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess)
+            return;
+        c->pool.push_back(e);
+    }
+    *a = c->pool[c->pool_used++];
+    *b = c->pool[c->pool_used++];
+    (void)hipEventRecord(*a, c->stream);
+}
+void tend(fbt_ctx *c, int cls, double flops, hipEvent_t a, hipEvent_t b)
+{
+    if (!c->timing)
+        return;
+    (void)hipEventRecord(b, c->stream);
+    c->pending.push_back({cls, flops, a, b});
+}
+void tcollect(fbt_ctx *c)
+{
+    if (!c->timing)
+        return;
+    for (const Timed &t : c->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+            c->cls_n[t.cls] += 1;
+            c->cls_ms[t.cls] += ms;
+            c->cls_flops[t.cls] += t.flops;
+        }
+    }
+    c->pending.clear();
+    c->pool_used = 0;
+}
+
+#define TIMED(ctx, cls, flops, call)                                                               \
+    do {                                                                                           \
+        hipEvent_t ta_ = nullptr, tb_ = nullptr;                                                   \
+        tbegin(ctx, &ta_, &tb_);                                                                   \
+        call;                                                                                      \
+        if (ta_)                                                                                   \
+            tend(ctx, cls, flops, ta_, tb_);                                                       \
+    } while (0)
+
+void free_buffers(fbt_ctx *c)
+{
+    (void)hipFree(c->x);
+    (void)hipFree(c->y);
+    (void)hipFree(c->z);
+    (void)hipFree(c->A);
+    (void)hipFree(c->S2);
+    (void)hipFree(c->Linv);
+    (void)hipFree(c->logdet);
+    (void)hipFree(c->partials);
+    (void)hipFree(c->out);
+    (void)hipFree(c->info);
+    (void)hipFree(c->tab);
+    c->x = c->y = c->z = c->A = c->S2 = c->Linv = c->logdet = c->partials = c->out = nullptr;
+    c->info = nullptr;
+    c->tab = nullptr;
+    c->alloc_npad = 0;
+}
+
+fbt_status alloc_for(fbt_ctx *c, int64_t n)
+{
+    const int64_t npad = NB * ((n + 1 + NB - 1) / NB);
+    c->factor_valid = false;
+    if ((size_t)npad != c->alloc_npad) {
+        free_buffers(c);
+        const size_t ld = (size_t)npad;
+        const int T = (int)(npad / NB);
+        const size_t part = (size_t)T * (size_t)(npad / 64) * 8;
+        struct {
+            void **p;
+            size_t bytes;
+        } req[] = {
+            {(void **)&c->x, ld * 8},           {(void **)&c->y, ld * 8},
+            {(void **)&c->z, ld * 8},           {(void **)&c->A, ld * ld * 8},
+            {(void **)&c->S2, ld * ld * 16},  {(void **)&c->Linv, (size_t)T * NB * NB * 8},
+            {(void **)&c->logdet, (size_t)T * 8}, {(void **)&c->partials, part * 8},
+            {(void **)&c->out, 16 * 8},         {(void **)&c->info, 64},
+            {(void **)&c->tab, TAB_MAX * sizeof(Node)},
+        };
+        for (auto &r : req) {
+            if (hipMalloc(r.p, r.bytes) != hipSuccess) {
+                free_buffers(c);
+                return fail(c, FBT_ENOMEM, "device allocation failed (npad = " +
+                                               std::to_string(npad) + ")");
+            }
+        }
+        c->alloc_npad = npad;
+    }
+    c->n = n;
+    c->npad = npad;
+    c->ld = npad;
+    c->T = (int)(npad / NB);
+    c->ncols = 128 * ((n + 127) / 128);
+    return FBT_OK;
+}
+
+fbt_status upload_theta(fbt_ctx *c, const double *th, GenParams *gp)
+{
+    *gp = setup_theta(c, th);
+    HIPCHK(c, hipMemcpyAsync(c->tab, c->h_tab, TAB_MAX * sizeof(Node), hipMemcpyHostToDevice,
+                             c->stream));
+    return FBT_OK;
+}
+
+// Generate Sigma' (and/or the derivative matrices) and factor the bordered
+// Sigma'.  On success c->factor_out = {log det, y^T y}.
+fbt_status factorize(fbt_ctx *c, const double *th, int mode)
+{
+    GenParams gp;
+    fbt_status st = upload_theta(c, th, &gp);
+    if (st != FBT_OK)
+        return st;
+    c->factor_valid = false;
+    const int64_t npad = c->npad, ld = c->ld, n = c->n;
+    const int T = c->T;
+    launch_init_info(c->stream, c->info);
+    TIMED(c, KC_GEN, 0.0, launch_gen(c->stream, gp, c->x, c->y, c->z, c->tab, c->A, c->S2,
+                                       c->S2 + npad * ld, mode));
+    for (int k = 0; k < T; ++k) {
+        double *Lk = c->Linv + (size_t)k * NB * NB;
+        TIMED(c, KC_DIAG, 2.0 * NB * (double)NB * NB / 3.0,
+              launch_potrf_diag(c->stream, c->A, ld, k, n, Lk, c->logdet, c->info));
+        const int64_t r0 = (int64_t)(k + 1) * NB, rows = npad - r0;
+        if (rows <= 0)
+            continue;
+        const double m = (double)std::max<int64_t>(0, n - r0);
+        double *panel = c->A + r0 + (int64_t)k * NB * ld;
+        TIMED(c, KC_PANEL, m * NB * NB, launch_panel(c->stream, panel, ld, rows, Lk));
+        TIMED(c, KC_SYRK, m * m * NB,
+              launch_update_lower(c->stream, 1, c->A + r0 + r0 * ld, nullptr, ld, panel, nullptr,
+                                  ld, panel, ld, T - k - 1));
+    }
+    TIMED(c, KC_RED, 0.0, launch_reduce_loglik(c->stream, c->A, ld, n, T, c->logdet, c->out));
+    HIPCHK(c, hipMemcpyAsync(c->h_out, c->out, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->h_info, c->info, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    tcollect(c);
+    if (c->h_info[0] != 0x7fffffff) {
+        c->notpd = c->h_info[0];
+        return fail(c, FBT_ENOTPD, "Sigma(theta) is not positive definite: pivot " +
+                                       std::to_string(c->h_info[0]) + " is not positive");
+    }
+    c->factor_out[0] = c->h_out[0];
+    c->factor_out[1] = c->h_out[1];
+    if (!std::isfinite(c->factor_out[0]) || !std::isfinite(c->factor_out[1]))
+        return fail(c, FBT_ENONFINITE, "log-determinant or quadratic form is not finite");
+    c->factor_valid = true;
+    std::memcpy(c->factor_theta, th, sizeof(c->factor_theta));
+    return FBT_OK;
+}
+
+// The factor of the last fbt_loglik / fbt_factor call is reused by the next
+// derivative evaluation at the bitwise-same theta (the accepted trial of the
+// line search), once: every other evaluation factors Sigma afresh.
+bool same_theta(const fbt_ctx *c, const double *th)
+{
+    return c->factor_valid && std::memcmp(c->factor_theta, th, sizeof(c->factor_theta)) == 0;
+}
+
+// W phase of Algorithm 3 on a valid factor: out[0..8] (see fbt_eval_terms).
+fbt_status derivative_terms(fbt_ctx *c, const double *th, double terms[9])
+{
+    fbt_status st;
+    if (same_theta(c, th)) {
+        GenParams gp;
+        if ((st = upload_theta(c, th, &gp)) != FBT_OK)
+            return st;
+        TIMED(c, KC_GEN, 0.0, launch_gen(c->stream, gp, c->x, c->y, c->z, c->tab, c->A, c->S2,
+                                           c->S2 + c->npad * c->ld, GEN_DERIV));
+    } else if ((st = factorize(c, th, GEN_ALL)) != FBT_OK) {
+        return st;
+    }
+    c->factor_valid = false; // reuse is for one derivative evaluation only
+    const int64_t npad = c->npad, ld = c->ld, n = c->n, ncols = c->ncols;
+    const int T = c->T;
+    double *Sa = c->S2, *Sn = c->S2 + npad * ld;
+    const double dn = (double)n;
+    // left solve X = L'^{-1} [Sigma_alpha' | Sigma_nu'] on columns [0, ncols) of each half
+    for (int k = 0; k < T; ++k) {
+        const double *Lk = c->Linv + (size_t)k * NB * NB;
+        const int64_t krow = (int64_t)k * NB, r0 = krow + NB;
+        TIMED(c, KC_LAPPLY, 2.0 * dn * NB * NB,
+              launch_diag_apply(c->stream, c->S2, ld, krow, Lk, ncols, npad));
+        const double m = (double)std::max<int64_t>(0, n - r0);
+        TIMED(c, KC_LUPD, 2.0 * m * NB * 2.0 * dn,
+              launch_update_nn(c->stream, c->S2, ld, c->A, ld, r0, krow, npad - r0, ncols,
+                               npad));
+    }
+    // right solve W = X L'^{-T} (block-lower) with the fused reductions
+    int64_t groups = 0;
+    for (int k = 0; k < T; ++k) {
+        const double *Lk = c->Linv + (size_t)k * NB * NB;
+        const int64_t kc = (int64_t)k * NB, r1 = kc + NB, rows = npad - kc;
+        const double mp = (double)std::max<int64_t>(0, n - kc);
+        TIMED(c, KC_RPANEL, 2.0 * mp * NB * NB,
+              launch_panel_reduce(c->stream, Sa, Sn, ld, kc, kc, rows, Lk, n,
+                                  c->partials + 8 * groups));
+        groups += rows / 64;
+        const double m = (double)std::max<int64_t>(0, n - r1);
+        TIMED(c, KC_RUPD, 2.0 * m * m * NB,
+              launch_update_lower(c->stream, 2, Sa + r1 + r1 * ld, Sn + r1 + r1 * ld, ld,
+                                  Sa + r1 + kc * ld, Sn + r1 + kc * ld, ld, c->A + r1 + kc * ld,
+                                  ld, T - k - 1));
+    }
+    TIMED(c, KC_RED, 0.0, launch_reduce_terms(c->stream, c->partials, groups, c->out));
+    HIPCHK(c, hipMemcpyAsync(c->h_out, c->out, 9 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    tcollect(c);
+    // the derivative matrices were overwritten; the factor itself is intact
+    terms[0] = c->factor_out[0];
+    terms[1] = c->factor_out[1];
+    for (int i = 2; i < 9; ++i)
+        terms[i] = c->h_out[i];
+    for (int i = 0; i < 9; ++i)
+        if (!std::isfinite(terms[i]))
+            return fail(c, FBT_ENONFINITE, "a trace term is not finite");
+    return FBT_OK;
+}
+
+double loglik_from(int64_t n, double logdet, double quad)
+{
+    return -0.5 * (double)n * std::log(2.0 * M_PI) - 0.5 * logdet - 0.5 * quad;
+}
+
+fbt_status check_call(fbt_ctx *c, const double *th)
+{
+    if (!c)
+        return FBT_EINVAL;
+    c->err.clear();
+    if (!theta_ok(th))
+        return fail(c, FBT_EINVAL, "theta must be three finite positive numbers");
+    if (c->n <= 0)
+        return fail(c, FBT_ENODATA, "no data set");
+    if (hipSetDevice(c->device) != hipSuccess)
+        return fail(c, FBT_EDEVICE, "hipSetDevice failed");
+    return FBT_OK;
+}
+
+fbt_status set_data_common(fbt_ctx *c, int64_t n, const double *locs, const double *z, bool device)
+{
+    if (!c)
+        return FBT_EINVAL;
+    c->err.clear();
+    if (n < 1 || !locs || !z)
+        return fail(c, FBT_EINVAL, "n must be >= 1 and locs, z non-NULL");
+    if (n > (int64_t)1 << 20)
+        return fail(c, FBT_EINVAL, "n too large");
+    if (hipSetDevice(c->device) != hipSuccess)
+        return fail(c, FBT_EDEVICE, "hipSetDevice failed");
+    std::vector<double> hl((size_t)n * 2), hz((size_t)n);
+    if (device) {
+        HIPCHK(c, hipMemcpyAsync(hl.data(), locs, n * 16, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(hz.data(), z, n * 8, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    } else {
+        std::memcpy(hl.data(), locs, n * 16);
+        std::memcpy(hz.data(), z, n * 8);
+    }
+    for (int64_t i = 0; i < 2 * n; ++i)
+        if (!std::isfinite(hl[i]))
+            return fail(c, FBT_EINVAL, "non-finite location");
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(hz[i]))
+            return fail(c, FBT_EINVAL, "non-finite observation");
+    fbt_status st = alloc_for(c, n);
+    if (st != FBT_OK)
+        return st;
+    std::vector<double> xs(c->npad, 0.0), ys(c->npad, 0.0), zs(c->npad, 0.0);
+    for (int64_t i = 0; i < n; ++i) {
+        xs[i] = hl[2 * i];
+        ys[i] = hl[2 * i + 1];
+        zs[i] = hz[i];
+    }
+    HIPCHK(c, hipMemcpyAsync(c->x, xs.data(), c->npad * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->y, ys.data(), c->npad * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->z, zs.data(), c->npad * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return FBT_OK;
+}
+
+} // namespace
+
+// =========================================================================
+// C ABI
+// =========================================================================
+extern "C" {
+
+const char *fbt_status_string(fbt_status s)
+{
+    switch (s) {
+    case FBT_OK: return "ok";
+    case FBT_EINVAL: return "invalid argument";
+    case FBT_ENOTPD: return "covariance not positive definite";
+    case FBT_ENOMEM: return "out of memory";
+    case FBT_EDEVICE: return "device error";
+    case FBT_ENONFINITE: return "non-finite result";
+    case FBT_EBUDGET: return "call budget exhausted";
+    case FBT_ENODATA: return "no data";
+    }
+    return "unknown status";
+}
+
+const char *fbt_last_error(const fbt_ctx *ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+
+int64_t fbt_last_notpd_pivot(const fbt_ctx *ctx) { return ctx ? ctx->notpd : -1; }
+
+fbt_status fbt_create(const fbt_config *cfg, fbt_ctx **out)
+{
+    if (!cfg || !out)
+        return FBT_EINVAL;
+    *out = nullptr;
+    if (!(cfg->tile == 0 || cfg->tile == NB) || cfg->reserved != 0)
+        return FBT_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev)
+        return FBT_EDEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, cfg->device) != hipSuccess ||
+        std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return FBT_EDEVICE;
+    if (hipSetDevice(cfg->device) != hipSuccess)
+        return FBT_EDEVICE;
+    fbt_ctx *c = new fbt_ctx();
+    c->device = cfg->device;
+    if (cfg->hip_stream) {
+        c->stream = (hipStream_t)cfg->hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return FBT_EDEVICE;
+        }
+        c->own_stream = true;
+    }
+    if (hipHostMalloc((void **)&c->h_tab, TAB_MAX * sizeof(Node), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&c->h_out, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&c->h_info, 16 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+        fbt_destroy(c);
+        return FBT_ENOMEM;
+    }
+    *out = c;
+    return FBT_OK;
+}
+
+void fbt_destroy(fbt_ctx *c)
+{
+    if (!c)
+        return;
+    (void)hipSetDevice(c->device);
+    if (c->stream)
+        (void)hipStreamSynchronize(c->stream);
+    free_buffers(c);
+    for (hipEvent_t e : c->pool)
+        (void)hipEventDestroy(e);
+    if (c->h_tab)
+        (void)hipHostFree(c->h_tab);
+    if (c->h_out)
+        (void)hipHostFree(c->h_out);
+    if (c->h_info)
+        (void)hipHostFree(c->h_info);
+    if (c->own_stream && c->stream)
+        (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+fbt_status fbt_set_data(fbt_ctx *ctx, int64_t n, const double *locs_xy, const double *z)
+{
+    return set_data_common(ctx, n, locs_xy, z, false);
+}
+
+fbt_status fbt_set_data_device(fbt_ctx *ctx, int64_t n, const double *d_locs_xy, const double *d_z)
+{
+    return set_data_common(ctx, n, d_locs_xy, d_z, true);
+}
+
+fbt_status fbt_loglik(fbt_ctx *ctx, const double theta[3], double *loglik)
+{
+    fbt_status st = check_call(ctx, theta);
+    if (st != FBT_OK)
+        return st;
+    if (!loglik)
+        return fail(ctx, FBT_EINVAL, "loglik is NULL");
+    if ((st = factorize(ctx, theta, GEN_SIGMA)) != FBT_OK)
+        return st;
+    *loglik = loglik_from(ctx->n, ctx->factor_out[0], ctx->factor_out[1]);
+    return FBT_OK;
+}
+
+fbt_status fbt_eval_terms(fbt_ctx *ctx, const double theta[3], double terms[9])
+{
+    fbt_status st = check_call(ctx, theta);
+    if (st != FBT_OK)
+        return st;
+    if (!terms)
+        return fail(ctx, FBT_EINVAL, "terms is NULL");
+    double t[9];
+    if ((st = derivative_terms(ctx, theta, t)) != FBT_OK)
+        return st;
+    std::memcpy(terms, t, sizeof(t));
+    return FBT_OK;
+}
+
+fbt_status fbt_eval(fbt_ctx *ctx, const double theta[3], double *loglik, double score[3],
+                    double fisher[9])
+{
+    fbt_status st = check_call(ctx, theta);
+    if (st != FBT_OK)
+        return st;
+    if (!loglik || !score || !fisher)
+        return fail(ctx, FBT_EINVAL, "NULL output");
+    double t[9];
+    if ((st = derivative_terms(ctx, theta, t)) != FBT_OK)
+        return st;
+    const double s2 = theta[0], n = (double)ctx->n;
+    *loglik = loglik_from(ctx->n, t[0], t[1]);
+    // Algorithm 3, steps 2-4
+    score[0] = (t[1] - n) / (2.0 * s2);
+    score[1] = -0.5 * t[2] + 0.5 * t[4];
+    score[2] = -0.5 * t[3] + 0.5 * t[5];
+    const double I00 = n / (2.0 * s2 * s2), I01 = t[2] / (2.0 * s2), I02 = t[3] / (2.0 * s2);
+    const double I11 = 0.5 * t[6], I12 = 0.5 * t[7], I22 = 0.5 * t[8];
+    const double F[9] = {I00, I01, I02, I01, I11, I12, I02, I12, I22};
+    std::memcpy(fisher, F, sizeof(F));
+    return FBT_OK;
+}
+
+fbt_status fbt_covariance(fbt_ctx *ctx, const double theta[3], int32_t which, double *out,
+                          int64_t ld)
+{
+    fbt_status st = check_call(ctx, theta);
+    if (st != FBT_OK)
+        return st;
+    if (!out || ld < ctx->n || which < 0 || which > 2)
+        return fail(ctx, FBT_EINVAL, "bad output arguments");
+    GenParams gp;
+    if ((st = upload_theta(ctx, theta, &gp)) != FBT_OK)
+        return st;
+    ctx->factor_valid = false;
+    const int64_t n = ctx->n, npad = ctx->npad, dld = ctx->ld;
+    launch_gen(ctx->stream, gp, ctx->x, ctx->y, ctx->z, ctx->tab, ctx->A, ctx->S2,
+               ctx->S2 + npad * dld, which == 0 ? GEN_SIGMA : GEN_DERIV);
+    const double *src = which == 0 ? ctx->A : (which == 1 ? ctx->S2 : ctx->S2 + npad * dld);
+    HIPCHK(ctx, hipMemcpy2DAsync(out, ld * 8, src, dld * 8, n * 8, n, hipMemcpyDeviceToHost,
+                                 ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (which == 0) // Sigma' is generated in its lower triangle only
+        for (int64_t j = 0; j < n; ++j)
+            for (int64_t i = 0; i < j; ++i)
+                out[i + j * ld] = out[j + i * ld];
+    return FBT_OK;
+}
+
+fbt_status fbt_factor(fbt_ctx *ctx, const double theta[3], double *out, int64_t ld)
+{
+    fbt_status st = check_call(ctx, theta);
+    if (st != FBT_OK)
+        return st;
+    if (!out || ld < ctx->n)
+        return fail(ctx, FBT_EINVAL, "bad output arguments");
+    if ((st = factorize(ctx, theta, GEN_SIGMA)) != FBT_OK)
+        return st;
+    const int64_t n = ctx->n;
+    HIPCHK(ctx, hipMemcpy2DAsync(out, ld * 8, ctx->A, ctx->ld * 8, n * 8, n, hipMemcpyDeviceToHost,
+                                 ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < j; ++i)
+            out[i + j * ld] = 0.0;
+    return FBT_OK;
+}
+
+fbt_status fbt_set_timing(fbt_ctx *ctx, int32_t enable)
+{
+    if (!ctx)
+        return FBT_EINVAL;
+    ctx->timing = enable != 0;
+    ctx->pending.clear();
+    ctx->pool_used = 0;
+    for (int i = 0; i < NCLASS; ++i) {
+        ctx->cls_n[i] = 0;
+        ctx->cls_ms[i] = 0.0;
+        ctx->cls_flops[i] = 0.0;
+    }
+    return FBT_OK;
+}
+
+fbt_status fbt_get_timing(fbt_ctx *ctx, int32_t kernel_class, int64_t *launches, double *ms,
+                          double *flops)
+{
+    if (!ctx || kernel_class < 0 || kernel_class >= NCLASS || !launches || !ms || !flops)
+        return FBT_EINVAL;
+    *launches = ctx->cls_n[kernel_class];
+    *ms = ctx->cls_ms[kernel_class];
+    *flops = ctx->cls_flops[kernel_class];
+    return FBT_OK;
+}
+
+} // extern "C"

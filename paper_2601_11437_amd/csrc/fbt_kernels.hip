@@ -1,0 +1,749 @@
+// HIP kernels for gfx950 (MI355X): Matern covariance generation, tiled FP64
+// Cholesky, the two triangular solves that form W_i = L^{-1} Sigma_i L^{-T},
+// and the trace reductions of the score and Fisher information.
+//
+// Storage: every matrix is column-major with leading dimension ld and padded
+// order npad = NB * ceil((n + 1) / NB).  Row/column n of Sigma' carries the
+// observations (Sigma'[n][j] = Z_j for j < n), so the factorisation of the
+// bordered matrix returns y = L^{-1} Z in row n of the factor; all rows and
+// columns beyond n are identity (Sigma') or zero (Sigma_alpha', Sigma_nu').
+// The padded problem has exactly the same log-determinant, quadratic form,
+// traces and Frobenius products as the n x n one, and needs no ragged tiles.
+#include "fbt_internal.h"
+
+#include <math.h>
+
+namespace fbt {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c)
+{
+    // D(16x16) = A(16x4) B(4x16) + C.  Lane l supplies A[l%16][l/16] and
+    // B[l/16][l%16]; it holds D[l/16 + 4r][l%16] in element r.
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Covariance generation (Section 2.1; derivatives Section 2.2)
+//
+// With x = h / alpha and the exponentially scaled integrals
+//   SK  = e^x K_nu(x)      = int_0^inf e^{-x (cosh t - 1)} cosh(nu t) dt
+//   SK1 = e^x K_{nu-1}(x)  = int_0^inf e^{-x (cosh t - 1)} cosh((nu-1) t) dt
+//   SD  = e^x dK_nu/dnu(x) = int_0^inf e^{-x (cosh t - 1)} t sinh(nu t) dt
+// (the integral form of K and its order derivative), each entry is
+//   C       = sigma2 c_nu E SK,            E = x^nu e^{-x}, c_nu = 2^(1-nu)/Gamma(nu)
+//   C_alpha = sigma2/alpha c_nu x E SK1
+//   C_nu    = sigma2 c_nu E ((log x - log 2 - psi(nu)) SK + SD)
+// The integrals use the trapezoid rule with step h_L = 0.2 / 2^L, where the
+// level L is the smallest with x <= 9 * 4^L (so h_L <= 0.6 / sqrt(x)), and
+// stop at the t where x (cosh t - 1) - (|nu| + 1) t reaches 45: beyond it the
+// integrands are below e^-45 of their value at t = 0.  At x = 0 the entry is
+// (sigma2, 0, 0).
+// ---------------------------------------------------------------------------
+constexpr int GT = 64; // generation tile (rows x cols)
+
+__device__ __forceinline__ double acosh_ge1(double y) { return log(y + sqrt((y - 1.0) * (y + 1.0))); }
+
+__device__ __forceinline__ void matern3(const GenParams &gp, const Node *tab, double x, int mode,
+                                        double &c, double &ca, double &cn)
+{
+    if (x == 0.0) {
+        c = gp.sigma2;
+        ca = 0.0;
+        cn = 0.0;
+        return;
+    }
+    if (!(x <= gp.xtop[NLEV - 1])) { // beyond every level: e^{-x} underflows
+        c = 0.0;
+        ca = 0.0;
+        cn = 0.0;
+        return;
+    }
+    int L = 0;
+#pragma unroll
+    for (int l = 0; l < NLEV - 1; ++l)
+        L += (x > gp.xtop[l]);
+    const double h = gp.h[L];
+    // truncation point
+    const double g = gp.abs_nu + 1.0;
+    double t = acosh_ge1(1.0 + 45.0 / x);
+#pragma unroll
+    for (int it = 0; it < 3; ++it)
+        t = acosh_ge1(1.0 + (45.0 + g * t) / x);
+    t = fmin(t, 1.0e4); // x below ~1e-300: every node of the level
+    int J = (int)(t / h) + 2;
+    J = J < gp.len[L] ? J : gp.len[L];
+    const Node *nd = tab + gp.off[L];
+    double sk = 0.0, sk1 = 0.0, sd = 0.0;
+    if (mode == GEN_SIGMA) {
+        for (int j = 0; j < J; ++j) {
+            const double e = exp(-x * nd[j].cm1);
+            sk = fma(e, nd[j].wk, sk);
+        }
+    } else {
+        for (int j = 0; j < J; ++j) {
+            const double e = exp(-x * nd[j].cm1);
+            sk = fma(e, nd[j].wk, sk);
+            sk1 = fma(e, nd[j].wk1, sk1);
+            sd = fma(e, nd[j].wd, sd);
+        }
+    }
+    const double lx = log(x);
+    const double E = gp.cnu * exp(gp.nu * lx - x); // c_nu x^nu e^{-x}
+    c = gp.sigma2 * E * sk;
+    ca = gp.sigma2 / gp.alpha * x * E * sk1;
+    cn = gp.sigma2 * E * ((lx - gp.log2_psi) * sk + sd);
+}
+
+__global__ __launch_bounds__(256) void k_gen(GenParams gp, const double *__restrict__ xs,
+                                             const double *__restrict__ ys,
+                                             const double *__restrict__ z,
+                                             const Node *__restrict__ gtab, double *__restrict__ S,
+                                             double *__restrict__ Sa, double *__restrict__ Sn,
+                                             int mode)
+{
+    __shared__ Node tab[TAB_MAX];
+    const int t = threadIdx.x;
+    const int ntab = gp.off[NLEV - 1] + gp.len[NLEV - 1];
+    for (int i = t; i < ntab; i += 256)
+        tab[i] = gtab[i];
+    // tile pair (ti >= tj) from the linear block index
+    const int64_t p = blockIdx.x;
+    int64_t ti = (int64_t)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+    while ((ti + 1) * (ti + 2) / 2 <= p)
+        ++ti;
+    while (ti * (ti + 1) / 2 > p)
+        --ti;
+    const int64_t tj = p - ti * (ti + 1) / 2;
+    const bool diag = (ti == tj);
+    const int al = t & 63;
+    const int64_t a = ti * GT + al;
+    const int64_t n = gp.n, ld = gp.ld;
+    const double xa = a < n ? xs[a] : 0.0, ya = a < n ? ys[a] : 0.0;
+    const double inv_alpha = 1.0 / gp.alpha;
+    __syncthreads();
+
+#pragma unroll 1
+    for (int e = 0; e < 16; ++e) {
+        const int bl = (t >> 6) * 16 + e;
+        const int64_t b = tj * GT + bl;
+        if (diag && al < bl)
+            continue;
+        double c = 0.0, ca = 0.0, cn = 0.0;
+        if (a < n) {
+            const double dx = xa - xs[b], dy = ya - ys[b];
+            matern3(gp, tab, sqrt(dx * dx + dy * dy) * inv_alpha, mode, c, ca, cn);
+        } else if (a == n) {
+            c = (b < n) ? z[b] : 1.0;
+        } else {
+            c = (a == b) ? 1.0 : 0.0;
+        }
+        if (mode & GEN_SIGMA)
+            S[a + b * ld] = c;
+        if (mode & GEN_DERIV) {
+            // full symmetric storage: the entry and its mirror.  The mirrored
+            // stores are strided, but the kernel is bound by the quadrature
+            // arithmetic (hundreds of instructions per entry), not by stores.
+            Sa[a + b * ld] = ca;
+            Sn[a + b * ld] = cn;
+            if (a != b) {
+                Sa[b + a * ld] = ca;
+                Sn[b + a * ld] = cn;
+            }
+        }
+    }
+}
+
+void launch_gen(hipStream_t s, const GenParams &gp, const double *xs, const double *ys,
+                const double *z, const Node *tab, double *S, double *Sa, double *Sn, int mode)
+{
+    const int64_t nt = gp.npad / GT;
+    const int64_t pairs = nt * (nt + 1) / 2;
+    hipLaunchKernelGGL(k_gen, dim3((unsigned)pairs), dim3(256), 0, s, gp, xs, ys, z, tab, S, Sa,
+                       Sn, mode);
+}
+
+// ---------------------------------------------------------------------------
+// Diagonal block: Cholesky factor L_kk (in place) and its inverse Linv_k.
+// One workgroup.  Left-looking over 32-column panels: each panel is updated
+// by the panels to its left with FP64 MFMA, then factored unblocked in LDS.
+// Then the inverse is assembled block row by block row:
+//   Linv[I][J] = -D_I sum_{J <= M < I} L[I][M] Linv[M][J],   D_I = L[I][I]^{-1}.
+// Pivot rule: rows g >= n (the observation border and the identity padding)
+// take pivot 1; a pivot <= 0 or NaN at g < n records min(g) in *info and
+// continues with pivot 1 so that nothing downstream becomes non-finite.
+// logdet_part[k] = sum of log(pivot) over rows g < n of the block, in order.
+// ---------------------------------------------------------------------------
+constexpr int PW = 32;
+
+__global__ __launch_bounds__(256) void k_potrf_diag(double *__restrict__ A, int64_t lda, int kblk,
+                                                    int64_t n, double *__restrict__ Linv,
+                                                    double *__restrict__ logdet_part,
+                                                    int *__restrict__ info)
+{
+    __shared__ double P[NB * (PW + 1)];
+    __shared__ double piv[NB];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int64_t o = (int64_t)kblk * NB;
+    double *Ab = A + o + o * lda;
+
+    for (int pnl = 0; pnl < NB / PW; ++pnl) {
+        const int jb = pnl * PW;
+        const int M = NB - jb;
+        // (a) P = A[jb:, jb:jb+PW] - L[jb:, :jb] L[jb:jb+PW, :jb]^T
+        for (int tr = wave; tr < M / 16; tr += 4) {
+            d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+            const double *arow = Ab + (jb + tr * 16 + (lane & 15));
+            const double *brow = Ab + (jb + (lane & 15));
+#pragma unroll 4
+            for (int k0 = 0; k0 < jb; k0 += 4) {
+                const int64_t kk = (int64_t)(k0 + (lane >> 4)) * lda;
+                const double a = arow[kk], b0 = brow[kk], b1 = brow[kk + 16];
+                acc0 = mfma(a, b0, acc0);
+                acc1 = mfma(a, b1, acc1);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = tr * 16 + (lane >> 4) + 4 * r;
+                const int col = lane & 15;
+                P[row * (PW + 1) + col] = Ab[(jb + row) + (int64_t)(jb + col) * lda] - acc0[r];
+                P[row * (PW + 1) + col + 16] =
+                    Ab[(jb + row) + (int64_t)(jb + col + 16) * lda] - acc1[r];
+            }
+        }
+        // (b) unblocked factorisation of the M x PW panel, thread t owns row t
+        for (int c = 0; c < PW; ++c) {
+            __syncthreads();
+            const double d = P[c * (PW + 1) + c];
+            const int64_t g = o + jb + c;
+            double pv;
+            if (g >= n)
+                pv = 1.0;
+            else if (d > 0.0)
+                pv = sqrt(d);
+            else
+                pv = 1.0;
+            if (t == 0) {
+                piv[jb + c] = pv;
+                if (g < n && !(d > 0.0))
+                    atomicMin(info, (int)g);
+            }
+            if (t > c && t < M)
+                P[t * (PW + 1) + c] = P[t * (PW + 1) + c] / pv;
+            __syncthreads();
+            if (t > c && t < M) {
+                const double lt = P[t * (PW + 1) + c];
+                const int cend = t < PW - 1 ? t : PW - 1;
+                for (int c2 = c + 1; c2 <= cend; ++c2)
+                    P[t * (PW + 1) + c2] -= lt * P[c2 * (PW + 1) + c];
+            }
+        }
+        __syncthreads();
+        // (c) write the panel back: L[jb + i][jb + c] for i >= c
+        for (int idx = t; idx < M * PW; idx += 256) {
+            const int i = idx % M, c = idx / M;
+            if (i >= c)
+                Ab[(jb + i) + (int64_t)(jb + c) * lda] = (i == c) ? piv[jb + c] : P[i * (PW + 1) + c];
+        }
+        // (d) D = inverse of the top PW x PW block; thread t < PW forms column t
+        if (t < PW) {
+            double col[PW];
+#pragma unroll
+            for (int i = 0; i < PW; ++i) {
+                double s = (i == t) ? 1.0 : 0.0;
+#pragma unroll
+                for (int m = 0; m < i; ++m)
+                    s -= P[i * (PW + 1) + m] * col[m];
+                col[i] = (i < t) ? 0.0 : s / piv[jb + i];
+            }
+#pragma unroll
+            for (int i = 0; i < PW; ++i)
+                Linv[(jb + i) + (int64_t)(jb + t) * NB] = col[i];
+        }
+        __syncthreads();
+    }
+
+    // zero the blocks of Linv above the diagonal 32-blocks
+    for (int idx = t; idx < NB * NB; idx += 256) {
+        const int i = idx % NB, j = idx / NB;
+        if (i / PW < j / PW)
+            Linv[i + (int64_t)j * NB] = 0.0;
+    }
+    __syncthreads();
+
+    // inverse, block row by block row; T (32 x 224) staged in LDS (reuses P)
+    double *T = P; // T[r * NB + c], r < 32, c < 32 I
+    for (int I = 1; I < NB / PW; ++I) {
+        // T[:, J] = sum_{M=J}^{I-1} L[I][M] Linv[M][J] : units (J, 16x16 subtile)
+        for (int u = wave; u < 4 * I; u += 4) {
+            const int J = u >> 2, ti = (u >> 1) & 1, tj = u & 1;
+            d4 acc = {0, 0, 0, 0};
+            const double *arow = Ab + (PW * I + 16 * ti + (lane & 15));
+            const double *bcol = Linv + (int64_t)(PW * J + 16 * tj + (lane & 15)) * NB;
+            for (int k0 = PW * J; k0 < PW * I; k0 += 4) {
+                const int k = k0 + (lane >> 4);
+                acc = mfma(arow[(int64_t)k * lda], bcol[k], acc);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                T[(16 * ti + (lane >> 4) + 4 * r) * NB + PW * J + 16 * tj + (lane & 15)] = acc[r];
+        }
+        __syncthreads();
+        // Linv[I][J] = -D_I T[:, J]
+        for (int u = wave; u < 4 * I; u += 4) {
+            const int J = u >> 2, ti = (u >> 1) & 1, tj = u & 1;
+            d4 acc = {0, 0, 0, 0};
+            const double *drow = Linv + (PW * I + 16 * ti + (lane & 15)) + (int64_t)(PW * I) * NB;
+#pragma unroll
+            for (int k0 = 0; k0 < PW; k0 += 4) {
+                const int k = k0 + (lane >> 4);
+                acc = mfma(drow[(int64_t)k * NB], T[k * NB + PW * J + 16 * tj + (lane & 15)], acc);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = PW * I + 16 * ti + (lane >> 4) + 4 * r;
+                const int col = PW * J + 16 * tj + (lane & 15);
+                Linv[row + (int64_t)col * NB] = -acc[r];
+            }
+        }
+        __syncthreads();
+    }
+    // log-determinant of the block: fixed-order tree over the NB pivots
+    __shared__ double sh[4];
+    double lg = (o + t < n) ? log(piv[t]) : 0.0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        lg += __shfl_xor(lg, off, 64);
+    if (lane == 0)
+        sh[wave] = lg;
+    __syncthreads();
+    if (t == 0)
+        logdet_part[kblk] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+__global__ void k_init_info(int *info)
+{
+    if (threadIdx.x == 0)
+        info[0] = 0x7fffffff;
+}
+
+void launch_init_info(hipStream_t s, int *info)
+{
+    hipLaunchKernelGGL(k_init_info, dim3(1), dim3(64), 0, s, info);
+}
+
+void launch_potrf_diag(hipStream_t s, double *A, int64_t lda, int k, int64_t n, double *Linv,
+                       double *logdet_part, int *info)
+{
+    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, s, A, lda, k, n, Linv, logdet_part,
+                       info);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 MFMA tile engine.  A workgroup of 4 waves computes a (64 WM) x (64 WN)
+// tile of A * B^T, each wave a 64 x 64 block held as 4 x 4 MFMA accumulators.
+// A is M-contiguous (element (m, k) at A[m + k lda]).  B is N-contiguous
+// (element (n, k) at B[n + k ldb]) or, with BKC, K-contiguous (at B[k + n ldb]).
+// K is streamed in chunks of 16 through double-buffered LDS.  With the MFMA
+// operands swapped (B fragment first), lane l holds in accumulator (i, j),
+// element r, the tile entry (16 i + l % 16, 16 j + l / 16 + 4 r): 16
+// consecutive rows per column, so stores are 128-byte segments.
+// ---------------------------------------------------------------------------
+template <int WM, int WN, bool BKC> struct Tile {
+    static constexpr int BM = 64 * WM, BN = 64 * WN, KC = 16;
+    static constexpr int LSA = BM + 4, LSB = BN + 4; // padded LDS rows (doubles)
+    static constexpr int STAGE = KC * (LSA + LSB);
+    static constexpr int LDS = 2 * STAGE;
+    static constexpr int NA = BM * KC / 512; // double2 loads per thread
+    static constexpr int NBL = BN * KC / 512;
+
+    __device__ static void load(double2 *ra, double2 *rb, const double *A, int64_t lda,
+                                const double *B, int64_t ldb, int k0)
+    {
+        const int t = threadIdx.x;
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const int q = t + 256 * i, m2 = q % (BM / 2), k = q / (BM / 2);
+            ra[i] = *(const double2 *)(A + 2 * m2 + (int64_t)(k0 + k) * lda);
+        }
+#pragma unroll
+        for (int i = 0; i < NBL; ++i) {
+            const int q = t + 256 * i;
+            if (!BKC) {
+                const int n2 = q % (BN / 2), k = q / (BN / 2);
+                rb[i] = *(const double2 *)(B + 2 * n2 + (int64_t)(k0 + k) * ldb);
+            } else {
+                const int k2 = q % (KC / 2), nn = q / (KC / 2);
+                rb[i] = *(const double2 *)(B + (k0 + 2 * k2) + (int64_t)nn * ldb);
+            }
+        }
+    }
+    __device__ static void store(const double2 *ra, const double2 *rb, double *st)
+    {
+        const int t = threadIdx.x;
+        double *As = st, *Bs = st + KC * LSA;
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const int q = t + 256 * i, m2 = q % (BM / 2), k = q / (BM / 2);
+            *(double2 *)(As + k * LSA + 2 * m2) = ra[i];
+        }
+#pragma unroll
+        for (int i = 0; i < NBL; ++i) {
+            const int q = t + 256 * i;
+            if (!BKC) {
+                const int n2 = q % (BN / 2), k = q / (BN / 2);
+                *(double2 *)(Bs + k * LSB + 2 * n2) = rb[i];
+            } else {
+                const int k2 = q % (KC / 2), nn = q / (KC / 2);
+                Bs[(2 * k2) * LSB + nn] = rb[i].x;
+                Bs[(2 * k2 + 1) * LSB + nn] = rb[i].y;
+            }
+        }
+    }
+    __device__ static void compute(d4 (&acc)[4][4], const double *st, int wm, int wn, int lane)
+    {
+        const double *As = st + wm * 64 + (lane & 15);
+        const double *Bs = st + KC * LSA + wn * 64 + (lane & 15);
+#pragma unroll
+        for (int s = 0; s < KC / 4; ++s) {
+            const int kk = 4 * s + (lane >> 4);
+            double a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                a[i] = As[kk * LSA + 16 * i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                b[j] = Bs[kk * LSB + 16 * j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = mfma(b[j], a[i], acc[i][j]);
+        }
+    }
+    // acc = A(BM x K) * B(BN x K)^T for the workgroup tile; K % 16 == 0
+    __device__ static void run(d4 (&acc)[4][4], const double *A, int64_t lda, const double *B,
+                               int64_t ldb, int K, double *lds)
+    {
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        const int wm = wave % WM, wn = wave / WM;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = (d4){0, 0, 0, 0};
+        double2 ra[NA], rb[NBL];
+        load(ra, rb, A, lda, B, ldb, 0);
+        store(ra, rb, lds);
+        __syncthreads();
+        const int nch = K / KC;
+        for (int c = 0; c < nch; ++c) {
+            if (c + 1 < nch)
+                load(ra, rb, A, lda, B, ldb, (c + 1) * KC);
+            compute(acc, lds + (c & 1) * STAGE, wm, wn, lane);
+            if (c + 1 < nch)
+                store(ra, rb, lds + ((c + 1) & 1) * STAGE);
+            __syncthreads();
+        }
+    }
+    // row / column of accumulator (i, j) element r inside the workgroup tile
+    __device__ static int row(int i, int lane, int wm) { return wm * 64 + 16 * i + (lane & 15); }
+    __device__ static int col(int j, int r, int lane, int wn) { return wn * 64 + 16 * j + (lane >> 4) + 4 * r; }
+};
+
+// C -= A * B^T over the block-lower tiles of a trailing matrix of nblk x nblk
+// NB-blocks (128 x 128 tiles; both 128-tiles above the diagonal inside a
+// diagonal NB-block are included).  blockIdx.y selects (C0, A0) or (C1, A1).
+__global__ __launch_bounds__(256) void k_update_lower(double *C0, double *C1, int64_t ldc,
+                                                      const double *A0, const double *A1,
+                                                      int64_t lda, const double *B, int64_t ldb)
+{
+    using TL = Tile<2, 2, false>;
+    __shared__ double lds[TL::LDS];
+    const int64_t p = blockIdx.x >> 2;
+    const int s = blockIdx.x & 3;
+    int64_t I = (int64_t)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+    while ((I + 1) * (I + 2) / 2 <= p)
+        ++I;
+    while (I * (I + 1) / 2 > p)
+        --I;
+    const int64_t J = p - I * (I + 1) / 2;
+    const int64_t m0 = I * NB + 128 * (s >> 1), n0 = J * NB + 128 * (s & 1);
+    double *C = (blockIdx.y ? C1 : C0) + m0 + n0 * ldc;
+    const double *A = (blockIdx.y ? A1 : A0) + m0;
+    d4 acc[4][4];
+    TL::run(acc, A, lda, B + n0, ldb, NB, lds);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, wm = wave & 1, wn = wave >> 1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                double *c = C + TL::row(i, lane, wm) + (int64_t)TL::col(j, r, lane, wn) * ldc;
+                *c = *c - acc[i][j][r];
+            }
+}
+
+void launch_update_lower(hipStream_t s, int nmat, double *C0, double *C1, int64_t ldc,
+                         const double *A0, const double *A1, int64_t lda, const double *B,
+                         int64_t ldb, int nblk)
+{
+    if (nblk <= 0)
+        return;
+    const int64_t pairs = (int64_t)nblk * (nblk + 1) / 2;
+    hipLaunchKernelGGL(k_update_lower, dim3((unsigned)(4 * pairs), nmat), dim3(256), 0, s, C0, C1,
+                       ldc, A0, A1, lda, B, ldb);
+}
+
+// Panel solve of the factorisation: P (rows x NB, in place) = P Linv^T.
+// A workgroup owns 64 full rows, so the in-place update is race free.
+__global__ __launch_bounds__(256) void k_panel(double *P, int64_t ld, const double *Linv)
+{
+    using TL = Tile<1, 4, false>;
+    __shared__ double lds[TL::LDS];
+    double *Pb = P + (int64_t)blockIdx.x * 64;
+    d4 acc[4][4];
+    TL::run(acc, Pb, ld, Linv, NB, NB, lds);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                Pb[TL::row(i, lane, 0) + (int64_t)TL::col(j, r, lane, wave) * ld] = acc[i][j][r];
+}
+
+void launch_panel(hipStream_t s, double *P, int64_t ld, int64_t rows, const double *Linv)
+{
+    if (rows <= 0)
+        return;
+    hipLaunchKernelGGL(k_panel, dim3((unsigned)(rows / 64)), dim3(256), 0, s, P, ld, Linv);
+}
+
+// Left solve, diagonal block: S[krow:krow+NB, cols] = Linv * S[krow:krow+NB, cols]
+// (in place; a workgroup owns all NB rows of 64 columns).  Column tile c maps
+// to column 64 c, shifted by col_shift past the first half (two right-hand
+// sides stored side by side).
+__global__ __launch_bounds__(256) void k_diag_apply(double *S, int64_t ld, int64_t krow,
+                                                    const double *Linv, int64_t half_tiles,
+                                                    int64_t col_shift)
+{
+    using TL = Tile<4, 1, true>;
+    __shared__ double lds[TL::LDS];
+    const int64_t ct = blockIdx.x;
+    const int64_t c0 = (ct < half_tiles) ? 64 * ct : col_shift + 64 * (ct - half_tiles);
+    double *Sb = S + krow + c0 * ld;
+    d4 acc[4][4];
+    TL::run(acc, Linv, NB, Sb, ld, NB, lds);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                Sb[TL::row(i, lane, wave) + (int64_t)TL::col(j, r, lane, 0) * ld] = acc[i][j][r];
+}
+
+void launch_diag_apply(hipStream_t s, double *S, int64_t ld, int64_t krow, const double *Linv,
+                       int64_t ncols, int64_t col_shift)
+{
+    const int64_t half = ncols / 64;
+    hipLaunchKernelGGL(k_diag_apply, dim3((unsigned)(2 * half)), dim3(256), 0, s, S, ld, krow,
+                       Linv, half, col_shift);
+}
+
+// Left solve, update below the diagonal block:
+// S[r0 + 128 y, cols] -= L[r0 + 128 y, krow:krow+NB] * S[krow:krow+NB, cols].
+__global__ __launch_bounds__(256) void k_update_nn(double *S, int64_t ld, const double *L,
+                                                   int64_t lda, int64_t r0, int64_t krow,
+                                                   int64_t half_tiles, int64_t col_shift)
+{
+    using TL = Tile<2, 2, true>;
+    __shared__ double lds[TL::LDS];
+    const int64_t ct = blockIdx.x;
+    const int64_t c0 = (ct < half_tiles) ? 128 * ct : col_shift + 128 * (ct - half_tiles);
+    const int64_t m0 = r0 + 128 * (int64_t)blockIdx.y;
+    d4 acc[4][4];
+    TL::run(acc, L + m0 + krow * lda, lda, S + krow + c0 * ld, ld, NB, lds);
+    double *C = S + m0 + c0 * ld;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, wm = wave & 1, wn = wave >> 1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                double *c = C + TL::row(i, lane, wm) + (int64_t)TL::col(j, r, lane, wn) * ld;
+                *c = *c - acc[i][j][r];
+            }
+}
+
+void launch_update_nn(hipStream_t s, double *S, int64_t ld, const double *L, int64_t lda,
+                      int64_t r0, int64_t krow, int64_t rows, int64_t ncols, int64_t col_shift)
+{
+    if (rows <= 0)
+        return;
+    const int64_t half = ncols / 128;
+    hipLaunchKernelGGL(k_update_nn, dim3((unsigned)(2 * half), (unsigned)(rows / 128)), dim3(256),
+                       0, s, S, ld, L, lda, r0, krow, half, col_shift);
+}
+
+// ---------------------------------------------------------------------------
+// Right solve panel with the trace reductions.  For block column k, both
+// right-hand sides: W_i[r0 + 64 x, kcol:kcol+NB] = X_i[...] Linv^T in place,
+// after which those entries of W_i are final.  The epilogue accumulates, over
+// entries (a, b) with a, b < n,
+//   t_i = sum_a W_i[a][a],  F_ij = sum w_ab W_i[a][b] W_j[a][b]
+// with weight w_ab = 1 inside a diagonal NB-block (stored in full) and 2 below
+// it (the mirrored upper block is not stored), and picks u_i = W_i[n][n]
+// = y^T W_i y from the observation border.  Seven partial sums per workgroup
+// go to partials[8 blockIdx.x + 0..6] in a fixed order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_panel_reduce(double *Xa, double *Xn, int64_t ld,
+                                                      int64_t r0, int64_t kcol,
+                                                      const double *Linv, int64_t n,
+                                                      double *partials)
+{
+    using TL = Tile<1, 4, false>;
+    __shared__ double lds[TL::LDS];
+    __shared__ double red[4][8];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t m0 = r0 + (int64_t)blockIdx.x * 64;
+    d4 acc[4][4];
+    double wa[4][4][4];
+    double s[7] = {0, 0, 0, 0, 0, 0, 0}; // t_a, t_n, u_a, u_n, F_aa, F_an, F_nn
+    TL::run(acc, Xa + m0 + kcol * ld, ld, Linv, NB, NB, lds);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                wa[i][j][r] = acc[i][j][r];
+                Xa[m0 + TL::row(i, lane, 0) + (kcol + TL::col(j, r, lane, wave)) * ld] = acc[i][j][r];
+            }
+    TL::run(acc, Xn + m0 + kcol * ld, ld, Linv, NB, NB, lds);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const double vn = acc[i][j][r], va = wa[i][j][r];
+                const int64_t a = m0 + TL::row(i, lane, 0);
+                const int64_t b = kcol + TL::col(j, r, lane, wave);
+                Xn[a + b * ld] = vn;
+                if (a < n && b < n) {
+                    const double w = (a / NB == b / NB) ? 1.0 : 2.0;
+                    s[4] = fma(w * va, va, s[4]);
+                    s[5] = fma(w * va, vn, s[5]);
+                    s[6] = fma(w * vn, vn, s[6]);
+                    if (a == b) {
+                        s[0] += va;
+                        s[1] += vn;
+                    }
+                } else if (a == n && b == n) {
+                    s[2] = va;
+                    s[3] = vn;
+                }
+            }
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+        const double v = wave_sum(s[q]);
+        if (lane == 0)
+            red[wave][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 7) {
+        const int q = threadIdx.x;
+        partials[8 * (int64_t)blockIdx.x + q] = ((red[0][q] + red[1][q]) + red[2][q]) + red[3][q];
+    }
+}
+
+void launch_panel_reduce(hipStream_t s, double *Xa, double *Xn, int64_t ld, int64_t r0,
+                         int64_t kcol, int64_t rows, const double *Linv, int64_t n,
+                         double *partials)
+{
+    hipLaunchKernelGGL(k_panel_reduce, dim3((unsigned)(rows / 64)), dim3(256), 0, s, Xa, Xn, ld, r0,
+                       kcol, Linv, n, partials);
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic reductions (fixed summation order, one workgroup).
+// out[0] = log det Sigma = 2 sum_k logdet_part[k];  out[1] = y^T y with
+// y = row n of the bordered factor.
+// ---------------------------------------------------------------------------
+__device__ double block_sum(double v, double *sh)
+{
+    const int t = threadIdx.x;
+    v = wave_sum(v);
+    if ((t & 63) == 0)
+        sh[t >> 6] = v;
+    __syncthreads();
+    double r = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(256) void k_reduce_loglik(const double *A, int64_t lda, int64_t n,
+                                                       int T, const double *logdet_part,
+                                                       double *out)
+{
+    __shared__ double sh[4];
+    const int t = threadIdx.x;
+    double q = 0.0;
+    for (int64_t c = t; c < n; c += 256) {
+        const double y = A[n + c * lda];
+        q = fma(y, y, q);
+    }
+    double ld = 0.0;
+    for (int k = t; k < T; k += 256)
+        ld += logdet_part[k];
+    q = block_sum(q, sh);
+    ld = block_sum(ld, sh);
+    if (t == 0) {
+        out[0] = 2.0 * ld;
+        out[1] = q;
+    }
+}
+
+void launch_reduce_loglik(hipStream_t s, const double *A, int64_t lda, int64_t n, int T,
+                          const double *logdet_part, double *out)
+{
+    hipLaunchKernelGGL(k_reduce_loglik, dim3(1), dim3(256), 0, s, A, lda, n, T, logdet_part, out);
+}
+
+// out[2..8] = sums over `count` groups of 8 partials (t_a, t_n, u_a, u_n, F_aa, F_an, F_nn)
+__global__ __launch_bounds__(256) void k_reduce_terms(const double *partials, int64_t count,
+                                                      double *out)
+{
+    __shared__ double sh[4];
+    const int t = threadIdx.x;
+    for (int q = 0; q < 7; ++q) {
+        double v = 0.0;
+        for (int64_t g = t; g < count; g += 256)
+            v += partials[8 * g + q];
+        v = block_sum(v, sh);
+        if (t == 0)
+            out[2 + q] = v;
+    }
+}
+
+void launch_reduce_terms(hipStream_t s, const double *partials, int64_t count, double *out)
+{
+    hipLaunchKernelGGL(k_reduce_terms, dim3(1), dim3(256), 0, s, partials, count, out);
+}
+
+}  // namespace fbt

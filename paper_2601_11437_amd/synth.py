@@ -55,12 +55,13 @@ def _matern_for_simulation(h: np.ndarray, theta) -> np.ndarray:
 
 def grf(locs: np.ndarray, theta, gen: np.random.Generator) -> np.ndarray:
     """One realisation Z ~ N(0, Sigma(theta)); raises LinAlgError if not PD."""
+    from scipy.spatial.distance import cdist
+
     n = locs.shape[0]
     S = np.empty((n, n))
     blk = 2048
     for r0 in range(0, n, blk):       # bounded temporaries at large n
-        d = locs[r0:r0 + blk, None, :] - locs[None, :, :]
-        S[r0:r0 + blk] = _matern_for_simulation(np.sqrt(np.einsum("ijk,ijk->ij", d, d)), theta)
+        S[r0:r0 + blk] = _matern_for_simulation(cdist(locs[r0:r0 + blk], locs), theta)
     L = np.linalg.cholesky(S)
     del S
     w = gen.standard_normal(n)

@@ -1,0 +1,190 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle on
+the same seeded inputs.
+
+Tolerances (FP64 throughout):
+  * log-likelihood (Eq. 1): |d l| <= 1e-10 |l|;
+  * score (Eq. 2), per term: |d l_i| <= 1e-10 * (|tr(Sigma^-1 Sigma_i)| + |w' Sigma_i w|) / 2
+    (for sigma2 the terms are (Z' Sigma^-1 Z + n) / (2 sigma2)), because the score
+    is a difference of two such terms and vanishes at the optimum;
+  * Fisher (Eq. 3): |d I_ij| <= 1e-8 sqrt(I_ii I_jj);
+  * covariance entries: |d C| <= 1e-13 |C| + 1e-300; the derivatives add a
+    cancellation allowance 1e-14 |C| (1 + |log x| + |psi(nu)|) for C_nu (two
+    terms of that size cancel as x -> 0) and 1e-14 |C| for C_alpha.
+Gates apply where eps * cond(Sigma) <= 1e-6 (conditioning is checked).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import scipy.special as sp
+
+import paper_2601_11437_amd as fbt
+from paper_2601_11437_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = fbt.Context(0)
+    yield c
+    c.close()
+
+
+THETAS = [(1.0, 0.1, 0.5), (0.6, 0.05, 1.4), (2.0, 0.2, 0.25), (1.5, 0.07, 1.0),
+          (0.8, 0.3, 0.05), (1.2, 0.02, 2.6)]
+
+
+def _dist(locs):
+    d = locs[:, None, :] - locs[None, :, :]
+    return np.sqrt((d ** 2).sum(-1))
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 255, 256, 257, 700])
+@pytest.mark.parametrize("theta", THETAS)
+def test_covariance_entries(ctx, oracle_mod, n, theta):
+    say("covariance n=%d theta=%s" % (n, theta))
+    locs, z, _ = synth.dataset(n, (1.0, 0.1, 0.5), 100 + n)
+    ctx.set_data(locs, z)
+    S, Sa, Sn = oracle_mod.cov_matrices(locs, theta)
+    G = [ctx.covariance(theta, w) for w in (0, 1, 2)]
+    x = _dist(locs) / theta[1]
+    with np.errstate(divide="ignore"):
+        lx = np.where(x > 0, np.abs(np.log(np.where(x > 0, x, 1.0))), 0.0)
+    base = 1e-13 * np.abs(S) + 1e-300
+    assert np.all(np.abs(G[0] - S) <= base), np.max(np.abs(G[0] - S) / (np.abs(S) + 1e-300))
+    assert np.all(np.abs(G[1] - Sa) <= 1e-13 * np.abs(Sa) + 1e-14 * np.abs(S) + 1e-300)
+    tol_n = 1e-13 * np.abs(Sn) + 1e-14 * np.abs(S) * (1 + lx + abs(sp.digamma(theta[2]))) + 1e-300
+    assert np.all(np.abs(G[2] - Sn) <= tol_n), np.max(np.abs(G[2] - Sn) / tol_n)
+    np.testing.assert_array_equal(G[0], G[0].T)
+    np.testing.assert_array_equal(G[1], G[1].T)
+    np.testing.assert_array_equal(G[2], G[2].T)
+
+
+def _cond(locs, theta, oracle_mod):
+    (S,) = oracle_mod.cov_matrices(locs, theta, which=("S",))
+    w = np.linalg.eigvalsh(S)
+    return w[-1] / w[0] if w[0] > 0 else math.inf
+
+
+CASES = [(1, THETAS[0]), (2, THETAS[1]), (100, THETAS[2]), (255, THETAS[0]), (256, THETAS[3]),
+         (257, THETAS[4]), (600, THETAS[0]), (600, THETAS[1]), (600, THETAS[5]),
+         (1500, THETAS[0]), (1500, THETAS[3])]
+
+
+@pytest.mark.parametrize("n,theta", CASES)
+def test_eval_parity(ctx, oracle_mod, n, theta):
+    say("eval n=%d theta=%s" % (n, theta))
+    locs, z, _ = synth.dataset(n, (1.0, 0.1, 0.5), 1000 + n)
+    if n > 2:
+        kappa = _cond(locs, theta, oracle_mod)
+        assert np.finfo(float).eps * kappa <= 1e-6, kappa
+    ctx.set_data(locs, z)
+    want = oracle_mod.evaluate(locs, z, theta)
+    ll = ctx.loglik(theta)
+    assert abs(ll - want["loglik"]) <= 1e-10 * abs(want["loglik"])
+    gll, score, fisher = ctx.eval(theta)
+    assert abs(gll - want["loglik"]) <= 1e-10 * abs(want["loglik"])
+    scale = np.array([(want["quad"] + n) / (2 * theta[0]),
+                      0.5 * (abs(want["trace"]["a"]) + abs(want["wSw"]["a"])),
+                      0.5 * (abs(want["trace"]["n"]) + abs(want["wSw"]["n"]))])
+    assert np.all(np.abs(score - want["score"]) <= 1e-10 * scale), (score, want["score"], scale)
+    I = want["fisher"]
+    d = np.sqrt(np.outer(np.diag(I), np.diag(I)))
+    assert np.all(np.abs(fisher - I) <= 1e-8 * d), (fisher, I)
+    t = ctx.eval_terms(theta)
+    ref = [want["logdet"], want["quad"], want["trace"]["a"], want["trace"]["n"], want["wSw"]["a"],
+           want["wSw"]["n"], want["trAB_direct"]["aa"], want["trAB_direct"]["an"],
+           want["trAB_direct"]["nn"]]
+    sc = [abs(want["logdet"]) + n, want["quad"], scale[1], scale[2], scale[1], scale[2],
+          I[1, 1] * 2, d[1, 2] * 2, I[2, 2] * 2]
+    for k in range(9):
+        assert abs(t[k] - ref[k]) <= 1e-9 * sc[k] + 1e-300, (k, t[k], ref[k])
+
+
+@pytest.mark.parametrize("n", [300, 700])
+def test_factor_parity(ctx, oracle_mod, n):
+    say("factor n=%d" % n)
+    locs, z, _ = synth.dataset(n, (1.0, 0.1, 0.5), 2000 + n)
+    theta = (1.0, 0.1, 0.5)
+    ctx.set_data(locs, z)
+    L = ctx.factor(theta)
+    (S,) = oracle_mod.cov_matrices(locs, theta, which=("S",))
+    Lref = np.linalg.cholesky(S)
+    assert np.max(np.abs(L - Lref)) <= 1e-12 * np.max(np.abs(Lref))
+    np.testing.assert_array_equal(np.triu(L, 1), 0.0)
+
+
+def test_determinism(ctx):
+    say("determinism")
+    locs, z, _ = synth.dataset(900, (1.0, 0.1, 0.5), 5)
+    ctx.set_data(locs, z)
+    a = ctx.eval_terms((1.1, 0.09, 0.7))
+    b = ctx.eval_terms((1.1, 0.09, 0.7))
+    np.testing.assert_array_equal(a, b)
+    # eval right after loglik at the same theta reuses the factor: same numbers
+    ctx.loglik((1.1, 0.09, 0.7))
+    c = ctx.eval_terms((1.1, 0.09, 0.7))
+    np.testing.assert_array_equal(a, c)
+
+
+def test_not_positive_definite(ctx):
+    say("notpd")
+    locs, z, _ = synth.dataset(300, (1.0, 0.1, 0.5), 6)
+    locs[200] = locs[17]                      # duplicated location -> singular Sigma
+    ctx.set_data(locs, z)
+    with pytest.raises(fbt.FisherBTError) as e:
+        ctx.loglik((1.0, 0.1, 0.5))
+    assert e.value.status == fbt.ENOTPD and e.value.pivot == 200
+    with pytest.raises(fbt.FisherBTError) as e:
+        ctx.eval((1.0, 0.1, 0.5))
+    assert e.value.status == fbt.ENOTPD
+
+
+def test_invalid_arguments(ctx):
+    say("invalid")
+    locs, z, _ = synth.dataset(50, (1.0, 0.1, 0.5), 7)
+    ctx.set_data(locs, z)
+    for bad in ((0.0, 0.1, 0.5), (1.0, -0.1, 0.5), (1.0, 0.1, float("nan"))):
+        with pytest.raises(fbt.FisherBTError) as e:
+            ctx.loglik(bad)
+        assert e.value.status == fbt.EINVAL
+    bad_z = z.copy()
+    bad_z[3] = np.inf
+    with pytest.raises(fbt.FisherBTError) as e:
+        ctx.set_data(locs, bad_z)
+    assert e.value.status == fbt.EINVAL
+
+
+def test_device_pointer_input(ctx, oracle_mod):
+    say("device input")
+    torch = pytest.importorskip("torch")
+    locs, z, _ = synth.dataset(400, (1.0, 0.1, 0.5), 8)
+    ctx.set_data(torch.tensor(locs, device="cuda"), torch.tensor(z, device="cuda"))
+    want = oracle_mod.loglik(locs, z, (1.0, 0.1, 0.5))["loglik"]
+    assert abs(ctx.loglik((1.0, 0.1, 0.5)) - want) <= 1e-10 * abs(want)
+
+
+def test_fit_n400_matches_oracle(ctx, oracle_mod):
+    """Fisher-BT from theta0 = (0.5, 0.05, 1.0), at most 50 iterations, on 400
+    uniform points with theta_true = (1, 0.1, 0.5)."""
+    say("fit n400")
+    w = synth.WORKLOADS["n400"]
+    locs, z, _ = synth.dataset(w["n"], w["theta_true"], w["seed"])
+    ctx.set_data(locs, z)
+    it_gpu = []
+    got = ctx.fit(theta0=(0.5, 0.05, 1.0), max_iter=50,
+                  callback=lambda it, th, ll, g, f: it_gpu.append((th, ll, g, f)))
+    want = oracle_mod.fisher_bt(oracle_mod.OracleEvaluator(locs, z), theta0=(0.5, 0.05, 1.0),
+                                max_iter=50)
+    say("gpu", got["theta"], got["n_iter"], "oracle", want["theta"], want["n_iter"])
+    assert got["converged"] and want["converged"]
+    assert (got["n_loglik_calls"], got["n_grad_calls"]) == (want["n_loglik_calls"], want["n_grad_calls"])
+    np.testing.assert_allclose(got["theta"], want["theta"], rtol=1e-6)
+    assert len(it_gpu) == got["n_iter"] + 1
