@@ -30,7 +30,9 @@ struct Timed {
 
 struct fbt_ctx {
     int device = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;  // s0: the caller's stream; the critical path runs here
+    hipStream_t stream2 = nullptr; // s1: bulk trailing updates (lookahead), joined back to s0
+    hipEvent_t evP = nullptr, evB = nullptr;
     bool own_stream = false;
     std::string err;
     int64_t notpd = -1;
@@ -136,8 +138,8 @@ GenParams setup_theta(fbt_ctx *c, const double *th)
     return gp;
 }
 
-// ---- timing helpers ----
-void tbegin(fbt_ctx *c, hipEvent_t *a, hipEvent_t *b)
+// ---- timing helpers: HIP events around each launch on the launch's stream ----
+void tbegin(fbt_ctx *c, hipStream_t st, hipEvent_t *a, hipEvent_t *b)
 {
     if (!c->timing)
         return;
@@ -149,13 +151,13 @@ void tbegin(fbt_ctx *c, hipEvent_t *a, hipEvent_t *b)
     }
     *a = c->pool[c->pool_used++];
     *b = c->pool[c->pool_used++];
-    (void)hipEventRecord(*a, c->stream);
+    (void)hipEventRecord(*a, st);
 }
-void tend(fbt_ctx *c, int cls, double flops, hipEvent_t a, hipEvent_t b)
+void tend(fbt_ctx *c, hipStream_t st, int cls, double flops, hipEvent_t a, hipEvent_t b)
 {
     if (!c->timing)
         return;
-    (void)hipEventRecord(b, c->stream);
+    (void)hipEventRecord(b, st);
     c->pending.push_back({cls, flops, a, b});
 }
 void tcollect(fbt_ctx *c)
@@ -174,13 +176,13 @@ void tcollect(fbt_ctx *c)
     c->pool_used = 0;
 }
 
-#define TIMED(ctx, cls, flops, call)                                                               \
+#define TIMED(ctx, st, cls, flops, call)                                                           \
     do {                                                                                           \
         hipEvent_t ta_ = nullptr, tb_ = nullptr;                                                   \
-        tbegin(ctx, &ta_, &tb_);                                                                   \
+        tbegin(ctx, st, &ta_, &tb_);                                                               \
         call;                                                                                      \
         if (ta_)                                                                                   \
-            tend(ctx, cls, flops, ta_, tb_);                                                       \
+            tend(ctx, st, cls, flops, ta_, tb_);                                                   \
     } while (0)
 
 void free_buffers(fbt_ctx *c)
@@ -249,6 +251,12 @@ fbt_status upload_theta(fbt_ctx *c, const double *th, GenParams *gp)
 
 // Generate Sigma' (and/or the derivative matrices) and factor the bordered
 // Sigma'.  On success c->factor_out = {log det, y^T y}.
+//
+// Right-looking block Cholesky with one step of lookahead on two streams.
+// Step k on s0 (critical path): update block column k+1 with panel k, factor
+// diagonal block k+1 and solve panel k+1.  On s1: the rest of the trailing
+// update with panel k (block columns >= k+2).  Block column k+1 is written
+// by s0 only after the previous bulk update (which also wrote it) is done.
 fbt_status factorize(fbt_ctx *c, const double *th, int mode)
 {
     GenParams gp;
@@ -258,27 +266,45 @@ fbt_status factorize(fbt_ctx *c, const double *th, int mode)
     c->factor_valid = false;
     const int64_t npad = c->npad, ld = c->ld, n = c->n;
     const int T = c->T;
-    launch_init_info(c->stream, c->info);
-    TIMED(c, KC_GEN, 0.0, launch_gen(c->stream, gp, c->x, c->y, c->z, c->tab, c->A, c->S2,
-                                       c->S2 + npad * ld, mode));
-    for (int k = 0; k < T; ++k) {
-        double *Lk = c->Linv + (size_t)k * NB * NB;
-        TIMED(c, KC_DIAG, 2.0 * NB * (double)NB * NB / 3.0,
-              launch_potrf_diag(c->stream, c->A, ld, k, n, Lk, c->logdet, c->info));
-        const int64_t r0 = (int64_t)(k + 1) * NB, rows = npad - r0;
-        if (rows <= 0)
-            continue;
-        const double m = (double)std::max<int64_t>(0, n - r0);
-        double *panel = c->A + r0 + (int64_t)k * NB * ld;
-        TIMED(c, KC_PANEL, m * NB * NB, launch_panel(c->stream, panel, ld, rows, Lk));
-        TIMED(c, KC_SYRK, m * m * NB,
-              launch_update_lower(c->stream, 1, c->A + r0 + r0 * ld, nullptr, ld, panel, nullptr,
-                                  ld, panel, ld, T - k - 1));
+    hipStream_t s0 = c->stream, s1 = c->stream2;
+    double *A = c->A;
+    const double dNB = NB;
+    auto Lk = [&](int k) { return c->Linv + (size_t)k * NB * NB; };
+    launch_init_info(s0, c->info);
+    TIMED(c, s0, KC_GEN, 0.0, launch_gen(s0, gp, c->x, c->y, c->z, c->tab, A, c->S2,
+                                           c->S2 + npad * ld, mode));
+    TIMED(c, s0, KC_DIAG, 2.0 * dNB * dNB * dNB / 3.0,
+          launch_potrf_diag(s0, A, ld, 0, n, Lk(0), c->logdet, c->info));
+    if (T > 1)
+        TIMED(c, s0, KC_PANEL, std::max(0.0, double(n - NB)) * dNB * dNB,
+              launch_panel(s0, A + NB, ld, npad - NB, Lk(0)));
+    HIPCHK(c, hipEventRecord(c->evP, s0));
+    HIPCHK(c, hipEventRecord(c->evB, s0));
+    for (int k = 0; k + 1 < T; ++k) {
+        const int64_t r1 = (int64_t)(k + 1) * NB, r2 = r1 + NB, kc = (int64_t)k * NB;
+        const double m1 = std::max<int64_t>(0, n - r1), m2 = std::max<int64_t>(0, n - r2);
+        HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
+        TIMED(c, s0, KC_SYRK, std::max(0.0, 2.0 * m1 * dNB * dNB - dNB * dNB * dNB),
+              launch_update_rect(s0, 1, A + r1 + r1 * ld, nullptr, ld, A + r1 + kc * ld, nullptr,
+                                 ld, A + r1 + kc * ld, ld, npad - r1));
+        TIMED(c, s0, KC_DIAG, 2.0 * dNB * dNB * dNB / 3.0,
+              launch_potrf_diag(s0, A, ld, k + 1, n, Lk(k + 1), c->logdet, c->info));
+        if (k + 2 < T)
+            TIMED(c, s0, KC_PANEL, m2 * dNB * dNB,
+                  launch_panel(s0, A + r2 + r1 * ld, ld, npad - r2, Lk(k + 1)));
+        HIPCHK(c, hipStreamWaitEvent(s1, c->evP, 0));
+        if (k + 2 < T)
+            TIMED(c, s1, KC_SYRK, m2 * m2 * dNB,
+                  launch_update_lower(s1, 1, A + r2 + r2 * ld, nullptr, ld, A + r2 + kc * ld,
+                                      nullptr, ld, A + r2 + kc * ld, ld, T - k - 2));
+        HIPCHK(c, hipEventRecord(c->evB, s1));
+        HIPCHK(c, hipEventRecord(c->evP, s0));
     }
-    TIMED(c, KC_RED, 0.0, launch_reduce_loglik(c->stream, c->A, ld, n, T, c->logdet, c->out));
-    HIPCHK(c, hipMemcpyAsync(c->h_out, c->out, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->h_info, c->info, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
+    TIMED(c, s0, KC_RED, 0.0, launch_reduce_loglik(s0, A, ld, n, T, c->logdet, c->out));
+    HIPCHK(c, hipMemcpyAsync(c->h_out, c->out, 2 * sizeof(double), hipMemcpyDeviceToHost, s0));
+    HIPCHK(c, hipMemcpyAsync(c->h_info, c->info, sizeof(int), hipMemcpyDeviceToHost, s0));
+    HIPCHK(c, hipStreamSynchronize(s0));
     tcollect(c);
     if (c->h_info[0] != 0x7fffffff) {
         c->notpd = c->h_info[0];
@@ -303,53 +329,84 @@ bool same_theta(const fbt_ctx *c, const double *th)
 }
 
 // W phase of Algorithm 3 on a valid factor: out[0..8] (see fbt_eval_terms).
+// Both block solves use the same two-stream lookahead as the factorisation:
+// s0 finishes block row / column k+1 and applies its diagonal inverse while
+// s1 applies step k to everything beyond it.
 fbt_status derivative_terms(fbt_ctx *c, const double *th, double terms[9])
 {
     fbt_status st;
+    hipStream_t s0 = c->stream, s1 = c->stream2;
     if (same_theta(c, th)) {
         GenParams gp;
         if ((st = upload_theta(c, th, &gp)) != FBT_OK)
             return st;
-        TIMED(c, KC_GEN, 0.0, launch_gen(c->stream, gp, c->x, c->y, c->z, c->tab, c->A, c->S2,
-                                           c->S2 + c->npad * c->ld, GEN_DERIV));
+        TIMED(c, s0, KC_GEN, 0.0, launch_gen(s0, gp, c->x, c->y, c->z, c->tab, c->A, c->S2,
+                                               c->S2 + c->npad * c->ld, GEN_DERIV));
     } else if ((st = factorize(c, th, GEN_ALL)) != FBT_OK) {
         return st;
     }
     c->factor_valid = false; // reuse is for one derivative evaluation only
     const int64_t npad = c->npad, ld = c->ld, n = c->n, ncols = c->ncols;
     const int T = c->T;
-    double *Sa = c->S2, *Sn = c->S2 + npad * ld;
-    const double dn = (double)n;
+    double *Sa = c->S2, *Sn = c->S2 + npad * ld, *A = c->A;
+    const double dn = (double)n, dNB = NB;
+    auto Lk = [&](int k) { return c->Linv + (size_t)k * NB * NB; };
+
     // left solve X = L'^{-1} [Sigma_alpha' | Sigma_nu'] on columns [0, ncols) of each half
-    for (int k = 0; k < T; ++k) {
-        const double *Lk = c->Linv + (size_t)k * NB * NB;
-        const int64_t krow = (int64_t)k * NB, r0 = krow + NB;
-        TIMED(c, KC_LAPPLY, 2.0 * dn * NB * NB,
-              launch_diag_apply(c->stream, c->S2, ld, krow, Lk, ncols, npad));
-        const double m = (double)std::max<int64_t>(0, n - r0);
-        TIMED(c, KC_LUPD, 2.0 * m * NB * 2.0 * dn,
-              launch_update_nn(c->stream, c->S2, ld, c->A, ld, r0, krow, npad - r0, ncols,
-                               npad));
+    TIMED(c, s0, KC_LAPPLY, 2.0 * dn * dNB * dNB,
+          launch_diag_apply(s0, c->S2, ld, 0, Lk(0), ncols, npad));
+    HIPCHK(c, hipEventRecord(c->evP, s0));
+    HIPCHK(c, hipEventRecord(c->evB, s0));
+    for (int k = 0; k + 1 < T; ++k) {
+        const int64_t kc = (int64_t)k * NB, r1 = kc + NB, r2 = r1 + NB;
+        const double m1 = std::min<double>(NB, std::max<int64_t>(0, n - r1));
+        const double m2 = std::max<int64_t>(0, n - r2);
+        HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
+        TIMED(c, s0, KC_LUPD, 2.0 * m1 * dNB * 2.0 * dn,
+              launch_update_nn(s0, c->S2, ld, A, ld, r1, kc, NB, ncols, npad));
+        TIMED(c, s0, KC_LAPPLY, 2.0 * dn * dNB * dNB,
+              launch_diag_apply(s0, c->S2, ld, r1, Lk(k + 1), ncols, npad));
+        HIPCHK(c, hipStreamWaitEvent(s1, c->evP, 0));
+        if (k + 2 < T)
+            TIMED(c, s1, KC_LUPD, 2.0 * m2 * dNB * 2.0 * dn,
+                  launch_update_nn(s1, c->S2, ld, A, ld, r2, kc, npad - r2, ncols, npad));
+        HIPCHK(c, hipEventRecord(c->evB, s1));
+        HIPCHK(c, hipEventRecord(c->evP, s0));
     }
+    HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
+
     // right solve W = X L'^{-T} (block-lower) with the fused reductions
     int64_t groups = 0;
-    for (int k = 0; k < T; ++k) {
-        const double *Lk = c->Linv + (size_t)k * NB * NB;
-        const int64_t kc = (int64_t)k * NB, r1 = kc + NB, rows = npad - kc;
-        const double mp = (double)std::max<int64_t>(0, n - kc);
-        TIMED(c, KC_RPANEL, 2.0 * mp * NB * NB,
-              launch_panel_reduce(c->stream, Sa, Sn, ld, kc, kc, rows, Lk, n,
+    TIMED(c, s0, KC_RPANEL, 2.0 * 2.0 * dn * dNB * dNB,
+          launch_panel_reduce(s0, Sa, Sn, ld, 0, 0, npad, Lk(0), n, c->partials));
+    groups += npad / 64;
+    HIPCHK(c, hipEventRecord(c->evP, s0));
+    HIPCHK(c, hipEventRecord(c->evB, s0));
+    for (int k = 0; k + 1 < T; ++k) {
+        const int64_t kc = (int64_t)k * NB, r1 = kc + NB, r2 = r1 + NB;
+        const double m1 = std::max<int64_t>(0, n - r1), m2 = std::max<int64_t>(0, n - r2);
+        HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
+        TIMED(c, s0, KC_RUPD, 2.0 * 2.0 * m1 * dNB * dNB,
+              launch_update_rect(s0, 2, Sa + r1 + r1 * ld, Sn + r1 + r1 * ld, ld,
+                                 Sa + r1 + kc * ld, Sn + r1 + kc * ld, ld, A + r1 + kc * ld, ld,
+                                 npad - r1));
+        TIMED(c, s0, KC_RPANEL, 2.0 * 2.0 * m1 * dNB * dNB,
+              launch_panel_reduce(s0, Sa, Sn, ld, r1, r1, npad - r1, Lk(k + 1), n,
                                   c->partials + 8 * groups));
-        groups += rows / 64;
-        const double m = (double)std::max<int64_t>(0, n - r1);
-        TIMED(c, KC_RUPD, 2.0 * m * m * NB,
-              launch_update_lower(c->stream, 2, Sa + r1 + r1 * ld, Sn + r1 + r1 * ld, ld,
-                                  Sa + r1 + kc * ld, Sn + r1 + kc * ld, ld, c->A + r1 + kc * ld,
-                                  ld, T - k - 1));
+        groups += (npad - r1) / 64;
+        HIPCHK(c, hipStreamWaitEvent(s1, c->evP, 0));
+        if (k + 2 < T)
+            TIMED(c, s1, KC_RUPD, 2.0 * m2 * m2 * dNB,
+                  launch_update_lower(s1, 2, Sa + r2 + r2 * ld, Sn + r2 + r2 * ld, ld,
+                                      Sa + r2 + kc * ld, Sn + r2 + kc * ld, ld, A + r2 + kc * ld,
+                                      ld, T - k - 2));
+        HIPCHK(c, hipEventRecord(c->evB, s1));
+        HIPCHK(c, hipEventRecord(c->evP, s0));
     }
-    TIMED(c, KC_RED, 0.0, launch_reduce_terms(c->stream, c->partials, groups, c->out));
-    HIPCHK(c, hipMemcpyAsync(c->h_out, c->out, 9 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
+    TIMED(c, s0, KC_RED, 0.0, launch_reduce_terms(s0, c->partials, groups, c->out));
+    HIPCHK(c, hipMemcpyAsync(c->h_out, c->out, 9 * sizeof(double), hipMemcpyDeviceToHost, s0));
+    HIPCHK(c, hipStreamSynchronize(s0));
     tcollect(c);
     // the derivative matrices were overwritten; the factor itself is intact
     terms[0] = c->factor_out[0];
@@ -476,6 +533,12 @@ fbt_status fbt_create(const fbt_config *cfg, fbt_ctx **out)
         }
         c->own_stream = true;
     }
+    if (hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->evP, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->evB, hipEventDisableTiming) != hipSuccess) {
+        fbt_destroy(c);
+        return FBT_EDEVICE;
+    }
     if (hipHostMalloc((void **)&c->h_tab, TAB_MAX * sizeof(Node), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&c->h_out, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&c->h_info, 16 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
@@ -502,6 +565,14 @@ void fbt_destroy(fbt_ctx *c)
         (void)hipHostFree(c->h_out);
     if (c->h_info)
         (void)hipHostFree(c->h_info);
+    if (c->stream2) {
+        (void)hipStreamSynchronize(c->stream2);
+        (void)hipStreamDestroy(c->stream2);
+    }
+    if (c->evP)
+        (void)hipEventDestroy(c->evP);
+    if (c->evB)
+        (void)hipEventDestroy(c->evB);
     if (c->own_stream && c->stream)
         (void)hipStreamDestroy(c->stream);
     delete c;

@@ -350,7 +350,7 @@ void launch_potrf_diag(hipStream_t s, double *A, int64_t lda, int k, int64_t n, 
 // element r, the tile entry (16 i + l % 16, 16 j + l / 16 + 4 r): 16
 // consecutive rows per column, so stores are 128-byte segments.
 // ---------------------------------------------------------------------------
-template <int WM, int WN, bool BKC> struct Tile {
+template <int WM, int WN, bool BKC, bool NEG = false> struct Tile {
     static constexpr int BM = 64 * WM, BN = 64 * WN, KC = 16;
     static constexpr int LSA = BM + 4, LSB = BN + 4; // padded LDS rows (doubles)
     static constexpr int STAGE = KC * (LSA + LSB);
@@ -386,7 +386,12 @@ template <int WM, int WN, bool BKC> struct Tile {
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
             const int q = t + 256 * i, m2 = q % (BM / 2), k = q / (BM / 2);
-            *(double2 *)(As + k * LSA + 2 * m2) = ra[i];
+            double2 v = ra[i];
+            if (NEG) {
+                v.x = -v.x;
+                v.y = -v.y;
+            }
+            *(double2 *)(As + k * LSA + 2 * m2) = v;
         }
 #pragma unroll
         for (int i = 0; i < NBL; ++i) {
@@ -422,17 +427,12 @@ template <int WM, int WN, bool BKC> struct Tile {
                     acc[i][j] = mfma(b[j], a[i], acc[i][j]);
         }
     }
-    // acc = A(BM x K) * B(BN x K)^T for the workgroup tile; K % 16 == 0
+    // acc += (NEG ? -A : A)(BM x K) * B(BN x K)^T for the workgroup tile; K % 16 == 0
     __device__ static void run(d4 (&acc)[4][4], const double *A, int64_t lda, const double *B,
                                int64_t ldb, int K, double *lds)
     {
         const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
         const int wm = wave % WM, wn = wave / WM;
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                acc[i][j] = (d4){0, 0, 0, 0};
         double2 ra[NA], rb[NBL];
         load(ra, rb, A, lda, B, ldb, 0);
         store(ra, rb, lds);
@@ -447,6 +447,40 @@ template <int WM, int WN, bool BKC> struct Tile {
             __syncthreads();
         }
     }
+    __device__ static void zero(d4 (&acc)[4][4])
+    {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = (d4){0, 0, 0, 0};
+    }
+    // acc = the C tile (column-major, ldc), for C -= A B^T run with NEG: the
+    // accumulators start from C, so the epilogue only stores.
+    __device__ static void load_c(d4 (&acc)[4][4], const double *C, int64_t ldc)
+    {
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        const int wm = wave % WM, wn = wave / WM;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    acc[i][j][r] = C[row(i, lane, wm) + (int64_t)col(j, r, lane, wn) * ldc];
+    }
+    __device__ static void store_c(const d4 (&acc)[4][4], double *C, int64_t ldc)
+    {
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        const int wm = wave % WM, wn = wave / WM;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    C[row(i, lane, wm) + (int64_t)col(j, r, lane, wn) * ldc] = acc[i][j][r];
+    }
     // row / column of accumulator (i, j) element r inside the workgroup tile
     __device__ static int row(int i, int lane, int wm) { return wm * 64 + 16 * i + (lane & 15); }
     __device__ static int col(int j, int r, int lane, int wn) { return wn * 64 + 16 * j + (lane >> 4) + 4 * r; }
@@ -459,7 +493,7 @@ __global__ __launch_bounds__(256) void k_update_lower(double *C0, double *C1, in
                                                       const double *A0, const double *A1,
                                                       int64_t lda, const double *B, int64_t ldb)
 {
-    using TL = Tile<2, 2, false>;
+    using TL = Tile<2, 2, false, true>;
     __shared__ double lds[TL::LDS];
     const int64_t p = blockIdx.x >> 2;
     const int s = blockIdx.x & 3;
@@ -473,17 +507,36 @@ __global__ __launch_bounds__(256) void k_update_lower(double *C0, double *C1, in
     double *C = (blockIdx.y ? C1 : C0) + m0 + n0 * ldc;
     const double *A = (blockIdx.y ? A1 : A0) + m0;
     d4 acc[4][4];
+    TL::load_c(acc, C, ldc);
     TL::run(acc, A, lda, B + n0, ldb, NB, lds);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, wm = wave & 1, wn = wave >> 1;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                double *c = C + TL::row(i, lane, wm) + (int64_t)TL::col(j, r, lane, wn) * ldc;
-                *c = *c - acc[i][j][r];
-            }
+    TL::store_c(acc, C, ldc);
+}
+
+// C -= A * B^T on a rectangle of rows x NB (128 x 128 tiles): the next block
+// column of a trailing update (lookahead).  blockIdx.z selects the matrix.
+__global__ __launch_bounds__(256) void k_update_rect(double *C0, double *C1, int64_t ldc,
+                                                     const double *A0, const double *A1,
+                                                     int64_t lda, const double *B, int64_t ldb)
+{
+    using TL = Tile<2, 2, false, true>;
+    __shared__ double lds[TL::LDS];
+    const int64_t m0 = 128 * (int64_t)blockIdx.x, n0 = 128 * (int64_t)blockIdx.y;
+    double *C = (blockIdx.z ? C1 : C0) + m0 + n0 * ldc;
+    const double *A = (blockIdx.z ? A1 : A0) + m0;
+    d4 acc[4][4];
+    TL::load_c(acc, C, ldc);
+    TL::run(acc, A, lda, B + n0, ldb, NB, lds);
+    TL::store_c(acc, C, ldc);
+}
+
+void launch_update_rect(hipStream_t s, int nmat, double *C0, double *C1, int64_t ldc,
+                        const double *A0, const double *A1, int64_t lda, const double *B,
+                        int64_t ldb, int64_t rows)
+{
+    if (rows <= 0)
+        return;
+    hipLaunchKernelGGL(k_update_rect, dim3((unsigned)(rows / 128), NB / 128, nmat), dim3(256), 0,
+                       s, C0, C1, ldc, A0, A1, lda, B, ldb);
 }
 
 void launch_update_lower(hipStream_t s, int nmat, double *C0, double *C1, int64_t ldc,
@@ -505,6 +558,7 @@ __global__ __launch_bounds__(256) void k_panel(double *P, int64_t ld, const doub
     __shared__ double lds[TL::LDS];
     double *Pb = P + (int64_t)blockIdx.x * 64;
     d4 acc[4][4];
+    TL::zero(acc);
     TL::run(acc, Pb, ld, Linv, NB, NB, lds);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
@@ -537,6 +591,7 @@ __global__ __launch_bounds__(256) void k_diag_apply(double *S, int64_t ld, int64
     const int64_t c0 = (ct < half_tiles) ? 64 * ct : col_shift + 64 * (ct - half_tiles);
     double *Sb = S + krow + c0 * ld;
     d4 acc[4][4];
+    TL::zero(acc);
     TL::run(acc, Linv, NB, Sb, ld, NB, lds);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
@@ -562,24 +617,16 @@ __global__ __launch_bounds__(256) void k_update_nn(double *S, int64_t ld, const 
                                                    int64_t lda, int64_t r0, int64_t krow,
                                                    int64_t half_tiles, int64_t col_shift)
 {
-    using TL = Tile<2, 2, true>;
+    using TL = Tile<2, 2, true, true>;
     __shared__ double lds[TL::LDS];
     const int64_t ct = blockIdx.x;
     const int64_t c0 = (ct < half_tiles) ? 128 * ct : col_shift + 128 * (ct - half_tiles);
     const int64_t m0 = r0 + 128 * (int64_t)blockIdx.y;
-    d4 acc[4][4];
-    TL::run(acc, L + m0 + krow * lda, lda, S + krow + c0 * ld, ld, NB, lds);
     double *C = S + m0 + c0 * ld;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, wm = wave & 1, wn = wave >> 1;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                double *c = C + TL::row(i, lane, wm) + (int64_t)TL::col(j, r, lane, wn) * ld;
-                *c = *c - acc[i][j][r];
-            }
+    d4 acc[4][4];
+    TL::load_c(acc, C, ld);
+    TL::run(acc, L + m0 + krow * lda, lda, S + krow + c0 * ld, ld, NB, lds);
+    TL::store_c(acc, C, ld);
 }
 
 void launch_update_nn(hipStream_t s, double *S, int64_t ld, const double *L, int64_t lda,
@@ -624,6 +671,7 @@ __global__ __launch_bounds__(256) void k_panel_reduce(double *Xa, double *Xn, in
     d4 acc[4][4];
     double wa[4][4][4];
     double s[7] = {0, 0, 0, 0, 0, 0, 0}; // t_a, t_n, u_a, u_n, F_aa, F_an, F_nn
+    TL::zero(acc);
     TL::run(acc, Xa + m0 + kcol * ld, ld, Linv, NB, NB, lds);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -634,6 +682,7 @@ __global__ __launch_bounds__(256) void k_panel_reduce(double *Xa, double *Xn, in
                 wa[i][j][r] = acc[i][j][r];
                 Xa[m0 + TL::row(i, lane, 0) + (kcol + TL::col(j, r, lane, wave)) * ld] = acc[i][j][r];
             }
+    TL::zero(acc);
     TL::run(acc, Xn + m0 + kcol * ld, ld, Linv, NB, NB, lds);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
