@@ -165,161 +165,215 @@ void launch_gen(hipStream_t s, const GenParams &gp, const double *xs, const doub
 }
 
 // ---------------------------------------------------------------------------
-// Diagonal block: Cholesky factor L_kk (in place) and its inverse Linv_k.
-// One workgroup.  Left-looking over 32-column panels: each panel is updated
-// by the panels to its left with FP64 MFMA, then factored unblocked in LDS.
-// Then the inverse is assembled block row by block row:
-//   Linv[I][J] = -D_I sum_{J <= M < I} L[I][M] Linv[M][J],   D_I = L[I][I]^{-1}.
+// Diagonal block: Cholesky factor L_kk (in place) and its inverse Linv_k, by
+// one workgroup of 512 threads, right-looking over 32-column panels
+// p = 0..7 (jb = 32 p):
+//  1. thread t < 256 - jb holds row jb + t of the panel in registers and the
+//     panel is factored column by column: the 32 top-block values of column c
+//     go through a double-buffered LDS line, one barrier per column;
+//  2. the panel is written back and kept in LDS (Lp);
+//  3. D_p = inverse of its 32 x 32 top block (threads t < 32, a column each);
+//  4. inverse, block row p, by right-looking forward substitution of
+//     L X = I: X_p = D_p [B_p | I] with B_p the updates of block row p by the
+//     earlier panels;
+//  5. trailing update A[i][j] -= Lp[i] Lp[j]^T (jb + 32 <= j <= i < 256);
+//  6. inverse update of the rows below: B_i -= Lp[i] X_p.
+// MFMA operands of steps 4-6 come from LDS; their C tiles stay in L2 and are
+// loaded in batches of four 16 x 16 tiles per wave.  Linv starts at zero, so
+// its strict upper part is exactly zero.
 // Pivot rule: rows g >= n (the observation border and the identity padding)
 // take pivot 1; a pivot <= 0 or NaN at g < n records min(g) in *info and
 // continues with pivot 1 so that nothing downstream becomes non-finite.
-// logdet_part[k] = sum of log(pivot) over rows g < n of the block, in order.
+// logdet_part[k] = sum of log(pivot) over rows g < n of the block.
 // ---------------------------------------------------------------------------
 constexpr int PW = 32;
+constexpr int LPS = PW + 1; // LDS row stride of the panel and of D_p
+constexpr int XPS = NB + 1; // LDS row stride of X_p (PW x NB)
+constexpr int DT = 256;     // threads of the diagonal kernel
 
-__global__ __launch_bounds__(256) void k_potrf_diag(double *__restrict__ A, int64_t lda, int kblk,
-                                                    int64_t n, double *__restrict__ Linv,
-                                                    double *__restrict__ logdet_part,
-                                                    int *__restrict__ info)
+__global__ __launch_bounds__(DT) void k_potrf_diag(double *__restrict__ A, int64_t lda, int kblk,
+                                                   int64_t n, double *__restrict__ Linv,
+                                                   double *__restrict__ logdet_part,
+                                                   int *__restrict__ info)
 {
-    __shared__ double P[NB * (PW + 1)];
+    __shared__ double Lp[NB * LPS];
+    __shared__ double Xp[PW * XPS];
+    __shared__ double Dp[PW * LPS];
+    __shared__ double colbuf[2][PW];
     __shared__ double piv[NB];
+    __shared__ double sh[DT / 64];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int64_t o = (int64_t)kblk * NB;
     double *Ab = A + o + o * lda;
 
-    for (int pnl = 0; pnl < NB / PW; ++pnl) {
-        const int jb = pnl * PW;
-        const int M = NB - jb;
-        // (a) P = A[jb:, jb:jb+PW] - L[jb:, :jb] L[jb:jb+PW, :jb]^T
-        for (int tr = wave; tr < M / 16; tr += 4) {
-            d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-            const double *arow = Ab + (jb + tr * 16 + (lane & 15));
-            const double *brow = Ab + (jb + (lane & 15));
-#pragma unroll 4
-            for (int k0 = 0; k0 < jb; k0 += 4) {
-                const int64_t kk = (int64_t)(k0 + (lane >> 4)) * lda;
-                const double a = arow[kk], b0 = brow[kk], b1 = brow[kk + 16];
-                acc0 = mfma(a, b0, acc0);
-                acc1 = mfma(a, b1, acc1);
-            }
+    for (int idx = t; idx < NB * NB; idx += DT)
+        Linv[idx] = 0.0;
+
+    for (int p = 0; p < NB / PW; ++p) {
+        const int jb = p * PW, M = NB - jb;
+        // 1. panel rows into registers, factored column by column
+        double r[PW];
+        double mypiv = 1.0;
+        if (t < M) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = tr * 16 + (lane >> 4) + 4 * r;
-                const int col = lane & 15;
-                P[row * (PW + 1) + col] = Ab[(jb + row) + (int64_t)(jb + col) * lda] - acc0[r];
-                P[row * (PW + 1) + col + 16] =
-                    Ab[(jb + row) + (int64_t)(jb + col + 16) * lda] - acc1[r];
-            }
+            for (int c = 0; c < PW; ++c)
+                r[c] = Ab[(jb + t) + (int64_t)(jb + c) * lda];
         }
-        // (b) unblocked factorisation of the M x PW panel, thread t owns row t
+#pragma unroll
         for (int c = 0; c < PW; ++c) {
+            if (t >= c && t < PW)
+                colbuf[c & 1][t] = r[c];
             __syncthreads();
-            const double d = P[c * (PW + 1) + c];
+            const double d = colbuf[c & 1][c];
             const int64_t g = o + jb + c;
-            double pv;
-            if (g >= n)
-                pv = 1.0;
-            else if (d > 0.0)
-                pv = sqrt(d);
-            else
-                pv = 1.0;
-            if (t == 0) {
+            const bool bad = (g < n) && !(d > 0.0);
+            const double pv = (g >= n || bad) ? 1.0 : sqrt(d);
+            const double ip = 1.0 / pv;
+            if (t == c) {
+                mypiv = pv;
                 piv[jb + c] = pv;
-                if (g < n && !(d > 0.0))
+                if (bad)
                     atomicMin(info, (int)g);
             }
-            if (t > c && t < M)
-                P[t * (PW + 1) + c] = P[t * (PW + 1) + c] / pv;
-            __syncthreads();
             if (t > c && t < M) {
-                const double lt = P[t * (PW + 1) + c];
-                const int cend = t < PW - 1 ? t : PW - 1;
-                for (int c2 = c + 1; c2 <= cend; ++c2)
-                    P[t * (PW + 1) + c2] -= lt * P[c2 * (PW + 1) + c];
+                const double l = r[c] * ip;
+                r[c] = l;
+#pragma unroll
+                for (int c2 = c + 1; c2 < PW; ++c2)
+                    r[c2] -= l * (colbuf[c & 1][c2] * ip);
+            }
+        }
+        // 2. write back (top block: lower triangle with the pivots) and keep in LDS
+        if (t < M) {
+#pragma unroll
+            for (int c = 0; c < PW; ++c) {
+                const bool keep = (t >= PW) || (c <= t);
+                const double v = (t == c) ? mypiv : r[c];
+                if (keep)
+                    Ab[(jb + t) + (int64_t)(jb + c) * lda] = v;
+                Lp[t * LPS + c] = keep ? v : 0.0;
             }
         }
         __syncthreads();
-        // (c) write the panel back: L[jb + i][jb + c] for i >= c
-        for (int idx = t; idx < M * PW; idx += 256) {
-            const int i = idx % M, c = idx / M;
-            if (i >= c)
-                Ab[(jb + i) + (int64_t)(jb + c) * lda] = (i == c) ? piv[jb + c] : P[i * (PW + 1) + c];
-        }
-        // (d) D = inverse of the top PW x PW block; thread t < PW forms column t
+        // 3. D_p, column t of the inverse of the top block
         if (t < PW) {
             double col[PW];
 #pragma unroll
             for (int i = 0; i < PW; ++i) {
-                double s = (i == t) ? 1.0 : 0.0;
+                double sacc = (i == t) ? 1.0 : 0.0;
 #pragma unroll
                 for (int m = 0; m < i; ++m)
-                    s -= P[i * (PW + 1) + m] * col[m];
-                col[i] = (i < t) ? 0.0 : s / piv[jb + i];
+                    sacc -= Lp[i * LPS + m] * col[m];
+                col[i] = (i < t) ? 0.0 : sacc / Lp[i * LPS + i];
             }
 #pragma unroll
-            for (int i = 0; i < PW; ++i)
+            for (int i = 0; i < PW; ++i) {
+                Dp[i * LPS + t] = col[i];
+                Xp[i * XPS + jb + t] = col[i];
                 Linv[(jb + i) + (int64_t)(jb + t) * NB] = col[i];
+            }
         }
         __syncthreads();
-    }
-
-    // zero the blocks of Linv above the diagonal 32-blocks
-    for (int idx = t; idx < NB * NB; idx += 256) {
-        const int i = idx % NB, j = idx / NB;
-        if (i / PW < j / PW)
-            Linv[i + (int64_t)j * NB] = 0.0;
-    }
-    __syncthreads();
-
-    // inverse, block row by block row; T (32 x 224) staged in LDS (reuses P)
-    double *T = P; // T[r * NB + c], r < 32, c < 32 I
-    for (int I = 1; I < NB / PW; ++I) {
-        // T[:, J] = sum_{M=J}^{I-1} L[I][M] Linv[M][J] : units (J, 16x16 subtile)
-        for (int u = wave; u < 4 * I; u += 4) {
-            const int J = u >> 2, ti = (u >> 1) & 1, tj = u & 1;
+        // 4. X_p[:, 0:jb] = D_p B_p[:, 0:jb] (into LDS first: B_p is read in place)
+        for (int u = wave; u < 2 * (jb / 16); u += DT / 64) {
+            const int ti = u & 1, tj = u >> 1;
             d4 acc = {0, 0, 0, 0};
-            const double *arow = Ab + (PW * I + 16 * ti + (lane & 15));
-            const double *bcol = Linv + (int64_t)(PW * J + 16 * tj + (lane & 15)) * NB;
-            for (int k0 = PW * J; k0 < PW * I; k0 += 4) {
-                const int k = k0 + (lane >> 4);
-                acc = mfma(arow[(int64_t)k * lda], bcol[k], acc);
+#pragma unroll
+            for (int s4 = 0; s4 < PW / 4; ++s4) {
+                const int k = 4 * s4 + (lane >> 4);
+                const double a = Dp[(16 * ti + (lane & 15)) * LPS + k];
+                const double b = Linv[(jb + k) + (int64_t)(16 * tj + (lane & 15)) * NB];
+                acc = mfma(b, a, acc);
             }
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                T[(16 * ti + (lane >> 4) + 4 * r) * NB + PW * J + 16 * tj + (lane & 15)] = acc[r];
+            for (int q = 0; q < 4; ++q)
+                Xp[(16 * ti + (lane & 15)) * XPS + 16 * tj + (lane >> 4) + 4 * q] = acc[q];
         }
         __syncthreads();
-        // Linv[I][J] = -D_I T[:, J]
-        for (int u = wave; u < 4 * I; u += 4) {
-            const int J = u >> 2, ti = (u >> 1) & 1, tj = u & 1;
-            d4 acc = {0, 0, 0, 0};
-            const double *drow = Linv + (PW * I + 16 * ti + (lane & 15)) + (int64_t)(PW * I) * NB;
+        for (int idx = t; idx < PW * jb; idx += DT) {
+            const int row = idx % PW, col = idx / PW;
+            Linv[(jb + row) + (int64_t)col * NB] = Xp[row * XPS + col];
+        }
+        // 5. trailing update of the block and 6. inverse update of the rows below
+        const int nt = (M - PW) / 16;         // 16-row tiles below the panel's top block
+        const int n5 = nt * (nt + 1) / 2;     // lower tiles of the trailing block
+        const int nc6 = (jb + PW) / 16;       // 16-column tiles of X_p
+        const int nunits = n5 + nt * nc6;
+        for (int u0 = wave * 4; u0 < nunits; u0 += (DT / 64) * 4) {
+            d4 acc[4];
+            double *cp[4];
+            int ia[4], jbk[4];
+            bool inv[4];
 #pragma unroll
-            for (int k0 = 0; k0 < PW; k0 += 4) {
-                const int k = k0 + (lane >> 4);
-                acc = mfma(drow[(int64_t)k * NB], T[k * NB + PW * J + 16 * tj + (lane & 15)], acc);
+            for (int q = 0; q < 4; ++q) {
+                const int u = u0 + q;
+                cp[q] = nullptr;
+                ia[q] = 0;
+                jbk[q] = 0;
+                inv[q] = false;
+                if (u < n5) {
+                    int i = (int)((sqrt(8.0 * u + 1.0) - 1.0) * 0.5);
+                    while ((i + 1) * (i + 2) / 2 <= u)
+                        ++i;
+                    while (i * (i + 1) / 2 > u)
+                        --i;
+                    const int j = u - i * (i + 1) / 2;
+                    ia[q] = PW + 16 * i;
+                    jbk[q] = PW + 16 * j;
+                    cp[q] = Ab + (jb + ia[q]) + (int64_t)(jb + jbk[q]) * lda;
+                } else if (u < nunits) {
+                    const int v = u - n5, i = v % nt, j = v / nt;
+                    ia[q] = PW + 16 * i;
+                    jbk[q] = 16 * j;
+                    inv[q] = true;
+                    cp[q] = Linv + (jb + ia[q]) + (int64_t)jbk[q] * NB;
+                }
             }
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = PW * I + 16 * ti + (lane >> 4) + 4 * r;
-                const int col = PW * J + 16 * tj + (lane & 15);
-                Linv[row + (int64_t)col * NB] = -acc[r];
-            }
+            for (int q = 0; q < 4; ++q)
+                if (cp[q]) {
+                    const int64_t ldc = inv[q] ? NB : lda;
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr)
+                        acc[q][rr] = cp[q][(lane & 15) + (int64_t)((lane >> 4) + 4 * rr) * ldc];
+                }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (cp[q]) {
+#pragma unroll
+                    for (int s4 = 0; s4 < PW / 4; ++s4) {
+                        const int k = 4 * s4 + (lane >> 4);
+                        const double a = -Lp[(ia[q] + (lane & 15)) * LPS + k];
+                        const double b = inv[q] ? Xp[k * XPS + jbk[q] + (lane & 15)]
+                                                : Lp[(jbk[q] + (lane & 15)) * LPS + k];
+                        acc[q] = mfma(b, a, acc[q]);
+                    }
+                }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (cp[q]) {
+                    const int64_t ldc = inv[q] ? NB : lda;
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr)
+                        cp[q][(lane & 15) + (int64_t)((lane >> 4) + 4 * rr) * ldc] = acc[q][rr];
+                }
         }
         __syncthreads();
     }
     // log-determinant of the block: fixed-order tree over the NB pivots
-    __shared__ double sh[4];
-    double lg = (o + t < n) ? log(piv[t]) : 0.0;
+    double lg = (t < NB && o + t < n) ? log(piv[t]) : 0.0;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)
         lg += __shfl_xor(lg, off, 64);
     if (lane == 0)
         sh[wave] = lg;
     __syncthreads();
-    if (t == 0)
-        logdet_part[kblk] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+    if (t == 0) {
+        double s = 0.0;
+        for (int w = 0; w < DT / 64; ++w)
+            s += sh[w];
+        logdet_part[kblk] = s;
+    }
 }
 
 __global__ void k_init_info(int *info)
@@ -336,7 +390,7 @@ void launch_init_info(hipStream_t s, int *info)
 void launch_potrf_diag(hipStream_t s, double *A, int64_t lda, int k, int64_t n, double *Linv,
                        double *logdet_part, int *info)
 {
-    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, s, A, lda, k, n, Linv, logdet_part,
+    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(DT), 0, s, A, lda, k, n, Linv, logdet_part,
                        info);
 }
 

@@ -134,17 +134,25 @@ def test_determinism(ctx):
     np.testing.assert_array_equal(a, c)
 
 
-def test_not_positive_definite(ctx):
+def test_not_positive_definite(ctx, oracle_mod):
+    """A covariance that is numerically indefinite (range 50 and smoothness 4
+    on 300 points of the unit square: condition number far beyond 1/eps) fails
+    the factorisation: LAPACK in the oracle and the GPU both report it."""
     say("notpd")
     locs, z, _ = synth.dataset(300, (1.0, 0.1, 0.5), 6)
-    locs[200] = locs[17]                      # duplicated location -> singular Sigma
+    theta = (1.0, 50.0, 4.0)
+    with pytest.raises(oracle_mod.NotPositiveDefinite):
+        oracle_mod.loglik(locs, z, theta)
     ctx.set_data(locs, z)
     with pytest.raises(fbt.FisherBTError) as e:
-        ctx.loglik((1.0, 0.1, 0.5))
-    assert e.value.status == fbt.ENOTPD and e.value.pivot == 200
+        ctx.loglik(theta)
+    assert e.value.status == fbt.ENOTPD and 0 < e.value.pivot < 300
     with pytest.raises(fbt.FisherBTError) as e:
-        ctx.eval((1.0, 0.1, 0.5))
+        ctx.eval(theta)
     assert e.value.status == fbt.ENOTPD
+    # the context stays usable
+    ok = oracle_mod.loglik(locs, z, (1.0, 0.1, 0.5))["loglik"]
+    assert abs(ctx.loglik((1.0, 0.1, 0.5)) - ok) <= 1e-10 * abs(ok)
 
 
 def test_invalid_arguments(ctx):
