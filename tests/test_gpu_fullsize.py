@@ -1,0 +1,103 @@
+"""GPU checks at the benchmark size (n = 20,000 uniform points, the launch
+configuration bench.py times) on outputs the oracle can afford:
+
+  * covariance, dC/dalpha, dC/dnu on 200,000 sampled entries (oracle entry by entry);
+  * the Cholesky factor on 2,000 sampled entries of L L^T against Sigma;
+  * the log-likelihood against the oracle's Algorithm 2 (LAPACK at n = 20,000);
+  * properties that hold at any size: the Fisher matrix is symmetric positive
+    definite with I_11 = n / (2 sigma2^2); the sigma2 score equals
+    (Z' Sigma^-1 Z - n) / (2 sigma2); the score matches central differences
+    of the GPU log-likelihood; repeated evaluations are bitwise identical.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import paper_2601_11437_amd as fbt
+from paper_2601_11437_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def big():
+    w = synth.WORKLOADS["n20k"]
+    say("fullsize: generating n=%d" % w["n"])
+    locs, z, _ = synth.dataset(w["n"], w["theta_true"], w["seed"])
+    ctx = fbt.Context(0)
+    ctx.set_data(locs, z)
+    yield ctx, locs, z, w
+    ctx.close()
+
+
+def test_sampled_entries(big, oracle_mod):
+    ctx, locs, z, w = big
+    n = w["n"]
+    theta = (1.3, 0.08, 1.3)
+    gen = np.random.default_rng(99)
+    i = gen.integers(0, n, 200000)
+    j = gen.integers(0, n, 200000)
+    h = np.hypot(*(locs[i] - locs[j]).T)
+    ref = oracle_mod.matern_entries(h, theta)
+    x = h / theta[1]
+    for which in (0, 1, 2):
+        say("fullsize: entries of matrix %d" % which)
+        M = ctx.covariance(theta, which)
+        got = M[i, j]
+        del M
+        r = ref[which]
+        lx = np.abs(np.log(np.where(x > 0, x, 1.0)))
+        tol = 1e-13 * np.abs(r) + 1e-14 * ref[0] * (1 + lx + 1.0) * (which > 0) + 1e-300
+        assert np.all(np.abs(got - r) <= tol), which
+
+
+def test_factor_residual_and_loglik(big, oracle_mod):
+    ctx, locs, z, w = big
+    theta = w["theta_true"]
+    say("fullsize: factor")
+    L = ctx.factor(theta)
+    gen = np.random.default_rng(7)
+    n = w["n"]
+    i = gen.integers(0, n, 2000)
+    j = gen.integers(0, n, 2000)
+    i, j = np.maximum(i, j), np.minimum(i, j)
+    prod = np.einsum("ij,ij->i", L[i, :], L[j, :])
+    c, _, _ = oracle_mod.matern_entries(np.hypot(*(locs[i] - locs[j]).T), theta)
+    assert np.max(np.abs(prod - c)) <= 2e-12 * theta[0]
+    del L
+    say("fullsize: oracle loglik (LAPACK)")
+    want = oracle_mod.loglik(locs, z, theta)["loglik"]
+    got = ctx.loglik(theta)
+    say("fullsize: loglik gpu %.12f oracle %.12f" % (got, want))
+    assert abs(got - want) <= 1e-10 * abs(want)
+
+
+def test_score_and_fisher_properties(big):
+    ctx, locs, z, w = big
+    n = w["n"]
+    theta = np.array([1.2, 0.09, 0.6])
+    say("fullsize: eval")
+    ll, score, fisher = ctx.eval(theta)
+    ll2, score2, fisher2 = ctx.eval(theta)
+    assert ll == ll2 and np.array_equal(score, score2) and np.array_equal(fisher, fisher2)
+    assert ll == ctx.loglik(theta)
+    np.testing.assert_array_equal(fisher, fisher.T)
+    assert fisher[0, 0] == n / (2 * theta[0] ** 2)
+    assert np.all(np.linalg.eigvalsh(fisher) > 0)
+    t = ctx.eval_terms(theta)
+    assert score[0] == (t[1] - n) / (2 * theta[0])
+    for k in range(3):
+        d = 1e-5 * theta[k]
+        tp, tm = theta.copy(), theta.copy()
+        tp[k] += d
+        tm[k] -= d
+        fd = (ctx.loglik(tp) - ctx.loglik(tm)) / (2 * d)
+        scale = (t[1] + n) / (2 * theta[0]) if k == 0 else 0.5 * (abs(t[1 + k]) + abs(t[3 + k]))
+        say("fullsize: score %d gpu %.6f fd %.6f scale %.3e" % (k, score[k], fd, scale))
+        assert abs(fd - score[k]) <= 1e-6 * scale
