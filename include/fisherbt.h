@@ -20,7 +20,8 @@
  *   - One context per host thread; contexts share nothing.
  *   - Errors are negative.  FBT_ENOTPD is recoverable (Sigma(theta) is not
  *     numerically positive definite); FBT_EDEVICE and FBT_ENOMEM are not.
- *   - All arithmetic on the evaluation path is IEEE FP64.
+ *   - All arithmetic on the evaluation path is IEEE FP64 unless the context
+ *     selects FBT_MIXED_FP32 (see fbt_precision).
  */
 #ifndef FISHERBT_H
 #define FISHERBT_H
@@ -44,11 +45,25 @@ typedef enum {
     FBT_ENODATA = -7     /* no data set on the context */
 } fbt_status;
 
+/* Arithmetic of the evaluation path.
+ * FBT_FP64: everything in IEEE FP64 (the default).
+ * FBT_MIXED_FP32: the trailing updates of the two block solves that form
+ *   W_i = L^{-1} Sigma_i L^{-T} (the trace terms of the score and Fisher
+ *   information, about 8/9 of the flops of fbt_eval) multiply on FP32 MFMA
+ *   with FP32 accumulation.  The Cholesky factorisation, log-determinant and
+ *   quadratic form (so the log-likelihood and every line-search test), the
+ *   Bessel terms, diagonal blocks, panel solves and all reductions stay FP64:
+ *   fbt_loglik is unchanged and fbt_eval returns the FP64 log-likelihood.
+ * FBT_MIXED_FP32_ALL: the Cholesky trailing updates in FP32 as well.  The
+ *   log-likelihood then carries FP32 rounding amplified by the conditioning
+ *   of Sigma, and the factorisation can fail for ill-conditioned Sigma. */
+typedef enum { FBT_FP64 = 0, FBT_MIXED_FP32 = 1, FBT_MIXED_FP32_ALL = 2 } fbt_precision;
+
 typedef struct {
-    int32_t device;   /* HIP device ordinal */
-    int32_t tile;     /* block size of the tiled factorisation; 0 = default (256); only 256 */
-    int32_t reserved; /* must be 0 */
-    void *hip_stream; /* hipStream_t to order work on; NULL = the library creates its own */
+    int32_t device;    /* HIP device ordinal */
+    int32_t tile;      /* block size of the tiled factorisation; 0 = default (256); only 256 */
+    int32_t precision; /* fbt_precision */
+    void *hip_stream;  /* hipStream_t to order work on; NULL = the library creates its own */
 } fbt_config;
 
 /* Create a context on cfg->device.  On success *out owns a stream (unless one
@@ -58,6 +73,9 @@ fbt_status fbt_create(const fbt_config *cfg, fbt_ctx **out);
 
 /* Release every resource of ctx.  NULL is a no-op. */
 void fbt_destroy(fbt_ctx *ctx);
+
+/* Switch the arithmetic of later evaluations (fbt_precision).  Errors: FBT_EINVAL. */
+fbt_status fbt_set_precision(fbt_ctx *ctx, int32_t precision);
 
 /* Observations (Section 2.1): n locations as an n x 2 row-major array
  * (x_i, y_i) and the n observations Z.  Both host arrays are copied; the

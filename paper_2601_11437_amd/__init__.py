@@ -50,7 +50,10 @@ class FitResult(ctypes.Structure):
 
 
 class Config(ctypes.Structure):
-    _fields_ = [("device", _i32), ("tile", _i32), ("reserved", _i32), ("hip_stream", _p)]
+    _fields_ = [("device", _i32), ("tile", _i32), ("precision", _i32), ("hip_stream", _p)]
+
+
+FP64, MIXED_FP32, MIXED_FP32_ALL = 0, 1, 2
 
 
 class Evaluator(ctypes.Structure):
@@ -61,6 +64,7 @@ class Evaluator(ctypes.Structure):
 SIGNATURES = {
     "fbt_create": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.POINTER(_p)]),
     "fbt_destroy": (None, [_p]),
+    "fbt_set_precision": (ctypes.c_int, [_p, _i32]),
     "fbt_set_data": (ctypes.c_int, [_p, _i64, _p, _p]),
     "fbt_set_data_device": (ctypes.c_int, [_p, _i64, _p, _p]),
     "fbt_loglik": (ctypes.c_int, [_p, _p, _p]),
@@ -210,8 +214,8 @@ def fit_with(loglik, evaluate, **opts) -> dict:
 class Context:
     """One device context: data on the GPU and the evaluation calls."""
 
-    def __init__(self, device: int = 0, stream=None):
-        cfg = Config(int(device), 0, 0, None)
+    def __init__(self, device: int = 0, stream=None, precision: int = FP64):
+        cfg = Config(int(device), 0, int(precision), None)
         if stream is not None:
             cfg.hip_stream = int(getattr(stream, "cuda_stream", stream))
         h = _p()
@@ -303,6 +307,11 @@ class Context:
         out = _result(r)
         out["status"] = st
         return out
+
+    def set_precision(self, precision: int):
+        """FP64 (0), MIXED_FP32 (1: solve updates in FP32) or MIXED_FP32_ALL
+        (2: Cholesky updates too) for the following evaluations."""
+        self._check(lib().fbt_set_precision(self._h, int(precision)))
 
     def set_timing(self, enable: bool):
         self._check(lib().fbt_set_timing(self._h, 1 if enable else 0))

@@ -34,6 +34,7 @@ struct fbt_ctx {
     hipStream_t stream2 = nullptr; // s1: bulk trailing updates (lookahead), joined back to s0
     hipEvent_t evP = nullptr, evB = nullptr;
     bool own_stream = false;
+    int precision = FBT_FP64; // see fbt_precision
     std::string err;
     int64_t notpd = -1;
 
@@ -269,6 +270,7 @@ fbt_status factorize(fbt_ctx *c, const double *th, int mode)
     hipStream_t s0 = c->stream, s1 = c->stream2;
     double *A = c->A;
     const double dNB = NB;
+    const int mix = c->precision == FBT_MIXED_FP32_ALL; // Cholesky updates in FP32
     auto Lk = [&](int k) { return c->Linv + (size_t)k * NB * NB; };
     launch_init_info(s0, c->info);
     TIMED(c, s0, KC_GEN, 0.0, launch_gen(s0, gp, c->x, c->y, c->z, c->tab, A, c->S2,
@@ -286,7 +288,7 @@ fbt_status factorize(fbt_ctx *c, const double *th, int mode)
         HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
         TIMED(c, s0, KC_SYRK, std::max(0.0, 2.0 * m1 * dNB * dNB - dNB * dNB * dNB),
               launch_update_rect(s0, 1, A + r1 + r1 * ld, nullptr, ld, A + r1 + kc * ld, nullptr,
-                                 ld, A + r1 + kc * ld, ld, npad - r1));
+                                 ld, A + r1 + kc * ld, ld, npad - r1, mix));
         TIMED(c, s0, KC_DIAG, 2.0 * dNB * dNB * dNB / 3.0,
               launch_potrf_diag(s0, A, ld, k + 1, n, Lk(k + 1), c->logdet, c->info));
         if (k + 2 < T)
@@ -296,7 +298,7 @@ fbt_status factorize(fbt_ctx *c, const double *th, int mode)
         if (k + 2 < T)
             TIMED(c, s1, KC_SYRK, m2 * m2 * dNB,
                   launch_update_lower(s1, 1, A + r2 + r2 * ld, nullptr, ld, A + r2 + kc * ld,
-                                      nullptr, ld, A + r2 + kc * ld, ld, T - k - 2));
+                                      nullptr, ld, A + r2 + kc * ld, ld, T - k - 2, mix));
         HIPCHK(c, hipEventRecord(c->evB, s1));
         HIPCHK(c, hipEventRecord(c->evP, s0));
     }
@@ -350,6 +352,7 @@ fbt_status derivative_terms(fbt_ctx *c, const double *th, double terms[9])
     const int T = c->T;
     double *Sa = c->S2, *Sn = c->S2 + npad * ld, *A = c->A;
     const double dn = (double)n, dNB = NB;
+    const int mix = c->precision != FBT_FP64; // solve updates in FP32
     auto Lk = [&](int k) { return c->Linv + (size_t)k * NB * NB; };
 
     // left solve X = L'^{-1} [Sigma_alpha' | Sigma_nu'] on columns [0, ncols) of each half
@@ -363,13 +366,13 @@ fbt_status derivative_terms(fbt_ctx *c, const double *th, double terms[9])
         const double m2 = std::max<int64_t>(0, n - r2);
         HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
         TIMED(c, s0, KC_LUPD, 2.0 * m1 * dNB * 2.0 * dn,
-              launch_update_nn(s0, c->S2, ld, A, ld, r1, kc, NB, ncols, npad));
+              launch_update_nn(s0, c->S2, ld, A, ld, r1, kc, NB, ncols, npad, mix));
         TIMED(c, s0, KC_LAPPLY, 2.0 * dn * dNB * dNB,
               launch_diag_apply(s0, c->S2, ld, r1, Lk(k + 1), ncols, npad));
         HIPCHK(c, hipStreamWaitEvent(s1, c->evP, 0));
         if (k + 2 < T)
             TIMED(c, s1, KC_LUPD, 2.0 * m2 * dNB * 2.0 * dn,
-                  launch_update_nn(s1, c->S2, ld, A, ld, r2, kc, npad - r2, ncols, npad));
+                  launch_update_nn(s1, c->S2, ld, A, ld, r2, kc, npad - r2, ncols, npad, mix));
         HIPCHK(c, hipEventRecord(c->evB, s1));
         HIPCHK(c, hipEventRecord(c->evP, s0));
     }
@@ -389,7 +392,7 @@ fbt_status derivative_terms(fbt_ctx *c, const double *th, double terms[9])
         TIMED(c, s0, KC_RUPD, 2.0 * 2.0 * m1 * dNB * dNB,
               launch_update_rect(s0, 2, Sa + r1 + r1 * ld, Sn + r1 + r1 * ld, ld,
                                  Sa + r1 + kc * ld, Sn + r1 + kc * ld, ld, A + r1 + kc * ld, ld,
-                                 npad - r1));
+                                 npad - r1, mix));
         TIMED(c, s0, KC_RPANEL, 2.0 * 2.0 * m1 * dNB * dNB,
               launch_panel_reduce(s0, Sa, Sn, ld, r1, r1, npad - r1, Lk(k + 1), n,
                                   c->partials + 8 * groups));
@@ -399,7 +402,7 @@ fbt_status derivative_terms(fbt_ctx *c, const double *th, double terms[9])
             TIMED(c, s1, KC_RUPD, 2.0 * m2 * m2 * dNB,
                   launch_update_lower(s1, 2, Sa + r2 + r2 * ld, Sn + r2 + r2 * ld, ld,
                                       Sa + r2 + kc * ld, Sn + r2 + kc * ld, ld, A + r2 + kc * ld,
-                                      ld, T - k - 2));
+                                      ld, T - k - 2, mix));
         HIPCHK(c, hipEventRecord(c->evB, s1));
         HIPCHK(c, hipEventRecord(c->evP, s0));
     }
@@ -511,7 +514,8 @@ fbt_status fbt_create(const fbt_config *cfg, fbt_ctx **out)
     if (!cfg || !out)
         return FBT_EINVAL;
     *out = nullptr;
-    if (!(cfg->tile == 0 || cfg->tile == NB) || cfg->reserved != 0)
+    if (!(cfg->tile == 0 || cfg->tile == NB) ||
+        cfg->precision < FBT_FP64 || cfg->precision > FBT_MIXED_FP32_ALL)
         return FBT_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev)
@@ -524,6 +528,7 @@ fbt_status fbt_create(const fbt_config *cfg, fbt_ctx **out)
         return FBT_EDEVICE;
     fbt_ctx *c = new fbt_ctx();
     c->device = cfg->device;
+    c->precision = cfg->precision;
     if (cfg->hip_stream) {
         c->stream = (hipStream_t)cfg->hip_stream;
     } else {
@@ -681,6 +686,16 @@ fbt_status fbt_factor(fbt_ctx *ctx, const double theta[3], double *out, int64_t 
     for (int64_t j = 0; j < n; ++j)
         for (int64_t i = 0; i < j; ++i)
             out[i + j * ld] = 0.0;
+    return FBT_OK;
+}
+
+fbt_status fbt_set_precision(fbt_ctx *ctx, int32_t precision)
+{
+    if (!ctx || precision < FBT_FP64 || precision > FBT_MIXED_FP32_ALL)
+        return FBT_EINVAL;
+    if (precision != ctx->precision)
+        ctx->factor_valid = false;
+    ctx->precision = precision;
     return FBT_OK;
 }
 

@@ -540,15 +540,134 @@ template <int WM, int WN, bool BKC, bool NEG = false> struct Tile {
     __device__ static int col(int j, int r, int lane, int wn) { return wn * 64 + 16 * j + (lane >> 4) + 4 * r; }
 };
 
+// FP32-compute variant for the mixed-precision form: FP64 operands are
+// rounded to FP32 when staged into LDS, multiplied on v_mfma_f32_16x16x4_f32
+// with FP32 accumulation, and the product is subtracted from the FP64 C tile.
+// FP32 MFMA output layout: lane l holds D[4 (l/16) + r][l%16], so with the
+// B fragment first lane l holds tile entry (16 i + l%16, 16 j + 4 (l/16) + r).
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <int WM, int WN, bool BKC> struct TileF {
+    static constexpr int BM = 64 * WM, BN = 64 * WN, KC = 32;
+    static constexpr int LSA = BM + 8, LSB = BN + 8; // padded LDS rows (floats)
+    static constexpr int STAGE = KC * (LSA + LSB);
+    static constexpr int LDS = 2 * STAGE;            // floats
+    static constexpr int NA = BM * KC / 512;          // double2 loads per thread
+    static constexpr int NBL = BN * KC / 512;
+
+    __device__ static void load(double2 *ra, double2 *rb, const double *A, int64_t lda,
+                                const double *B, int64_t ldb, int k0)
+    {
+        const int t = threadIdx.x;
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const int q = t + 256 * i, m2 = q % (BM / 2), k = q / (BM / 2);
+            ra[i] = *(const double2 *)(A + 2 * m2 + (int64_t)(k0 + k) * lda);
+        }
+#pragma unroll
+        for (int i = 0; i < NBL; ++i) {
+            const int q = t + 256 * i;
+            if (!BKC) {
+                const int n2 = q % (BN / 2), k = q / (BN / 2);
+                rb[i] = *(const double2 *)(B + 2 * n2 + (int64_t)(k0 + k) * ldb);
+            } else {
+                const int k2 = q % (KC / 2), nn = q / (KC / 2);
+                rb[i] = *(const double2 *)(B + (k0 + 2 * k2) + (int64_t)nn * ldb);
+            }
+        }
+    }
+    __device__ static void store(const double2 *ra, const double2 *rb, float *st)
+    {
+        const int t = threadIdx.x;
+        float *As = st, *Bs = st + KC * LSA;
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const int q = t + 256 * i, m2 = q % (BM / 2), k = q / (BM / 2);
+            *(float2 *)(As + k * LSA + 2 * m2) = make_float2((float)ra[i].x, (float)ra[i].y);
+        }
+#pragma unroll
+        for (int i = 0; i < NBL; ++i) {
+            const int q = t + 256 * i;
+            if (!BKC) {
+                const int n2 = q % (BN / 2), k = q / (BN / 2);
+                *(float2 *)(Bs + k * LSB + 2 * n2) = make_float2((float)rb[i].x, (float)rb[i].y);
+            } else {
+                const int k2 = q % (KC / 2), nn = q / (KC / 2);
+                Bs[(2 * k2) * LSB + nn] = (float)rb[i].x;
+                Bs[(2 * k2 + 1) * LSB + nn] = (float)rb[i].y;
+            }
+        }
+    }
+    __device__ static void compute(f4 (&acc)[4][4], const float *st, int wm, int wn, int lane)
+    {
+        const float *As = st + wm * 64 + (lane & 15);
+        const float *Bs = st + KC * LSA + wn * 64 + (lane & 15);
+#pragma unroll
+        for (int s = 0; s < KC / 4; ++s) {
+            const int kk = 4 * s + (lane >> 4);
+            float a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                a[i] = As[kk * LSA + 16 * i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                b[j] = Bs[kk * LSB + 16 * j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[j], a[i], acc[i][j], 0, 0, 0);
+        }
+    }
+    // C(BM x BN, FP64) -= A(BM x K) * B(BN x K)^T computed in FP32
+    __device__ static void update(double *C, int64_t ldc, const double *A, int64_t lda,
+                                  const double *B, int64_t ldb, int K, float *lds)
+    {
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        const int wm = wave % WM, wn = wave / WM;
+        f4 acc[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
+        double2 ra[NA], rb[NBL];
+        load(ra, rb, A, lda, B, ldb, 0);
+        store(ra, rb, lds);
+        __syncthreads();
+        const int nch = K / KC;
+        for (int c = 0; c < nch; ++c) {
+            if (c + 1 < nch)
+                load(ra, rb, A, lda, B, ldb, (c + 1) * KC);
+            compute(acc, lds + (c & 1) * STAGE, wm, wn, lane);
+            if (c + 1 < nch)
+                store(ra, rb, lds + ((c + 1) & 1) * STAGE);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    double *c = C + (wm * 64 + 16 * i + (lane & 15)) +
+                                (int64_t)(wn * 64 + 16 * j + 4 * (lane >> 4) + r) * ldc;
+                    *c = *c - (double)acc[i][j][r];
+                }
+    }
+};
+
 // C -= A * B^T over the block-lower tiles of a trailing matrix of nblk x nblk
 // NB-blocks (128 x 128 tiles; both 128-tiles above the diagonal inside a
 // diagonal NB-block are included).  blockIdx.y selects (C0, A0) or (C1, A1).
+template <bool MIX>
 __global__ __launch_bounds__(256) void k_update_lower(double *C0, double *C1, int64_t ldc,
                                                       const double *A0, const double *A1,
                                                       int64_t lda, const double *B, int64_t ldb)
 {
     using TL = Tile<2, 2, false, true>;
-    __shared__ double lds[TL::LDS];
+    using TF = TileF<2, 2, false>;
+    __shared__ double lds[MIX ? (TF::LDS + 1) / 2 : TL::LDS];
     const int64_t p = blockIdx.x >> 2;
     const int s = blockIdx.x & 3;
     int64_t I = (int64_t)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
@@ -560,48 +679,64 @@ __global__ __launch_bounds__(256) void k_update_lower(double *C0, double *C1, in
     const int64_t m0 = I * NB + 128 * (s >> 1), n0 = J * NB + 128 * (s & 1);
     double *C = (blockIdx.y ? C1 : C0) + m0 + n0 * ldc;
     const double *A = (blockIdx.y ? A1 : A0) + m0;
-    d4 acc[4][4];
-    TL::load_c(acc, C, ldc);
-    TL::run(acc, A, lda, B + n0, ldb, NB, lds);
-    TL::store_c(acc, C, ldc);
+    if constexpr (MIX) {
+        TF::update(C, ldc, A, lda, B + n0, ldb, NB, (float *)lds);
+    } else {
+        d4 acc[4][4];
+        TL::load_c(acc, C, ldc);
+        TL::run(acc, A, lda, B + n0, ldb, NB, lds);
+        TL::store_c(acc, C, ldc);
+    }
 }
 
 // C -= A * B^T on a rectangle of rows x NB (128 x 128 tiles): the next block
 // column of a trailing update (lookahead).  blockIdx.z selects the matrix.
+template <bool MIX>
 __global__ __launch_bounds__(256) void k_update_rect(double *C0, double *C1, int64_t ldc,
                                                      const double *A0, const double *A1,
                                                      int64_t lda, const double *B, int64_t ldb)
 {
     using TL = Tile<2, 2, false, true>;
-    __shared__ double lds[TL::LDS];
+    using TF = TileF<2, 2, false>;
+    __shared__ double lds[MIX ? (TF::LDS + 1) / 2 : TL::LDS];
     const int64_t m0 = 128 * (int64_t)blockIdx.x, n0 = 128 * (int64_t)blockIdx.y;
     double *C = (blockIdx.z ? C1 : C0) + m0 + n0 * ldc;
     const double *A = (blockIdx.z ? A1 : A0) + m0;
-    d4 acc[4][4];
-    TL::load_c(acc, C, ldc);
-    TL::run(acc, A, lda, B + n0, ldb, NB, lds);
-    TL::store_c(acc, C, ldc);
+    if constexpr (MIX) {
+        TF::update(C, ldc, A, lda, B + n0, ldb, NB, (float *)lds);
+    } else {
+        d4 acc[4][4];
+        TL::load_c(acc, C, ldc);
+        TL::run(acc, A, lda, B + n0, ldb, NB, lds);
+        TL::store_c(acc, C, ldc);
+    }
 }
 
 void launch_update_rect(hipStream_t s, int nmat, double *C0, double *C1, int64_t ldc,
                         const double *A0, const double *A1, int64_t lda, const double *B,
-                        int64_t ldb, int64_t rows)
+                        int64_t ldb, int64_t rows, int mixed)
 {
     if (rows <= 0)
         return;
-    hipLaunchKernelGGL(k_update_rect, dim3((unsigned)(rows / 128), NB / 128, nmat), dim3(256), 0,
-                       s, C0, C1, ldc, A0, A1, lda, B, ldb);
+    const dim3 g((unsigned)(rows / 128), NB / 128, nmat);
+    if (mixed)
+        hipLaunchKernelGGL(k_update_rect<true>, g, dim3(256), 0, s, C0, C1, ldc, A0, A1, lda, B, ldb);
+    else
+        hipLaunchKernelGGL(k_update_rect<false>, g, dim3(256), 0, s, C0, C1, ldc, A0, A1, lda, B, ldb);
 }
 
 void launch_update_lower(hipStream_t s, int nmat, double *C0, double *C1, int64_t ldc,
                          const double *A0, const double *A1, int64_t lda, const double *B,
-                         int64_t ldb, int nblk)
+                         int64_t ldb, int nblk, int mixed)
 {
     if (nblk <= 0)
         return;
     const int64_t pairs = (int64_t)nblk * (nblk + 1) / 2;
-    hipLaunchKernelGGL(k_update_lower, dim3((unsigned)(4 * pairs), nmat), dim3(256), 0, s, C0, C1,
-                       ldc, A0, A1, lda, B, ldb);
+    const dim3 g((unsigned)(4 * pairs), nmat);
+    if (mixed)
+        hipLaunchKernelGGL(k_update_lower<true>, g, dim3(256), 0, s, C0, C1, ldc, A0, A1, lda, B, ldb);
+    else
+        hipLaunchKernelGGL(k_update_lower<false>, g, dim3(256), 0, s, C0, C1, ldc, A0, A1, lda, B, ldb);
 }
 
 // Panel solve of the factorisation: P (rows x NB, in place) = P Linv^T.
@@ -667,30 +802,42 @@ void launch_diag_apply(hipStream_t s, double *S, int64_t ld, int64_t krow, const
 
 // Left solve, update below the diagonal block:
 // S[r0 + 128 y, cols] -= L[r0 + 128 y, krow:krow+NB] * S[krow:krow+NB, cols].
+template <bool MIX>
 __global__ __launch_bounds__(256) void k_update_nn(double *S, int64_t ld, const double *L,
                                                    int64_t lda, int64_t r0, int64_t krow,
                                                    int64_t half_tiles, int64_t col_shift)
 {
     using TL = Tile<2, 2, true, true>;
-    __shared__ double lds[TL::LDS];
+    using TF = TileF<2, 2, true>;
+    __shared__ double lds[MIX ? (TF::LDS + 1) / 2 : TL::LDS];
     const int64_t ct = blockIdx.x;
     const int64_t c0 = (ct < half_tiles) ? 128 * ct : col_shift + 128 * (ct - half_tiles);
     const int64_t m0 = r0 + 128 * (int64_t)blockIdx.y;
     double *C = S + m0 + c0 * ld;
-    d4 acc[4][4];
-    TL::load_c(acc, C, ld);
-    TL::run(acc, L + m0 + krow * lda, lda, S + krow + c0 * ld, ld, NB, lds);
-    TL::store_c(acc, C, ld);
+    if constexpr (MIX) {
+        TF::update(C, ld, L + m0 + krow * lda, lda, S + krow + c0 * ld, ld, NB, (float *)lds);
+    } else {
+        d4 acc[4][4];
+        TL::load_c(acc, C, ld);
+        TL::run(acc, L + m0 + krow * lda, lda, S + krow + c0 * ld, ld, NB, lds);
+        TL::store_c(acc, C, ld);
+    }
 }
 
 void launch_update_nn(hipStream_t s, double *S, int64_t ld, const double *L, int64_t lda,
-                      int64_t r0, int64_t krow, int64_t rows, int64_t ncols, int64_t col_shift)
+                      int64_t r0, int64_t krow, int64_t rows, int64_t ncols, int64_t col_shift,
+                      int mixed)
 {
     if (rows <= 0)
         return;
     const int64_t half = ncols / 128;
-    hipLaunchKernelGGL(k_update_nn, dim3((unsigned)(2 * half), (unsigned)(rows / 128)), dim3(256),
-                       0, s, S, ld, L, lda, r0, krow, half, col_shift);
+    const dim3 g((unsigned)(2 * half), (unsigned)(rows / 128));
+    if (mixed)
+        hipLaunchKernelGGL(k_update_nn<true>, g, dim3(256), 0, s, S, ld, L, lda, r0, krow, half,
+                           col_shift);
+    else
+        hipLaunchKernelGGL(k_update_nn<false>, g, dim3(256), 0, s, S, ld, L, lda, r0, krow, half,
+                           col_shift);
 }
 
 // ---------------------------------------------------------------------------

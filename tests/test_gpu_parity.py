@@ -196,3 +196,30 @@ def test_fit_n400_matches_oracle(ctx, oracle_mod):
     assert (got["n_loglik_calls"], got["n_grad_calls"]) == (want["n_loglik_calls"], want["n_grad_calls"])
     np.testing.assert_allclose(got["theta"], want["theta"], rtol=1e-6)
     assert len(it_gpu) == got["n_iter"] + 1
+
+
+@pytest.mark.parametrize("n,theta", [(600, (1.0, 0.1, 0.5)), (1500, (1.5, 0.07, 1.0))])
+def test_mixed_precision(ctx, oracle_mod, n, theta):
+    """Mixed form: the trace-phase updates on FP32 MFMA.  The log-likelihood is
+    the FP64 one bit for bit; score and Fisher carry FP32 rounding of the two
+    block solves: per-term score error <= 1e-5 and Fisher <= 1e-4 relative on
+    these moderately conditioned cases (measured 4e-8 .. 5e-6 and 3e-8 .. 7e-7)."""
+    say("mixed n=%d theta=%s" % (n, theta))
+    locs, z, _ = synth.dataset(n, (1.0, 0.1, 0.5), 3000 + n)
+    ctx.set_data(locs, z)
+    want = oracle_mod.evaluate(locs, z, theta)
+    ll64, s64, f64 = ctx.eval(theta)
+    ctx.set_precision(fbt.MIXED_FP32)
+    try:
+        ll, score, fisher = ctx.eval(theta)
+        ll_only = ctx.loglik(theta)
+    finally:
+        ctx.set_precision(fbt.FP64)
+    assert ll == ll64 and ll_only == ll64
+    scale = np.array([(want["quad"] + n) / (2 * theta[0]),
+                      0.5 * (abs(want["trace"]["a"]) + abs(want["wSw"]["a"])),
+                      0.5 * (abs(want["trace"]["n"]) + abs(want["wSw"]["n"]))])
+    assert np.all(np.abs(score - want["score"]) <= 1e-5 * scale)
+    d = np.sqrt(np.outer(np.diag(want["fisher"]), np.diag(want["fisher"])))
+    assert np.all(np.abs(fisher - want["fisher"]) <= 1e-4 * d)
+    assert np.array_equal(score[:1], s64[:1])          # sigma2 score: FP64 quadratic form
