@@ -20,6 +20,9 @@ sys.path.insert(0, ROOT)
 METRIC = "loglik+score+Fisher evals/s at n=20k, FP64 vs mixed; % of MFMA peak"
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+# timing class -> kernel that implements it (for the counter summaries)
+DOMINANT_KERNEL = {"left_update": "k_update_nn", "cholesky_update": "k_update_lower",
+                   "right_update": "k_update_lower"}
 
 
 def log(*a):
@@ -45,6 +48,51 @@ def cpu_baseline(n_full, n_sample, theta, seed):
                                                        n_full)}
 
 
+def kernel_source_sha256():
+    import hashlib
+
+    path = os.path.join(ROOT, "paper_2601_11437_amd", "csrc", "fbt_kernels.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE passes, each scaled by what the
+    same counter reads for a plain copy of known size).  None when no summary
+    exists for this kernel or the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "%s_n20k_pmc.md" % kernel)
+    if not os.path.exists(path):
+        return None, "no counter summary for this kernel"
+    rec = None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("traffic_json:"):
+                rec = json.loads(line.split(":", 1)[1])
+    if rec is None:
+        return None, "counter summary has no traffic_json line"
+    if rec["source_sha256"] != kernel_source_sha256():
+        return None, "kernel source changed since the counters were taken"
+    b = 1024.0 * (rec["fetch_kib_per_dispatch"] * rec["fetch_scale"] +
+                  rec["write_kib_per_dispatch"] * rec["write_scale"])
+    return b, "rocprofv3 --pmc, %s" % os.path.relpath(path, ROOT)
+
+
+def copy_calibration():
+    """A plain 1 GiB device-to-device copy, three times, for scaling the HBM
+    byte counters (run under rocprofv3 --pmc)."""
+    import torch
+
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8,
+                      "repeats": 3}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -53,7 +101,14 @@ def main():
     ap.add_argument("--n", type=int, default=20000)
     ap.add_argument("--cpu-sample-n", type=int, default=4000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-precision and adjoint comparisons (profiling runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run the 1 GiB copy used to scale the HBM byte counters")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the single-field evaluation is not sharded "
               "across GPUs in this build (see the design notes); use --gpus 1", file=sys.stderr)
@@ -90,27 +145,42 @@ def main():
         ctx.loglik(theta)
     dt_ll = (time.perf_counter() - t1) / max(1, args.steps)
 
-    # the mixed form (trace-phase updates on FP32 MFMA), same workload and steps
-    ctx.set_precision(fbt.MIXED_FP32)
-    for i in range(args.warmup):
-        ctx.eval(theta)
-    t2 = time.perf_counter()
-    for i in range(args.steps):
-        llm, scm, fim = ctx.eval(theta)
-    dt_mix = time.perf_counter() - t2
-    ctx.set_precision(fbt.FP64)
-    tscale = ctx.eval_terms(theta)
-    sscale = np.array([(tscale[1] + n) / (2 * theta[0]), 0.5 * (abs(tscale[2]) + abs(tscale[4])),
-                       0.5 * (abs(tscale[3]) + abs(tscale[5]))])
-    dd = np.sqrt(np.outer(np.diag(fisher), np.diag(fisher)))
-    mixed = {"precision": "trace-phase updates FP32 MFMA (FP32 accumulation); factorisation, "
-                          "log-det, solves of the diagonal blocks, Bessel terms and reductions FP64",
-             "value": args.steps / dt_mix, "unit": "evals/s", "ms_per_step": 1e3 * dt_mix / args.steps,
-             "speedup_vs_fp64": dt / dt_mix,
-             "loglik_rel_err_vs_fp64": abs(llm - ll) / abs(ll),
-             "score_err_per_term_vs_fp64": (np.abs(scm - score) / sscale).tolist(),
-             "fisher_rel_err_vs_fp64": float(np.max(np.abs(fim - fisher) / dd))}
-    log("mixed: %.1f ms per step" % (1e3 * dt_mix / args.steps))
+    mixed = adjoint = None
+    if not args.no_mixed:
+        # the mixed form (trace-phase updates on FP32 MFMA), same workload and steps
+        ctx.set_precision(fbt.MIXED_FP32)
+        for i in range(args.warmup):
+            ctx.eval(theta)
+        t2 = time.perf_counter()
+        for i in range(args.steps):
+            llm, scm, fim = ctx.eval(theta)
+        dt_mix = time.perf_counter() - t2
+        ctx.set_precision(fbt.FP64)
+        tscale = ctx.eval_terms(theta)
+        sscale = np.array([(tscale[1] + n) / (2 * theta[0]),
+                           0.5 * (abs(tscale[2]) + abs(tscale[4])),
+                           0.5 * (abs(tscale[3]) + abs(tscale[5]))])
+        dd = np.sqrt(np.outer(np.diag(fisher), np.diag(fisher)))
+        mixed = {"precision": "trace-phase updates FP32 MFMA (FP32 accumulation); factorisation, "
+                              "log-det, solves of the diagonal blocks, Bessel terms and reductions FP64",
+                 "value": args.steps / dt_mix, "unit": "evals/s",
+                 "ms_per_step": 1e3 * dt_mix / args.steps, "speedup_vs_fp64": dt / dt_mix,
+                 "loglik_rel_err_vs_fp64": abs(llm - ll) / abs(ll),
+                 "score_err_per_term_vs_fp64": (np.abs(scm - score) / sscale).tolist(),
+                 "fisher_rel_err_vs_fp64": float(np.max(np.abs(fim - fisher) / dd))}
+        log("mixed: %.1f ms per step" % (1e3 * dt_mix / args.steps))
+        # adjoint gradient (log-likelihood + score, no Fisher), FP64
+        ctx.grad(theta)
+        t3 = time.perf_counter()
+        for i in range(args.steps):
+            lla, sca = ctx.grad(theta)
+        dt_adj = time.perf_counter() - t3
+        adjoint = {"what": "loglik + score by the adjoint form (no Fisher information), FP64",
+                   "value": args.steps / dt_adj, "unit": "grads/s",
+                   "ms_per_step": 1e3 * dt_adj / args.steps,
+                   "score_err_per_term_vs_eval": (np.abs(sca - score) / sscale).tolist(),
+                   "loglik_equal": bool(lla == ll)}
+        log("adjoint: %.1f ms per gradient" % (1e3 * dt_adj / args.steps))
 
     evals_per_s = args.steps / dt
     phases = {}
@@ -123,8 +193,10 @@ def main():
     dom = max((k for k in tim if tim[k]["flops"] > 0), key=lambda k: tim[k]["ms"])
     d = tim[dom]
     achieved = d["flops"] / (d["ms"] * 1e-3) / 1e12
+    traffic, traffic_src = measured_traffic(DOMINANT_KERNEL.get(dom, dom))
     roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
+                "traffic_unit": "bytes per launch", "traffic_source": traffic_src,
                 "launches": d["launches"], "avg_launch_ms": d["ms"] / d["launches"],
                 "flops_per_launch": d["flops"] / d["launches"]}
     total_fl = sum(v["flops"] for v in tim.values())
@@ -151,6 +223,7 @@ def main():
         "loglik_only_evals_per_s": 1.0 / dt_ll,
         "phases": phases,
         "mixed": mixed,
+        "adjoint_grad": adjoint,
         "result": {"loglik": ll, "score": score.tolist(), "fisher_diag": np.diag(fisher).tolist()},
     }
     ctx.close()

@@ -112,6 +112,20 @@ fbt_status fbt_eval(fbt_ctx *ctx, const double theta[3], double *loglik, double 
  * with w = Sigma^{-1} Z.  Errors: as fbt_loglik. */
 fbt_status fbt_eval_terms(fbt_ctx *ctx, const double theta[3], double terms[9]);
 
+/* Adjoint gradient: the log-likelihood (Eq. (1)) and the score (Eq. (2))
+ * without the Fisher information, at about a third of the cost of fbt_eval.
+ * The score is evaluated as the Frobenius product
+ *   dl/dtheta_i = < (w w^T - Sigma^{-1}) / 2, Sigma_i >_F,  w = Sigma^{-1} Z,
+ * which is Eq. (2) with tr(A B) = <A, B^T>_F; Sigma^{-1} is formed from the
+ * inverse of the Cholesky factor and Sigma_alpha, Sigma_nu are regenerated
+ * entry by entry inside the contraction (never stored).  The sigma^2
+ * component is (Z^T Sigma^{-1} Z - n) / (2 sigma^2) as in fbt_eval.
+ * dloglik_dz: NULL, or host array of n doubles that receives dl/dZ = -w.
+ * Reuses the factor of an immediately preceding fbt_loglik at the bitwise
+ * same theta.  Errors: as fbt_loglik. */
+fbt_status fbt_grad(fbt_ctx *ctx, const double theta[3], double *loglik, double score[3],
+                    double *dloglik_dz);
+
 /* Covariance generation (Section 2.1, and Section 2.2 for the derivatives):
  * writes the n x n matrix Sigma (which = 0), Sigma_alpha (1) or Sigma_nu (2)
  * at theta into out (host, column-major, leading dimension ld >= n).
@@ -189,12 +203,60 @@ const char *fbt_last_error(const fbt_ctx *ctx);
 /* 0-based index of the first failing pivot of the last FBT_ENOTPD, else -1. */
 int64_t fbt_last_notpd_pivot(const fbt_ctx *ctx);
 
+/* ---- Batched fields ----------------------------------------------------
+ * Many independent fields evaluated together, e.g. one Fisher-BT iteration
+ * (Algorithm 1) over a set of fields: a pool of `workers` contexts, each with
+ * its own HIP streams and device buffers, driven by host threads that take
+ * fields in order of decreasing n.  Each field's result is bitwise the one a
+ * single context gives for it (the same kernels and reduction order).
+ * cfg->hip_stream is ignored (workers own their streams); cfg->precision
+ * applies to every worker.  Device memory: about 3 * 8 * npad^2 bytes per
+ * worker for the largest field (npad = 256 ceil((n + 1) / 256)). */
+typedef struct fbt_batch fbt_batch;
+/* workers in [1, 64].  Errors: FBT_EINVAL, FBT_EDEVICE, FBT_ENOMEM. */
+fbt_status fbt_batch_create(const fbt_config *cfg, int32_t workers, fbt_batch **out);
+void fbt_batch_destroy(fbt_batch *b); /* NULL-safe */
+/* nf fields; field f: n[f] >= 1 observations, locs[f] (n[f] x 2, row-major,
+ * host) and z[f] (n[f], host).  The data are copied.  Errors: FBT_EINVAL. */
+fbt_status fbt_batch_set_fields(fbt_batch *b, int32_t nf, const int64_t *n,
+                                const double *const *locs, const double *const *z);
+/* thetas: nf x 3 (row-major); mode[f]: 0 skip, 1 log-likelihood (Algorithm 2),
+ * 2 log-likelihood + score + Fisher (Algorithm 3), 3 log-likelihood + score
+ * (adjoint form, see fbt_grad).  Outputs (host): loglik[nf] (modes >= 1),
+ * score[3 nf] (modes 2, 3), fisher[9 nf] (mode 2); a buffer no field needs may
+ * be NULL.  status[nf] receives each field's fbt_status (e.g. FBT_ENOTPD for a
+ * theta whose covariance is not positive definite; that field's outputs are
+ * then not written).  Returns FBT_OK unless a device error or allocation
+ * failure stopped the batch (FBT_EDEVICE / FBT_ENOMEM, detail in
+ * fbt_batch_last_error), or FBT_EINVAL for bad arguments. */
+fbt_status fbt_batch_eval(fbt_batch *b, const double *thetas, const int32_t *mode,
+                          double *loglik, double *score, double *fisher, int32_t *status);
+const char *fbt_batch_last_error(const fbt_batch *b);
+
+/* How Sigma_nu = dSigma/dnu is computed (Section 2.2).
+ *   FBT_SIGMA_NU_EXACT (default): the exact derivative of the Matern entry,
+ *     by quadrature of the integral form of K_nu and its order derivative.
+ *   FBT_SIGMA_NU_PAPER: the paper's own numerical scheme for d/dnu[x^nu K_nu]
+ *     (Supplementary A): series for x < 8.5, uniform expansion for
+ *     8.5 <= x < 30, Hankel expansion for x >= 30, and a central difference
+ *     with lag 1e-9 where nu (x < 8.5) or nu + 1/2 (x >= 30) lies within 1e-6
+ *     of an integer; the prefactor derivative is exact in both modes.  Its
+ *     truncation and cancellation errors (up to ~1e-6 relative near x = 8.5,
+ *     more as nu approaches an integer) move the score and the fit; this
+ *     mode exists to measure that.
+ * Affects fbt_eval, fbt_eval_terms, fbt_grad, fbt_fit and fbt_covariance(which = 2).
+ * Errors: FBT_EINVAL (NULL context or unknown mode). */
+typedef enum { FBT_SIGMA_NU_EXACT = 0, FBT_SIGMA_NU_PAPER = 1 } fbt_sigma_nu_mode;
+fbt_status fbt_set_sigma_nu_mode(fbt_ctx *ctx, int32_t mode);
+
 /* Per-kernel-class timing with HIP events recorded on the context's stream.
  * enable != 0 starts recording (and clears the counters); 0 stops it. */
 fbt_status fbt_set_timing(fbt_ctx *ctx, int32_t enable);
 /* Kernel classes: 0 generation, 1 diagonal factor+inverse, 2 panel solve,
  * 3 trailing Cholesky update, 4 left-solve diagonal apply, 5 left-solve update,
- * 6 right-solve panel with trace reductions, 7 right-solve update, 8 reductions.
+ * 6 right-solve panel with trace reductions, 7 right-solve update, 8 reductions,
+ * 9 inverse of the factor (adjoint), 10 X^T X product (adjoint),
+ * 11 adjoint fill / extraction / contraction with the regenerated derivatives.
  * Returns launches, summed milliseconds and summed algorithmic flops of the
  * class since timing was enabled (timing must have been enabled). */
 fbt_status fbt_get_timing(fbt_ctx *ctx, int32_t kernel_class, int64_t *launches, double *ms,

@@ -152,7 +152,22 @@ def loglik(locs, z, theta):
     return {"loglik": float(ll), "logdet": float(logdet), "quad": quad}
 
 
-def evaluate(locs, z, theta):
+def _paper_sigma_nu(locs, theta):
+    """Dense Sigma_nu by the paper's case scheme (oracle.paper_mode)."""
+    from . import paper_mode
+
+    locs = np.asarray(locs, dtype=np.float64)
+    n = locs.shape[0]
+    i, j = np.tril_indices(n, -1)
+    h = np.hypot(locs[i, 0] - locs[j, 0], locs[i, 1] - locs[j, 1])
+    v = paper_mode.sigma_nu_entries(h, theta, bessel_k)
+    Sn = np.zeros((n, n))
+    Sn[i, j] = v
+    Sn[j, i] = v
+    return Sn
+
+
+def evaluate(locs, z, theta, sigma_nu="exact"):
     """Algorithm 3: log-likelihood, score (Eq. 2) and Fisher information (Eq. 3).
 
     The score is over theta = (sigma2, alpha, nu).  Besides the results it
@@ -165,6 +180,8 @@ def evaluate(locs, z, theta):
     z = np.asarray(z, dtype=np.float64)
     n = z.size
     S, Sa, Sn = cov_matrices(locs, theta)
+    if sigma_nu == "paper":
+        Sn = _paper_sigma_nu(locs, theta)
     # Step 1: log-likelihood
     L = _cholesky(S)
     logdet = 2.0 * np.sum(np.log(np.diag(L)))
@@ -196,6 +213,35 @@ def evaluate(locs, z, theta):
     return {"loglik": float(ll), "score": score, "fisher": fisher,
             "logdet": float(logdet), "quad": quad,
             "trace": tr, "wSw": wv, "trAB_frobenius": frob, "trAB_direct": direct}
+
+
+def adjoint_score(locs, z, theta, sigma_nu="exact"):
+    """Score of Eq. (2) in its adjoint (Frobenius) form, for the adjoint
+    gradient: with w = Sigma^{-1} Z,
+
+        dl/dtheta_i = 1/2 w^T Sigma_i w - 1/2 tr(Sigma^{-1} Sigma_i)
+                    = sum_jk G_jk (Sigma_i)_jk,   G = (w w^T - Sigma^{-1}) / 2,
+
+    written out with an explicit inverse Sigma^{-1} = cho_solve(I) and the
+    entrywise sum (tr(A B) = sum_jk A_jk B_kj, B symmetric).  Also returns
+    dl/dZ = -w, the gradient of Eq. (1) with respect to the observations.
+    """
+    theta = _check_theta(theta)
+    s2 = theta[0]
+    z = np.asarray(z, dtype=np.float64)
+    n = z.size
+    S, Sa, Sn = cov_matrices(locs, theta)
+    if sigma_nu == "paper":
+        Sn = _paper_sigma_nu(locs, theta)
+    L = _cholesky(S)
+    logdet = 2.0 * np.sum(np.log(np.diag(L)))
+    w = scipy.linalg.cho_solve((L, True), z)
+    quad = float(z @ w)
+    ll = -0.5 * n * np.log(2 * np.pi) - 0.5 * logdet - 0.5 * quad
+    Sinv = scipy.linalg.cho_solve((L, True), np.eye(n))
+    G = 0.5 * (np.outer(w, w) - Sinv)
+    score = np.array([float(np.sum(G * S)) / s2, float(np.sum(G * Sa)), float(np.sum(G * Sn))])
+    return {"loglik": float(ll), "score": score, "dz": -w, "quad": quad}
 
 
 from .fisher_bt import (  # noqa: E402  (re-export the fit)

@@ -21,7 +21,7 @@ OK, EINVAL, ENOTPD, ENOMEM, EDEVICE, ENONFINITE, EBUDGET, ENODATA = 0, -1, -2, -
 # kernel classes of fbt_get_timing
 KERNEL_CLASSES = ("generation", "diag_factor_inverse", "panel_solve", "cholesky_update",
                   "left_diag_apply", "left_update", "right_panel_reduce", "right_update",
-                  "reductions")
+                  "reductions", "adjoint_inverse", "adjoint_xtx", "adjoint_contraction")
 
 _lib = None
 _d = ctypes.c_double
@@ -54,6 +54,7 @@ class Config(ctypes.Structure):
 
 
 FP64, MIXED_FP32, MIXED_FP32_ALL = 0, 1, 2
+SIGMA_NU_EXACT, SIGMA_NU_PAPER = 0, 1
 
 
 class Evaluator(ctypes.Structure):
@@ -80,6 +81,13 @@ SIGNATURES = {
     "fbt_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "fbt_last_error": (ctypes.c_char_p, [_p]),
     "fbt_last_notpd_pivot": (_i64, [_p]),
+    "fbt_grad": (ctypes.c_int, [_p, _p, _p, _p, _p]),
+    "fbt_set_sigma_nu_mode": (ctypes.c_int, [_p, _i32]),
+    "fbt_batch_create": (ctypes.c_int, [ctypes.POINTER(Config), _i32, ctypes.POINTER(_p)]),
+    "fbt_batch_destroy": (None, [_p]),
+    "fbt_batch_set_fields": (ctypes.c_int, [_p, _i32, _p, _p, _p]),
+    "fbt_batch_eval": (ctypes.c_int, [_p, _p, _p, _p, _p, _p, _p]),
+    "fbt_batch_last_error": (ctypes.c_char_p, [_p]),
     "fbt_set_timing": (ctypes.c_int, [_p, _i32]),
     "fbt_get_timing": (ctypes.c_int, [_p, _i32, ctypes.POINTER(_i64), _dp, _dp]),
 }
@@ -280,6 +288,16 @@ class Context:
         self._check(lib().fbt_eval(self._h, _ptr(th), _ptr(ll), _ptr(sc), _ptr(fi)))
         return float(ll[0]), sc, fi.reshape(3, 3)
 
+    def grad(self, theta, dz: bool = False):
+        """(loglik, score[3]) by the adjoint form of Eq. (2), no Fisher
+        information; with dz=True also dl/dZ (n,) as a third element."""
+        th = _arr(theta, 3)
+        ll, sc = np.zeros(1), np.zeros(3)
+        g = np.zeros(self.n) if dz else None
+        self._check(lib().fbt_grad(self._h, _ptr(th), _ptr(ll), _ptr(sc),
+                                   _ptr(g) if dz else None))
+        return (float(ll[0]), sc, g) if dz else (float(ll[0]), sc)
+
     def eval_terms(self, theta) -> np.ndarray:
         th = _arr(theta, 3)
         t = np.zeros(9)
@@ -313,6 +331,11 @@ class Context:
         (2: Cholesky updates too) for the following evaluations."""
         self._check(lib().fbt_set_precision(self._h, int(precision)))
 
+    def set_sigma_nu_mode(self, mode: int):
+        """SIGMA_NU_EXACT (0, default) or SIGMA_NU_PAPER (1: the case scheme of
+        Supplementary A for dSigma/dnu)."""
+        self._check(lib().fbt_set_sigma_nu_mode(self._h, int(mode)))
+
     def set_timing(self, enable: bool):
         self._check(lib().fbt_set_timing(self._h, 1 if enable else 0))
 
@@ -324,3 +347,56 @@ class Context:
                                              ctypes.byref(fl)))
             out[name] = {"launches": n.value, "ms": ms.value, "flops": fl.value}
         return out
+
+
+class Batch:
+    """Many independent fields evaluated together (fbt_batch_*): a pool of
+    `workers` device contexts fed by host threads, longest field first."""
+
+    SKIP, LOGLIK, EVAL, GRAD = 0, 1, 2, 3
+
+    def __init__(self, workers: int = 8, device: int = 0, precision: int = FP64):
+        cfg = Config(int(device), 0, int(precision), None)
+        h = _p()
+        st = lib().fbt_batch_create(ctypes.byref(cfg), int(workers), ctypes.byref(h))
+        if st != OK:
+            raise FisherBTError(st, "fbt_batch_create(workers=%d)" % workers)
+        self._h = h
+        self.nf = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fbt_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def set_fields(self, fields):
+        """fields: sequence of (locs (n x 2), z (n)) numpy pairs."""
+        locs = [np.ascontiguousarray(l, dtype=np.float64) for l, _ in fields]
+        zs = [np.ascontiguousarray(z, dtype=np.float64) for _, z in fields]
+        n = np.array([z.size for z in zs], dtype=np.int64)
+        lp = (_p * len(locs))(*[a.ctypes.data for a in locs])
+        zp = (_p * len(zs))(*[a.ctypes.data for a in zs])
+        st = lib().fbt_batch_set_fields(self._h, len(zs), n.ctypes.data, lp, zp)
+        if st != OK:
+            raise FisherBTError(st, "fbt_batch_set_fields")
+        self._keep = (locs, zs)
+        self.nf = len(zs)
+
+    def eval(self, thetas, mode):
+        """thetas (nf x 3), mode (nf,) in {SKIP, LOGLIK, EVAL, GRAD}.
+        Returns (loglik (nf,), score (nf, 3), fisher (nf, 3, 3), status (nf,));
+        entries of fields that were skipped or failed are NaN."""
+        th = np.ascontiguousarray(thetas, dtype=np.float64).reshape(self.nf, 3)
+        md = np.ascontiguousarray(np.broadcast_to(np.asarray(mode, dtype=np.int32), (self.nf,)))
+        ll = np.full(self.nf, np.nan)
+        sc = np.full((self.nf, 3), np.nan)
+        fi = np.full((self.nf, 9), np.nan)
+        status = np.zeros(self.nf, dtype=np.int32)
+        st = lib().fbt_batch_eval(self._h, th.ctypes.data, md.ctypes.data, ll.ctypes.data,
+                                  sc.ctypes.data, fi.ctypes.data, status.ctypes.data)
+        if st != OK:
+            raise FisherBTError(st, lib().fbt_batch_last_error(self._h).decode())
+        return ll, sc, fi.reshape(self.nf, 3, 3), status

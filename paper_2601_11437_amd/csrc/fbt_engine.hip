@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -17,8 +18,13 @@ using namespace fbt;
 
 namespace {
 
-constexpr int NCLASS = 9;
-enum KClass { KC_GEN, KC_DIAG, KC_PANEL, KC_SYRK, KC_LAPPLY, KC_LUPD, KC_RPANEL, KC_RUPD, KC_RED };
+constexpr int NCLASS = 12;
+enum KClass {
+    KC_GEN, KC_DIAG, KC_PANEL, KC_SYRK, KC_LAPPLY, KC_LUPD, KC_RPANEL, KC_RUPD, KC_RED,
+    KC_INV,   // adjoint: X = L'^{-1} (diagonal apply and updates)
+    KC_LAUUM, // adjoint: P = X^T X
+    KC_ADJ    // adjoint: contraction with the regenerated derivatives
+};
 
 struct Timed {
     int cls;
@@ -35,6 +41,7 @@ struct fbt_ctx {
     hipEvent_t evP = nullptr, evB = nullptr;
     bool own_stream = false;
     int precision = FBT_FP64; // see fbt_precision
+    int sigma_nu_mode = FBT_SIGMA_NU_EXACT;
     std::string err;
     int64_t notpd = -1;
 
@@ -44,6 +51,7 @@ struct fbt_ctx {
     double *A = nullptr;  // Sigma' -> bordered factor L' (lower)
     double *S2 = nullptr; // [Sigma_alpha' | Sigma_nu'] -> X -> W (npad x 2 npad)
     double *Linv = nullptr, *logdet = nullptr, *partials = nullptr, *out = nullptr;
+    double *wv = nullptr; // w = Sigma^{-1} Z (adjoint gradient)
     int *info = nullptr;
     Node *tab = nullptr;
     Node *h_tab = nullptr; // pinned staging
@@ -64,6 +72,12 @@ struct fbt_ctx {
 };
 
 namespace {
+
+// CUs kept free of the bulk-update stream (see fbt_create)
+constexpr int BULK_CU_RESERVE = 0;
+
+// node table followed by the paper-mode coefficient table (one upload)
+constexpr size_t TAB_BYTES = TAB_MAX * sizeof(Node) + PC_SIZE * sizeof(double);
 
 fbt_status fail(fbt_ctx *c, fbt_status s, const std::string &m)
 {
@@ -101,6 +115,86 @@ double digamma(double v)
     return acc + std::log(v) - 0.5 / v - tail;
 }
 
+// Coefficients c_j^(k) of the Debye polynomials U_k(p) = sum_j c_j^(k) p^j,
+// k < 12, by the recurrence that follows from
+//   U_{k+1}(p) = p^2 (1 - p^2) U_k'(p) / 2 + (1/8) int_0^p (1 - 5 t^2) U_k(t) dt:
+//   c_j^(k+1) = (j - 1 + 1/(4j)) c_{j-1}^(k) / 2 - (j - 3 + 5/(4j)) c_{j-3}^(k) / 2.
+struct Debye {
+    double c[12][PC_DEB];
+    Debye()
+    {
+        std::memset(c, 0, sizeof(c));
+        c[0][0] = 1.0;
+        for (int k = 0; k + 1 < 12; ++k)
+            for (int j = 1; j <= 3 * (k + 1); ++j) {
+                double v = 0.5 * (j - 1 + 0.25 / j) * c[k][j - 1];
+                if (j >= 3)
+                    v -= 0.5 * (j - 3 + 1.25 / j) * c[k][j - 3];
+                c[k + 1][j] = v;
+            }
+    }
+};
+
+// Paper mode coefficient table for theta (layout in fbt_internal.h):
+//  case 2: term k of d/dnu[x^nu K_nu] is (x/2)^{2k} (A'_k + x^{2 nu} (B'_k + 2 log x B_k)),
+//    A'_k = 2^nu (log 2 + psi(nu) - d_k(-nu)) Gamma(nu) g_k(-nu) / (2 k!),
+//    B_k  = 2^-nu Gamma(-nu) g_k(nu) / (2 k!),  B'_k = B_k (-log 2 - psi(-nu) + d_k(nu)),
+//    g_k(v) = prod_{j<=k} 1/(v + j),  d_k(v) = -sum_{j<=k} 1/(v + j);
+//  case 3: S0 = sum_k (-1)^k nu^-k U_k, S1 = sum_k (-1)^k k nu^{-k-1} U_k,
+//    S2 = sum_k (-1)^k nu^-k U_k' as polynomials in p, for 12 and for 8 terms;
+//  case 4: a_k = prod_{j<=k} (4 nu^2 - (2j-1)^2) / (8^k k!),
+//    b_k = sum_{j<=k} 8 nu / (4 nu^2 - (2j-1)^2); stored a_k and a_k b_k.
+void paper_coefficients(const GenParams &gp, double *pc)
+{
+    static const Debye U;
+    const double nu = gp.nu, ln2 = std::log(2.0);
+    std::memset(pc, 0, PC_SIZE * sizeof(double));
+    if (!gp.fd_small) {
+        const double gn = std::tgamma(nu), gmn = std::tgamma(-nu);
+        const double pn = digamma(nu), pmn = digamma(-nu);
+        double gkm = 1.0, gkp = 1.0, dkm = 0.0, dkp = 0.0, fact = 1.0;
+        for (int k = 0; k < PC_SER; ++k) {
+            if (k > 0) {
+                gkm /= (-nu + k);
+                gkp /= (nu + k);
+                dkm -= 1.0 / (-nu + k);
+                dkp -= 1.0 / (nu + k);
+                fact *= k;
+            }
+            pc[PC_A1 + k] = std::pow(2.0, nu) * (ln2 + pn - dkm) * gn * gkm / (2.0 * fact);
+            pc[PC_B0 + k] = std::pow(2.0, -nu) * gmn * gkp / (2.0 * fact);
+            pc[PC_B1 + k] = pc[PC_B0 + k] * (-ln2 - pmn + dkp);
+        }
+    }
+    for (int set = 0; set < 2; ++set) {
+        const int K = set == 0 ? 12 : 8;
+        double *d = pc + (set == 0 ? PC_D12 : PC_D8);
+        for (int k = 0; k < K; ++k) {
+            const double sg = (k & 1) ? -1.0 : 1.0, nk = std::pow(nu, -k);
+            for (int j = 0; j < PC_DEB; ++j) {
+                d[j] += sg * nk * U.c[k][j];
+                d[PC_DEB + j] += sg * k * nk / nu * U.c[k][j];
+                if (j + 1 < PC_DEB)
+                    d[2 * PC_DEB + j] += sg * nk * (j + 1) * U.c[k][j + 1];
+            }
+        }
+    }
+    if (!gp.fd_large) {
+        double a = 1.0, b = 0.0;
+        for (int k = 0; k < PC_HAN; ++k) {
+            if (k > 0) {
+                const double f = 4.0 * nu * nu - double(2 * k - 1) * double(2 * k - 1);
+                a *= f / (8.0 * k);
+                b += 8.0 * nu / f;
+            }
+            pc[PC_HA + k] = a;
+            pc[PC_HB + k] = a * b;
+        }
+    }
+    pc[PC_LOGNU] = std::log(nu);
+    pc[PC_SQPI] = std::sqrt(M_PI / (2.0 * nu));
+}
+
 // Quadrature tables and prefactors for theta (see the generation kernel).
 GenParams setup_theta(fbt_ctx *c, const double *th)
 {
@@ -115,6 +209,10 @@ GenParams setup_theta(fbt_ctx *c, const double *th)
     gp.n = c->n;
     gp.npad = c->npad;
     gp.ld = c->ld;
+    const bool paper = c->sigma_nu_mode == FBT_SIGMA_NU_PAPER;
+    gp.paper = paper ? 1 : 0;
+    gp.fd_small = std::fabs(gp.nu - std::nearbyint(gp.nu)) > 1e-6 ? 0 : 1;
+    gp.fd_large = std::fabs((gp.nu + 0.5) - std::nearbyint(gp.nu + 0.5)) > 1e-6 ? 0 : 1;
     int off = 0;
     const double tcap = 700.0 / (gp.abs_nu + 1.0); // keeps cosh(nu t) finite
     for (int L = 0; L < NLEV; ++L) {
@@ -133,9 +231,14 @@ GenParams setup_theta(fbt_ctx *c, const double *th)
             nd.wk = w * std::cosh(gp.nu * t);
             nd.wk1 = w * std::cosh((gp.nu - 1.0) * t);
             nd.wd = w * t * std::sinh(gp.nu * t);
+            nd.wkp = paper ? w * std::cosh((gp.nu + PAPER_LAG) * t) : 0.0;
+            nd.wkm = paper ? w * std::cosh((gp.nu - PAPER_LAG) * t) : 0.0;
         }
         off += maxlen;
     }
+    gp.pc = reinterpret_cast<const double *>(c->tab + TAB_MAX);
+    if (paper)
+        paper_coefficients(gp, reinterpret_cast<double *>(c->h_tab + TAB_MAX));
     return gp;
 }
 
@@ -197,9 +300,11 @@ void free_buffers(fbt_ctx *c)
     (void)hipFree(c->logdet);
     (void)hipFree(c->partials);
     (void)hipFree(c->out);
+    (void)hipFree(c->wv);
     (void)hipFree(c->info);
     (void)hipFree(c->tab);
     c->x = c->y = c->z = c->A = c->S2 = c->Linv = c->logdet = c->partials = c->out = nullptr;
+    c->wv = nullptr;
     c->info = nullptr;
     c->tab = nullptr;
     c->alloc_npad = 0;
@@ -209,7 +314,7 @@ fbt_status alloc_for(fbt_ctx *c, int64_t n)
 {
     const int64_t npad = NB * ((n + 1 + NB - 1) / NB);
     c->factor_valid = false;
-    if ((size_t)npad != c->alloc_npad) {
+    if ((size_t)npad > c->alloc_npad) { // buffers only grow (a smaller n reuses them)
         free_buffers(c);
         const size_t ld = (size_t)npad;
         const int T = (int)(npad / NB);
@@ -223,7 +328,8 @@ fbt_status alloc_for(fbt_ctx *c, int64_t n)
             {(void **)&c->S2, ld * ld * 16},  {(void **)&c->Linv, (size_t)T * NB * NB * 8},
             {(void **)&c->logdet, (size_t)T * 8}, {(void **)&c->partials, part * 8},
             {(void **)&c->out, 16 * 8},         {(void **)&c->info, 64},
-            {(void **)&c->tab, TAB_MAX * sizeof(Node)},
+            {(void **)&c->wv, ld * 8},
+            {(void **)&c->tab, TAB_BYTES},
         };
         for (auto &r : req) {
             if (hipMalloc(r.p, r.bytes) != hipSuccess) {
@@ -245,7 +351,7 @@ fbt_status alloc_for(fbt_ctx *c, int64_t n)
 fbt_status upload_theta(fbt_ctx *c, const double *th, GenParams *gp)
 {
     *gp = setup_theta(c, th);
-    HIPCHK(c, hipMemcpyAsync(c->tab, c->h_tab, TAB_MAX * sizeof(Node), hipMemcpyHostToDevice,
+    HIPCHK(c, hipMemcpyAsync(c->tab, c->h_tab, TAB_BYTES, hipMemcpyHostToDevice,
                              c->stream));
     return FBT_OK;
 }
@@ -355,26 +461,43 @@ fbt_status derivative_terms(fbt_ctx *c, const double *th, double terms[9])
     const int mix = c->precision != FBT_FP64; // solve updates in FP32
     auto Lk = [&](int k) { return c->Linv + (size_t)k * NB * NB; };
 
-    // left solve X = L'^{-1} [Sigma_alpha' | Sigma_nu'] on columns [0, ncols) of each half
-    TIMED(c, s0, KC_LAPPLY, 2.0 * dn * dNB * dNB,
-          launch_diag_apply(s0, c->S2, ld, 0, Lk(0), ncols, npad));
-    HIPCHK(c, hipEventRecord(c->evP, s0));
+    // Left solve X = L'^{-1} [Sigma_alpha' | Sigma_nu'] on columns [0, ncols) of
+    // each half.  Block rows are taken in pairs (b, b + 1).  Inside a pair the
+    // solve runs on s0 with one panel at a time: diagonal apply of block b,
+    // update of block row b + 1 by panel b, diagonal apply of block b + 1.
+    // Everything below the pair is then updated by both panels at once
+    // (K = 2 NB, the better-shaped product): s0 updates the next pair
+    // (lookahead) once s1 has finished the previous bulk update, and s1
+    // updates all rows beyond the next pair.
+    auto real_rows = [&](int64_t r, int64_t cnt) {
+        return (double)std::max<int64_t>(0, std::min<int64_t>(n - r, cnt));
+    };
     HIPCHK(c, hipEventRecord(c->evB, s0));
-    for (int k = 0; k + 1 < T; ++k) {
-        const int64_t kc = (int64_t)k * NB, r1 = kc + NB, r2 = r1 + NB;
-        const double m1 = std::min<double>(NB, std::max<int64_t>(0, n - r1));
-        const double m2 = std::max<int64_t>(0, n - r2);
-        HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
-        TIMED(c, s0, KC_LUPD, 2.0 * m1 * dNB * 2.0 * dn,
-              launch_update_nn(s0, c->S2, ld, A, ld, r1, kc, NB, ncols, npad, mix));
+    for (int b = 0; b < T; b += 2) {
+        const int nb = std::min(2, T - b);
+        const int64_t r0 = (int64_t)b * NB, rn = r0 + (int64_t)nb * NB;
+        const int K = nb * NB;
         TIMED(c, s0, KC_LAPPLY, 2.0 * dn * dNB * dNB,
-              launch_diag_apply(s0, c->S2, ld, r1, Lk(k + 1), ncols, npad));
-        HIPCHK(c, hipStreamWaitEvent(s1, c->evP, 0));
-        if (k + 2 < T)
-            TIMED(c, s1, KC_LUPD, 2.0 * m2 * dNB * 2.0 * dn,
-                  launch_update_nn(s1, c->S2, ld, A, ld, r2, kc, npad - r2, ncols, npad, mix));
-        HIPCHK(c, hipEventRecord(c->evB, s1));
+              launch_diag_apply(s0, 2, c->S2, ld, r0, Lk(b), ncols, npad));
+        if (nb == 2) {
+            TIMED(c, s0, KC_LUPD, 2.0 * real_rows(r0 + NB, NB) * dNB * 2.0 * dn,
+                  launch_update_nn(s0, 2, c->S2, ld, A, ld, r0 + NB, r0, NB, ncols, npad, NB, mix));
+            TIMED(c, s0, KC_LAPPLY, 2.0 * dn * dNB * dNB,
+                  launch_diag_apply(s0, 2, c->S2, ld, r0 + NB, Lk(b + 1), ncols, npad));
+        }
         HIPCHK(c, hipEventRecord(c->evP, s0));
+        if (rn >= npad)
+            break;
+        const int64_t la = std::min<int64_t>(2 * NB, npad - rn); // rows of the next pair
+        HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
+        TIMED(c, s0, KC_LUPD, 2.0 * real_rows(rn, la) * K * 2.0 * dn,
+              launch_update_nn(s0, 2, c->S2, ld, A, ld, rn, r0, la, ncols, npad, K, mix));
+        HIPCHK(c, hipStreamWaitEvent(s1, c->evP, 0));
+        if (rn + la < npad)
+            TIMED(c, s1, KC_LUPD, 2.0 * real_rows(rn + la, npad) * K * 2.0 * dn,
+                  launch_update_nn(s1, 2, c->S2, ld, A, ld, rn + la, r0, npad - rn - la, ncols,
+                                   npad, K, mix));
+        HIPCHK(c, hipEventRecord(c->evB, s1));
     }
     HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
 
@@ -419,6 +542,74 @@ fbt_status derivative_terms(fbt_ctx *c, const double *th, double terms[9])
     for (int i = 0; i < 9; ++i)
         if (!std::isfinite(terms[i]))
             return fail(c, FBT_ENONFINITE, "a trace term is not finite");
+    return FBT_OK;
+}
+
+// Adjoint gradient on a valid factor (see k_adjoint): X = L'^{-1} by the left
+// solve of the identity restricted to the block-lower part (columns < (k+1) NB
+// in block row k; columns >= ncols are never needed), P = X^T X, w from row n
+// of X, and the contraction of w w^T - P / 2 with the regenerated Sigma_alpha,
+// Sigma_nu.  X occupies the first half of S2, P the second; L' is untouched.
+// out: sums {dl/dalpha, dl/dnu}; c->wv holds w.
+fbt_status adjoint_terms(fbt_ctx *c, const double *th, double g[2])
+{
+    fbt_status st;
+    hipStream_t s0 = c->stream, s1 = c->stream2;
+    if (!same_theta(c, th) && (st = factorize(c, th, GEN_SIGMA)) != FBT_OK)
+        return st;
+    c->factor_valid = false; // reuse is for one derivative evaluation only
+    GenParams gp;
+    if ((st = upload_theta(c, th, &gp)) != FBT_OK)
+        return st;
+    const int64_t npad = c->npad, ld = c->ld, n = c->n, ncols = c->ncols;
+    const int T = c->T;
+    double *X = c->S2, *P = c->S2 + npad * ld, *A = c->A;
+    const double dNB = NB;
+    auto Lk = [&](int k) { return c->Linv + (size_t)k * NB * NB; };
+    auto cols = [&](int k) { return std::min<int64_t>((int64_t)(k + 1) * NB, ncols); };
+
+    TIMED(c, s0, KC_ADJ, 0.0, launch_fill_identity(s0, X, ld, npad, ncols));
+    TIMED(c, s0, KC_INV, 2.0 * dNB * dNB * (double)cols(0),
+          launch_diag_apply(s0, 1, X, ld, 0, Lk(0), cols(0), 0));
+    HIPCHK(c, hipEventRecord(c->evP, s0));
+    HIPCHK(c, hipEventRecord(c->evB, s0));
+    for (int k = 0; k + 1 < T; ++k) {
+        const int64_t kc = (int64_t)k * NB, r1 = kc + NB, r2 = r1 + NB;
+        const int64_t ck = cols(k);
+        HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
+        TIMED(c, s0, KC_INV, 2.0 * dNB * dNB * (double)ck,
+              launch_update_nn(s0, 1, X, ld, A, ld, r1, kc, NB, ck, 0, NB, 0));
+        TIMED(c, s0, KC_INV, 2.0 * dNB * dNB * (double)cols(k + 1),
+              launch_diag_apply(s0, 1, X, ld, r1, Lk(k + 1), cols(k + 1), 0));
+        HIPCHK(c, hipStreamWaitEvent(s1, c->evP, 0));
+        if (k + 2 < T)
+            TIMED(c, s1, KC_INV, 2.0 * (double)(npad - r2) * dNB * (double)ck,
+                  launch_update_nn(s1, 1, X, ld, A, ld, r2, kc, npad - r2, ck, 0, NB, 0));
+        HIPCHK(c, hipEventRecord(c->evB, s1));
+        HIPCHK(c, hipEventRecord(c->evP, s0));
+    }
+    HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
+    {
+        // flops of the block-lower 128-tiles below ncols: sum over tiles of 2 128^2 (npad - m0)
+        double fl = 0.0;
+        for (int64_t m0 = 0; m0 < ncols; m0 += 128)
+            fl += (double)(m0 / 128 + 1) * 2.0 * 128.0 * 128.0 * (double)(npad - m0);
+        TIMED(c, s0, KC_LAUUM, fl, launch_lauum(s0, P, X, ld, npad, ncols));
+    }
+    TIMED(c, s0, KC_ADJ, 0.0, launch_extract_w(s0, X, ld, n, c->wv));
+    const int64_t nt = (n + 63) / 64, pairs = nt * (nt + 1) / 2;
+    if (2 * pairs > (int64_t)(c->T) * (npad / 64) * 8)
+        return fail(c, FBT_EINVAL, "internal: adjoint partials exceed the partials buffer");
+    TIMED(c, s0, KC_ADJ, 0.0,
+          launch_adjoint(s0, gp, c->x, c->y, c->tab, P, c->wv, c->partials));
+    TIMED(c, s0, KC_RED, 0.0, launch_reduce_pairs(s0, c->partials, pairs, c->out + 2));
+    HIPCHK(c, hipMemcpyAsync(c->h_out, c->out, 4 * sizeof(double), hipMemcpyDeviceToHost, s0));
+    HIPCHK(c, hipStreamSynchronize(s0));
+    tcollect(c);
+    g[0] = c->h_out[2];
+    g[1] = c->h_out[3];
+    if (!std::isfinite(g[0]) || !std::isfinite(g[1]))
+        return fail(c, FBT_ENONFINITE, "an adjoint gradient term is not finite");
     return FBT_OK;
 }
 
@@ -538,13 +729,38 @@ fbt_status fbt_create(const fbt_config *cfg, fbt_ctx **out)
         }
         c->own_stream = true;
     }
-    if (hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&c->evP, hipEventDisableTiming) != hipSuccess ||
+    // s1 (the bulk trailing updates) runs on all CUs but `reserve`, spread over
+    // the device, so that the critical-path kernels on s0 (diagonal blocks,
+    // panels) find free CUs instead of queueing behind bulk workgroups.
+    {
+        int reserve = BULK_CU_RESERVE;
+        if (const char *e = std::getenv("FBT_BULK_CU_RESERVE"))
+            reserve = std::atoi(e);
+        const int ncu = prop.multiProcessorCount;
+        hipError_t er;
+        if (reserve > 0 && reserve < ncu) {
+            std::vector<uint32_t> mask((ncu + 31) / 32, 0u);
+            for (int i = 0; i < ncu; ++i)
+                mask[i / 32] |= 1u << (i % 32);
+            for (int r = 0; r < reserve; ++r) {
+                const int cu = (int)((int64_t)r * ncu / reserve);
+                mask[cu / 32] &= ~(1u << (cu % 32));
+            }
+            er = hipExtStreamCreateWithCUMask(&c->stream2, (uint32_t)mask.size(), mask.data());
+        } else {
+            er = hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking);
+        }
+        if (er != hipSuccess) {
+            fbt_destroy(c);
+            return FBT_EDEVICE;
+        }
+    }
+    if (hipEventCreateWithFlags(&c->evP, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->evB, hipEventDisableTiming) != hipSuccess) {
         fbt_destroy(c);
         return FBT_EDEVICE;
     }
-    if (hipHostMalloc((void **)&c->h_tab, TAB_MAX * sizeof(Node), hipHostMallocDefault) != hipSuccess ||
+    if (hipHostMalloc((void **)&c->h_tab, TAB_BYTES, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&c->h_out, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&c->h_info, 16 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
         fbt_destroy(c);
@@ -644,6 +860,32 @@ fbt_status fbt_eval(fbt_ctx *ctx, const double theta[3], double *loglik, double 
     return FBT_OK;
 }
 
+fbt_status fbt_grad(fbt_ctx *ctx, const double theta[3], double *loglik, double score[3],
+                    double *dloglik_dz)
+{
+    fbt_status st = check_call(ctx, theta);
+    if (st != FBT_OK)
+        return st;
+    if (!loglik || !score)
+        return fail(ctx, FBT_EINVAL, "output pointers must not be NULL");
+    double g[2];
+    if ((st = adjoint_terms(ctx, theta, g)) != FBT_OK)
+        return st;
+    if (dloglik_dz) {
+        HIPCHK(ctx, hipMemcpyAsync(dloglik_dz, ctx->wv, (size_t)ctx->n * sizeof(double),
+                                   hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        for (int64_t i = 0; i < ctx->n; ++i)
+            dloglik_dz[i] = -dloglik_dz[i];
+    }
+    const double n = (double)ctx->n;
+    *loglik = loglik_from(ctx->n, ctx->factor_out[0], ctx->factor_out[1]);
+    score[0] = (ctx->factor_out[1] - n) / (2.0 * theta[0]);
+    score[1] = g[0];
+    score[2] = g[1];
+    return FBT_OK;
+}
+
 fbt_status fbt_covariance(fbt_ctx *ctx, const double theta[3], int32_t which, double *out,
                           int64_t ld)
 {
@@ -696,6 +938,14 @@ fbt_status fbt_set_precision(fbt_ctx *ctx, int32_t precision)
     if (precision != ctx->precision)
         ctx->factor_valid = false;
     ctx->precision = precision;
+    return FBT_OK;
+}
+
+fbt_status fbt_set_sigma_nu_mode(fbt_ctx *ctx, int32_t mode)
+{
+    if (!ctx || (mode != FBT_SIGMA_NU_EXACT && mode != FBT_SIGMA_NU_PAPER))
+        return fail(ctx, FBT_EINVAL, "unknown Sigma_nu mode");
+    ctx->sigma_nu_mode = mode;
     return FBT_OK;
 }
 

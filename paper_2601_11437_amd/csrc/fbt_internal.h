@@ -12,10 +12,28 @@ constexpr int TAB_LN = 64;     // nodes of levels 1..NLEV-1
 constexpr int TAB_MAX = TAB_L0 + (NLEV - 1) * TAB_LN;
 
 // Quadrature node of the scaled integrals (see fbt_kernels.hip):
-//   cm1 = cosh(t) - 1,  wk = w cosh(nu t),  wk1 = w cosh((nu-1) t),  wd = w t sinh(nu t)
+//   cm1 = cosh(t) - 1,  wk = w cosh(nu t),  wk1 = w cosh((nu-1) t),  wd = w t sinh(nu t),
+//   wkp, wkm = w cosh((nu +- PAPER_LAG) t) (paper mode only; zero otherwise)
 struct Node {
-    double cm1, wk, wk1, wd;
+    double cm1, wk, wk1, wd, wkp, wkm;
 };
+
+// Paper mode: dC/dnu by the case scheme of Supplementary A (see fbt_kernels.hip).
+constexpr double PAPER_LAG = 1e-9;  // case 5: central difference in nu
+constexpr int PC_SER = 20;          // case 2: terms of the power series
+constexpr int PC_DEB = 34;          // case 3: coefficients per polynomial in p (12 terms)
+constexpr int PC_HAN = 5;           // case 4: terms of the Hankel expansion
+// coefficient table layout (doubles)
+constexpr int PC_A1 = 0;                          // A'_k
+constexpr int PC_B0 = PC_A1 + PC_SER;             // B_k
+constexpr int PC_B1 = PC_B0 + PC_SER;             // B'_k
+constexpr int PC_D12 = PC_B1 + PC_SER;            // S0, S1, S2 for 12 terms (3 x PC_DEB)
+constexpr int PC_D8 = PC_D12 + 3 * PC_DEB;        // S0, S1, S2 for 8 terms
+constexpr int PC_HA = PC_D8 + 3 * PC_DEB;         // a_k
+constexpr int PC_HB = PC_HA + PC_HAN;             // a_k b_k
+constexpr int PC_LOGNU = PC_HB + PC_HAN;          // log nu
+constexpr int PC_SQPI = PC_LOGNU + 1;             // sqrt(pi / (2 nu))
+constexpr int PC_SIZE = PC_SQPI + 1;
 
 struct GenParams {
     double sigma2, alpha, nu, abs_nu;
@@ -25,6 +43,10 @@ struct GenParams {
     double xtop[NLEV]; // level L serves x <= xtop[L]
     int off[NLEV];     // first node of each level in the table
     int len[NLEV];     // nodes of each level
+    int paper;         // 1: Sigma_nu by the case scheme (paper mode)
+    int fd_small;      // paper mode: nu within 1e-6 of an integer (case 5 for x < 8.5)
+    int fd_large;      // paper mode: nu + 1/2 within 1e-6 of an integer (case 5 for x >= 30)
+    const double *pc;  // paper mode coefficient table (device, PC_SIZE doubles)
     int64_t n;         // observations
     int64_t npad;      // padded order (multiple of NB, > n)
     int64_t ld;        // leading dimension of the matrices
@@ -45,16 +67,24 @@ void launch_update_lower(hipStream_t s, int nmat, double *C0, double *C1, int64_
 void launch_update_rect(hipStream_t s, int nmat, double *C0, double *C1, int64_t ldc,
                         const double *A0, const double *A1, int64_t lda, const double *B,
                         int64_t ldb, int64_t rows, int mixed);
-void launch_diag_apply(hipStream_t s, double *S, int64_t ld, int64_t krow, const double *Linv,
-                       int64_t ncols, int64_t col_shift);
-void launch_update_nn(hipStream_t s, double *S, int64_t ld, const double *L, int64_t lda,
-                      int64_t r0, int64_t krow, int64_t rows, int64_t ncols, int64_t col_shift,
-                      int mixed);
+void launch_diag_apply(hipStream_t s, int nmat, double *S, int64_t ld, int64_t krow,
+                       const double *Linv, int64_t ncols, int64_t col_shift);
+void launch_update_nn(hipStream_t s, int nmat, double *S, int64_t ld, const double *L,
+                      int64_t lda, int64_t r0, int64_t krow, int64_t rows, int64_t ncols,
+                      int64_t col_shift, int K, int mixed);
 void launch_panel_reduce(hipStream_t s, double *Xa, double *Xn, int64_t ld, int64_t r0,
                          int64_t kcol, int64_t rows, const double *Linv, int64_t n,
                          double *partials);
 void launch_reduce_loglik(hipStream_t s, const double *A, int64_t lda, int64_t n, int T,
                           const double *logdet_part, double *out);
 void launch_reduce_terms(hipStream_t s, const double *partials, int64_t count, double *out);
+// adjoint gradient
+void launch_fill_identity(hipStream_t s, double *X, int64_t ld, int64_t rows, int64_t ncols);
+void launch_lauum(hipStream_t s, double *P, const double *X, int64_t ld, int64_t npad,
+                  int64_t ncols);
+void launch_extract_w(hipStream_t s, const double *X, int64_t ld, int64_t n, double *w);
+void launch_adjoint(hipStream_t s, const GenParams &gp, const double *xs, const double *ys,
+                    const Node *tab, const double *P, const double *w, double *part);
+void launch_reduce_pairs(hipStream_t s, const double *part, int64_t count, double *out);
 
 }  // namespace fbt

@@ -45,6 +45,54 @@ constexpr int GT = 64; // generation tile (rows x cols)
 
 __device__ __forceinline__ double acosh_ge1(double y) { return log(y + sqrt((y - 1.0) * (y + 1.0))); }
 
+// Paper mode (Supplementary A): d/dnu [x^nu K_nu(x)] by the first case that
+// applies: (2) x < 8.5, nu not within 1e-6 of an integer: the power series of
+// K_nu differentiated term by term (20 terms, coefficients per theta in
+// pc[PC_A1 / PC_B0 / PC_B1]); (3) 8.5 <= x < 30: the nu-derivative of the
+// uniform expansion of K_nu(nu z), z = x / nu (12 terms below x = 15, 8
+// beyond; the three sums are polynomials in p = (1 + z^2)^{-1/2} with
+// per-theta coefficients); (4) x >= 30, nu + 1/2 not within 1e-6 of an
+// integer: the nu-derivative of the Hankel expansion (5 terms); (5) otherwise
+// the central difference with lag 1e-9 of x^nu K_nu(x), whose two values
+// come from the quadrature with the cosh((nu +- lag) t) weights (skp, skm).
+__device__ __forceinline__ double paper_dxk(const GenParams &gp, double x, double lx, double skp,
+                                            double skm)
+{
+    const double nu = gp.nu;
+    const double *pc = gp.pc;
+    if (x < 8.5 && !gp.fd_small) {
+        const double x2 = 0.25 * x * x, x2nu = exp(2.0 * nu * lx), tl = 2.0 * lx * x2nu;
+        double acc = 0.0;
+        for (int k = PC_SER - 1; k >= 0; --k)
+            acc = fma(acc, x2, fma(tl, pc[PC_B0 + k], fma(x2nu, pc[PC_B1 + k], pc[PC_A1 + k])));
+        return acc;
+    }
+    if (x >= 8.5 && x < 30.0) {
+        const double z = x / nu, q = fma(z, z, 1.0), sq = sqrt(q), p = 1.0 / sq;
+        const double eta = sq + log(z / (1.0 + sq));
+        const double g = exp(nu * (lx - eta)) * pc[PC_SQPI] / sqrt(sq);
+        const double *d = pc + (x < 15.0 ? PC_D12 : PC_D8);
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int j = PC_DEB - 1; j >= 0; --j) {
+            s0 = fma(s0, p, d[j]);
+            s1 = fma(s1, p, d[PC_DEB + j]);
+            s2 = fma(s2, p, d[2 * PC_DEB + j]);
+        }
+        const double lead = pc[PC_LOGNU] + log(1.0 + sq) - 0.5 / (nu * q);
+        return g * (lead * s0 - s1 + (x * x / (nu * nu * nu)) / (q * sq) * s2);
+    }
+    if (x >= 30.0 && !gp.fd_large) {
+        const double r = 1.0 / x;
+        double acc = 0.0;
+        for (int k = PC_HAN - 1; k >= 0; --k)
+            acc = fma(acc, r, fma(lx, pc[PC_HA + k], pc[PC_HB + k]));
+        return 1.2533141373155003 * exp((nu - 0.5) * lx - x) * acc; // sqrt(pi / 2)
+    }
+    const double fp = exp((nu + PAPER_LAG) * lx - x) * skp;
+    const double fm = exp((nu - PAPER_LAG) * lx - x) * skm;
+    return (fp - fm) / (2.0 * PAPER_LAG);
+}
+
 __device__ __forceinline__ void matern3(const GenParams &gp, const Node *tab, double x, int mode,
                                         double &c, double &ca, double &cn)
 {
@@ -75,25 +123,39 @@ __device__ __forceinline__ void matern3(const GenParams &gp, const Node *tab, do
     int J = (int)(t / h) + 2;
     J = J < gp.len[L] ? J : gp.len[L];
     const Node *nd = tab + gp.off[L];
-    double sk = 0.0, sk1 = 0.0, sd = 0.0;
+    double sk = 0.0, sk1 = 0.0, sd = 0.0, skp = 0.0, skm = 0.0;
     if (mode == GEN_SIGMA) {
         for (int j = 0; j < J; ++j) {
             const double e = exp(-x * nd[j].cm1);
             sk = fma(e, nd[j].wk, sk);
         }
-    } else {
+    } else if (!gp.paper) {
         for (int j = 0; j < J; ++j) {
             const double e = exp(-x * nd[j].cm1);
             sk = fma(e, nd[j].wk, sk);
             sk1 = fma(e, nd[j].wk1, sk1);
             sd = fma(e, nd[j].wd, sd);
         }
+    } else {
+        for (int j = 0; j < J; ++j) {
+            const double e = exp(-x * nd[j].cm1);
+            sk = fma(e, nd[j].wk, sk);
+            sk1 = fma(e, nd[j].wk1, sk1);
+            skp = fma(e, nd[j].wkp, skp);
+            skm = fma(e, nd[j].wkm, skm);
+        }
     }
     const double lx = log(x);
     const double E = gp.cnu * exp(gp.nu * lx - x); // c_nu x^nu e^{-x}
     c = gp.sigma2 * E * sk;
     ca = gp.sigma2 / gp.alpha * x * E * sk1;
-    cn = gp.sigma2 * E * ((lx - gp.log2_psi) * sk + sd);
+    if (!gp.paper)
+        cn = gp.sigma2 * E * ((lx - gp.log2_psi) * sk + sd);
+    else
+        cn = (mode == GEN_SIGMA) ? 0.0
+                                 : gp.sigma2 * gp.cnu *
+                                       (paper_dxk(gp, x, lx, skp, skm) -
+                                        gp.log2_psi * exp(gp.nu * lx - x) * sk);
 }
 
 __global__ __launch_bounds__(256) void k_gen(GenParams gp, const double *__restrict__ xs,
@@ -399,12 +461,13 @@ void launch_potrf_diag(hipStream_t s, double *A, int64_t lda, int k, int64_t n, 
 // tile of A * B^T, each wave a 64 x 64 block held as 4 x 4 MFMA accumulators.
 // A is M-contiguous (element (m, k) at A[m + k lda]).  B is N-contiguous
 // (element (n, k) at B[n + k ldb]) or, with BKC, K-contiguous (at B[k + n ldb]).
+// With AKC, A is K-contiguous too (element (m, k) at A[k + m lda]).
 // K is streamed in chunks of 16 through double-buffered LDS.  With the MFMA
 // operands swapped (B fragment first), lane l holds in accumulator (i, j),
 // element r, the tile entry (16 i + l % 16, 16 j + l / 16 + 4 r): 16
 // consecutive rows per column, so stores are 128-byte segments.
 // ---------------------------------------------------------------------------
-template <int WM, int WN, bool BKC, bool NEG = false> struct Tile {
+template <int WM, int WN, bool BKC, bool NEG = false, bool AKC = false> struct Tile {
     static constexpr int BM = 64 * WM, BN = 64 * WN, KC = 16;
     static constexpr int LSA = BM + 4, LSB = BN + 4; // padded LDS rows (doubles)
     static constexpr int STAGE = KC * (LSA + LSB);
@@ -418,8 +481,14 @@ template <int WM, int WN, bool BKC, bool NEG = false> struct Tile {
         const int t = threadIdx.x;
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
-            const int q = t + 256 * i, m2 = q % (BM / 2), k = q / (BM / 2);
-            ra[i] = *(const double2 *)(A + 2 * m2 + (int64_t)(k0 + k) * lda);
+            const int q = t + 256 * i;
+            if (!AKC) {
+                const int m2 = q % (BM / 2), k = q / (BM / 2);
+                ra[i] = *(const double2 *)(A + 2 * m2 + (int64_t)(k0 + k) * lda);
+            } else {
+                const int k2 = q % (KC / 2), mm = q / (KC / 2);
+                ra[i] = *(const double2 *)(A + (k0 + 2 * k2) + (int64_t)mm * lda);
+            }
         }
 #pragma unroll
         for (int i = 0; i < NBL; ++i) {
@@ -439,13 +508,20 @@ template <int WM, int WN, bool BKC, bool NEG = false> struct Tile {
         double *As = st, *Bs = st + KC * LSA;
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
-            const int q = t + 256 * i, m2 = q % (BM / 2), k = q / (BM / 2);
+            const int q = t + 256 * i;
             double2 v = ra[i];
             if (NEG) {
                 v.x = -v.x;
                 v.y = -v.y;
             }
-            *(double2 *)(As + k * LSA + 2 * m2) = v;
+            if (!AKC) {
+                const int m2 = q % (BM / 2), k = q / (BM / 2);
+                *(double2 *)(As + k * LSA + 2 * m2) = v;
+            } else {
+                const int k2 = q % (KC / 2), mm = q / (KC / 2);
+                As[(2 * k2) * LSA + mm] = v.x;
+                As[(2 * k2 + 1) * LSA + mm] = v.y;
+            }
         }
 #pragma unroll
         for (int i = 0; i < NBL; ++i) {
@@ -548,7 +624,7 @@ template <int WM, int WN, bool BKC, bool NEG = false> struct Tile {
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 template <int WM, int WN, bool BKC> struct TileF {
-    static constexpr int BM = 64 * WM, BN = 64 * WN, KC = 32;
+    static constexpr int BM = 64 * WM, BN = 64 * WN, KC = 16;
     static constexpr int LSA = BM + 8, LSB = BN + 8; // padded LDS rows (floats)
     static constexpr int STAGE = KC * (LSA + LSB);
     static constexpr int LDS = 2 * STAGE;            // floats
@@ -620,7 +696,7 @@ template <int WM, int WN, bool BKC> struct TileF {
         }
     }
     // C(BM x BN, FP64) -= A(BM x K) * B(BN x K)^T computed in FP32
-    __device__ static void update(double *C, int64_t ldc, const double *A, int64_t lda,
+    __device__ __forceinline__ static void update(double *C, int64_t ldc, const double *A, int64_t lda,
                                   const double *B, int64_t ldb, int K, float *lds)
     {
         const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -644,16 +720,17 @@ template <int WM, int WN, bool BKC> struct TileF {
                 store(ra, rb, lds + ((c + 1) & 1) * STAGE);
             __syncthreads();
         }
+        // one per-lane base pointer; the (i, j, r) offsets are wave-uniform
+        double *cb = C + (wm * 64 + (lane & 15)) + (int64_t)(wn * 64 + 4 * (lane >> 4)) * ldc;
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int r = 0; r < 4; ++r) {
+                double *cc = cb + (int64_t)(16 * j + r) * ldc;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    double *c = C + (wm * 64 + 16 * i + (lane & 15)) +
-                                (int64_t)(wn * 64 + 16 * j + 4 * (lane >> 4) + r) * ldc;
-                    *c = *c - (double)acc[i][j][r];
-                }
+                for (int i = 0; i < 4; ++i)
+                    cc[16 * i] = cc[16 * i] - (double)acc[i][j][r];
+            }
     }
 };
 
@@ -769,7 +846,8 @@ void launch_panel(hipStream_t s, double *P, int64_t ld, int64_t rows, const doub
 // Left solve, diagonal block: S[krow:krow+NB, cols] = Linv * S[krow:krow+NB, cols]
 // (in place; a workgroup owns all NB rows of 64 columns).  Column tile c maps
 // to column 64 c, shifted by col_shift past the first half (two right-hand
-// sides stored side by side).
+// sides stored side by side; with one right-hand side only the first half is
+// launched).
 __global__ __launch_bounds__(256) void k_diag_apply(double *S, int64_t ld, int64_t krow,
                                                     const double *Linv, int64_t half_tiles,
                                                     int64_t col_shift)
@@ -792,17 +870,20 @@ __global__ __launch_bounds__(256) void k_diag_apply(double *S, int64_t ld, int64
                 Sb[TL::row(i, lane, wave) + (int64_t)TL::col(j, r, lane, 0) * ld] = acc[i][j][r];
 }
 
-void launch_diag_apply(hipStream_t s, double *S, int64_t ld, int64_t krow, const double *Linv,
-                       int64_t ncols, int64_t col_shift)
+void launch_diag_apply(hipStream_t s, int nmat, double *S, int64_t ld, int64_t krow,
+                       const double *Linv, int64_t ncols, int64_t col_shift)
 {
     const int64_t half = ncols / 64;
-    hipLaunchKernelGGL(k_diag_apply, dim3((unsigned)(2 * half)), dim3(256), 0, s, S, ld, krow,
+    if (half <= 0)
+        return;
+    hipLaunchKernelGGL(k_diag_apply, dim3((unsigned)(nmat * half)), dim3(256), 0, s, S, ld, krow,
                        Linv, half, col_shift);
 }
 
-// Left solve, update below the diagonal block:
-// S[r0 + 128 y, cols] -= L[r0 + 128 y, krow:krow+NB] * S[krow:krow+NB, cols].
-template <bool MIX>
+// Left solve, update below the diagonal block(s):
+// S[r0 + 128 y, cols] -= L[r0 + 128 y, krow:krow+K] * S[krow:krow+K, cols]
+// (K = NB for one panel, 2 NB for two consecutive panels at once).
+template <bool MIX, int K>
 __global__ __launch_bounds__(256) void k_update_nn(double *S, int64_t ld, const double *L,
                                                    int64_t lda, int64_t r0, int64_t krow,
                                                    int64_t half_tiles, int64_t col_shift)
@@ -815,29 +896,28 @@ __global__ __launch_bounds__(256) void k_update_nn(double *S, int64_t ld, const 
     const int64_t m0 = r0 + 128 * (int64_t)blockIdx.y;
     double *C = S + m0 + c0 * ld;
     if constexpr (MIX) {
-        TF::update(C, ld, L + m0 + krow * lda, lda, S + krow + c0 * ld, ld, NB, (float *)lds);
+        TF::update(C, ld, L + m0 + krow * lda, lda, S + krow + c0 * ld, ld, K, (float *)lds);
     } else {
         d4 acc[4][4];
         TL::load_c(acc, C, ld);
-        TL::run(acc, L + m0 + krow * lda, lda, S + krow + c0 * ld, ld, NB, lds);
+        TL::run(acc, L + m0 + krow * lda, lda, S + krow + c0 * ld, ld, K, lds);
         TL::store_c(acc, C, ld);
     }
 }
 
-void launch_update_nn(hipStream_t s, double *S, int64_t ld, const double *L, int64_t lda,
-                      int64_t r0, int64_t krow, int64_t rows, int64_t ncols, int64_t col_shift,
-                      int mixed)
+void launch_update_nn(hipStream_t s, int nmat, double *S, int64_t ld, const double *L,
+                      int64_t lda, int64_t r0, int64_t krow, int64_t rows, int64_t ncols,
+                      int64_t col_shift, int K, int mixed)
 {
-    if (rows <= 0)
-        return;
     const int64_t half = ncols / 128;
-    const dim3 g((unsigned)(2 * half), (unsigned)(rows / 128));
-    if (mixed)
-        hipLaunchKernelGGL(k_update_nn<true>, g, dim3(256), 0, s, S, ld, L, lda, r0, krow, half,
-                           col_shift);
-    else
-        hipLaunchKernelGGL(k_update_nn<false>, g, dim3(256), 0, s, S, ld, L, lda, r0, krow, half,
-                           col_shift);
+    if (rows <= 0 || half <= 0 || (K != NB && K != 2 * NB))
+        return;
+    const dim3 g((unsigned)(nmat * half), (unsigned)(rows / 128));
+    // the depth K is a template parameter: a known trip count keeps the
+    // main loop as fast as the fixed-depth form
+    auto kern = mixed ? (K == 2 * NB ? k_update_nn<true, 2 * NB> : k_update_nn<true, NB>)
+                      : (K == 2 * NB ? k_update_nn<false, 2 * NB> : k_update_nn<false, NB>);
+    hipLaunchKernelGGL(kern, g, dim3(256), 0, s, S, ld, L, lda, r0, krow, half, col_shift);
 }
 
 // ---------------------------------------------------------------------------
@@ -994,6 +1074,174 @@ __global__ __launch_bounds__(256) void k_reduce_terms(const double *partials, in
 void launch_reduce_terms(hipStream_t s, const double *partials, int64_t count, double *out)
 {
     hipLaunchKernelGGL(k_reduce_terms, dim3(1), dim3(256), 0, s, partials, count, out);
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint gradient (score without the W matrices).  With w = Sigma^{-1} Z,
+//   dl/dtheta_i = 1/2 w^T Sigma_i w - 1/2 tr(Sigma^{-1} Sigma_i)
+//               = sum_ab (1/2 w_a w_b - 1/2 (Sigma^{-1})_ab) (Sigma_i)_ab,
+// the Frobenius product of Sigma_i with 1/2 (w w^T - Sigma^{-1}) (Eq. (2)
+// with tr(A B) = <A, B^T>_F), so Sigma_i is regenerated entry by entry and is
+// never stored.  Sigma^{-1} comes from X = L'^{-1}: the bordered factor
+// [[L, 0], [y^T, 1]] has the inverse [[L^{-1}, 0], [-w^T, 1]] (row n is
+// -(L^{-T} y)^T), so P = X^T X restricted to a, b < n is Sigma^{-1} + w w^T
+// and the weight of entry (a, b) is w_a w_b - P_ab / 2.
+// ---------------------------------------------------------------------------
+
+// X[0:rows, 0:ncols] = identity
+__global__ __launch_bounds__(256) void k_fill_identity(double *X, int64_t ld, int64_t rows,
+                                                       int64_t ncols)
+{
+    const int64_t total = rows * ncols;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * 256) {
+        const int64_t r = i % rows, c = i / rows;
+        X[r + c * ld] = (r == c) ? 1.0 : 0.0;
+    }
+}
+
+void launch_fill_identity(hipStream_t s, double *X, int64_t ld, int64_t rows, int64_t ncols)
+{
+    if (rows <= 0 || ncols <= 0)
+        return;
+    hipLaunchKernelGGL(k_fill_identity, dim3(4096), dim3(256), 0, s, X, ld, rows, ncols);
+}
+
+// P = X^T X on the block-lower 128 x 128 tiles of the leading ncols x ncols
+// part, X lower triangular (npad x ncols):
+//   P[m0 + i][n0 + j] = sum_{k >= m0} X[k][m0 + i] X[k][n0 + j],
+// rows k < m0 being zero in column m0 + i.  Tiles starting at or beyond ncols
+// and the strictly upper 128-tile of each diagonal block are skipped.  Tile
+// pairs are enumerated with the block row ascending, so the longest sums
+// start first.
+__global__ __launch_bounds__(256) void k_lauum(double *P, const double *X, int64_t ld,
+                                               int64_t npad, int64_t ncols)
+{
+    using TL = Tile<2, 2, true, false, true>;
+    __shared__ double lds[TL::LDS];
+    const int64_t p = blockIdx.x >> 2;
+    const int s = blockIdx.x & 3;
+    int64_t I = (int64_t)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+    while ((I + 1) * (I + 2) / 2 <= p)
+        ++I;
+    while (I * (I + 1) / 2 > p)
+        --I;
+    const int64_t J = p - I * (I + 1) / 2;
+    const int64_t m0 = I * NB + 128 * (s >> 1), n0 = J * NB + 128 * (s & 1);
+    if (m0 >= ncols || n0 >= ncols || n0 > m0)
+        return;
+    d4 acc[4][4];
+    TL::zero(acc);
+    TL::run(acc, X + m0 + m0 * ld, ld, X + m0 + n0 * ld, ld, (int)(npad - m0), lds);
+    TL::store_c(acc, P + m0 + n0 * ld, ld);
+}
+
+void launch_lauum(hipStream_t s, double *P, const double *X, int64_t ld, int64_t npad,
+                  int64_t ncols)
+{
+    const int64_t T = npad / NB;
+    const int64_t pairs = T * (T + 1) / 2;
+    hipLaunchKernelGGL(k_lauum, dim3((unsigned)(4 * pairs)), dim3(256), 0, s, P, X, ld, npad,
+                       ncols);
+}
+
+// w[a] = -X[n][a] = (Sigma^{-1} Z)_a for a < n
+__global__ __launch_bounds__(256) void k_extract_w(const double *X, int64_t ld, int64_t n,
+                                                   double *w)
+{
+    const int64_t a = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (a < n)
+        w[a] = -X[n + a * ld];
+}
+
+void launch_extract_w(hipStream_t s, const double *X, int64_t ld, int64_t n, double *w)
+{
+    hipLaunchKernelGGL(k_extract_w, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, ld,
+                       n, w);
+}
+
+// Per 64 x 64 tile pair (ti >= tj) of the strictly lower triangle a > b
+// (a, b < n): 2 sum (w_a w_b - P_ab / 2) (Sigma_alpha)_ab and the same with
+// Sigma_nu, with the derivative entries regenerated as in k_gen.  The factor 2
+// counts the mirrored entry; the diagonal contributes nothing (both
+// derivatives vanish at distance 0).  Two partials per workgroup.
+__global__ __launch_bounds__(256) void k_adjoint(GenParams gp, const double *__restrict__ xs,
+                                                 const double *__restrict__ ys,
+                                                 const Node *__restrict__ gtab,
+                                                 const double *__restrict__ P,
+                                                 const double *__restrict__ w,
+                                                 double *__restrict__ part)
+{
+    __shared__ Node tab[TAB_MAX];
+    __shared__ double sh[4];
+    const int t = threadIdx.x;
+    const int ntab = gp.off[NLEV - 1] + gp.len[NLEV - 1];
+    for (int i = t; i < ntab; i += 256)
+        tab[i] = gtab[i];
+    const int64_t p = blockIdx.x;
+    int64_t ti = (int64_t)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+    while ((ti + 1) * (ti + 2) / 2 <= p)
+        ++ti;
+    while (ti * (ti + 1) / 2 > p)
+        --ti;
+    const int64_t tj = p - ti * (ti + 1) / 2;
+    const bool diag = (ti == tj);
+    const int al = t & 63;
+    const int64_t a = ti * GT + al;
+    const int64_t n = gp.n, ld = gp.ld;
+    const double xa = a < n ? xs[a] : 0.0, ya = a < n ? ys[a] : 0.0, wa = a < n ? w[a] : 0.0;
+    const double inv_alpha = 1.0 / gp.alpha;
+    __syncthreads();
+    double sa = 0.0, sn = 0.0;
+#pragma unroll 1
+    for (int e = 0; e < 16; ++e) {
+        const int bl = (t >> 6) * 16 + e;
+        const int64_t b = tj * GT + bl;
+        if (a >= n || b >= n || (diag && al <= bl))
+            continue;
+        const double dx = xa - xs[b], dy = ya - ys[b];
+        double c, ca, cn;
+        matern3(gp, tab, sqrt(dx * dx + dy * dy) * inv_alpha, GEN_DERIV, c, ca, cn);
+        const double g = fma(wa, w[b], -0.5 * P[a + b * ld]);
+        sa = fma(g, ca, sa);
+        sn = fma(g, cn, sn);
+    }
+    sa = block_sum(sa, sh);
+    sn = block_sum(sn, sh);
+    if (t == 0) {
+        part[2 * p] = 2.0 * sa;
+        part[2 * p + 1] = 2.0 * sn;
+    }
+}
+
+void launch_adjoint(hipStream_t s, const GenParams &gp, const double *xs, const double *ys,
+                    const Node *tab, const double *P, const double *w, double *part)
+{
+    const int64_t nt = (gp.n + GT - 1) / GT;
+    const int64_t pairs = nt * (nt + 1) / 2;
+    hipLaunchKernelGGL(k_adjoint, dim3((unsigned)pairs), dim3(256), 0, s, gp, xs, ys, tab, P, w,
+                       part);
+}
+
+// out[0..1] = sums of the `count` partial pairs, in a fixed order
+__global__ __launch_bounds__(256) void k_reduce_pairs(const double *part, int64_t count,
+                                                      double *out)
+{
+    __shared__ double sh[4];
+    const int t = threadIdx.x;
+    for (int q = 0; q < 2; ++q) {
+        double v = 0.0;
+        for (int64_t g = t; g < count; g += 256)
+            v += part[2 * g + q];
+        v = block_sum(v, sh);
+        if (t == 0)
+            out[q] = v;
+    }
+}
+
+void launch_reduce_pairs(hipStream_t s, const double *part, int64_t count, double *out)
+{
+    hipLaunchKernelGGL(k_reduce_pairs, dim3(1), dim3(256), 0, s, part, count, out);
 }
 
 }  // namespace fbt

@@ -43,6 +43,9 @@ def test_null_arguments_are_rejected():
     th = np.array([1.0, 0.1, 0.5])
     assert L.fbt_loglik(None, th.ctypes.data, th.ctypes.data) == fbt.EINVAL
     assert L.fbt_eval(None, th.ctypes.data, None, None, None) == fbt.EINVAL
+    # pointers as the binding passes them (c_void_p), for the adjoint entry point
+    out = np.zeros(4)
+    assert L.fbt_grad(None, fbt._ptr(th), fbt._ptr(out), fbt._ptr(out[1:]), None) == fbt.EINVAL
     assert L.fbt_create(None, None) == fbt.EINVAL
     assert L.fbt_fit_evaluator(None, None, None) == fbt.EINVAL
     assert L.fbt_set_timing(None, 1) == fbt.EINVAL
