@@ -93,6 +93,52 @@ def copy_calibration():
                       "repeats": 3}), flush=True)
 
 
+def batch_bench(args):
+    """One Fisher-BT round over many independent fields (loglik + score +
+    Fisher for every field), through the batch executor."""
+    import numpy as np
+
+    import paper_2601_11437_amd as fbt
+    from paper_2601_11437_amd import synth
+
+    t0 = time.perf_counter()
+    fields, thetas = synth.batch_workload(args.batch)
+    log("batch data: %d fields generated in %.1f s" % (len(fields), time.perf_counter() - t0))
+    b = fbt.Batch(args.batch_workers)
+    b.set_fields(fields)
+    gen = synth.rng(5000 + 104729)
+    redraws = 0
+    for _ in range(50):   # evaluation points whose covariance is not PD are redrawn
+        _, _, _, st = b.eval(thetas, fbt.Batch.LOGLIK)
+        bad = st != fbt.OK
+        if not bad.any():
+            break
+        redraws += int(bad.sum())
+        thetas = synth.batch_redraw_thetas(thetas, bad, gen)
+    for _ in range(args.warmup):
+        b.eval(thetas, fbt.Batch.EVAL)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ll, sc, fi, st = b.eval(thetas, fbt.Batch.EVAL)
+    dt = time.perf_counter() - t0
+    b.close()
+    ns = np.array([z.size for _, z in fields], dtype=np.float64)
+    exec_flops = float(np.sum(3.0 * ns ** 3)) * args.steps
+    nf = len(fields)
+    out = {"metric": "loglik+score+Fisher field evaluations/s, %d fields n~U[500,4000]" % nf,
+           "value": nf * args.steps / dt, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "%d independent Matern fields, n_f ~ U[500, 4000] uniform points, "
+                                  "theta_f uniform in [0.5,2]x[0.02,0.3]x[0.3,2.5], one full "
+                                  "evaluation per field per step" % nf,
+                      "workers": args.batch_workers, "theta_redraws": redraws},
+           "executed_tflops": exec_flops / dt / 1e12,
+           "fp64_frac": exec_flops / dt / 1e12 / PEAK_FP64_TFLOPS,
+           "failed_fields": int(np.sum(st != fbt.OK))}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,7 +151,13 @@ def main():
                     help="skip the mixed-precision and adjoint comparisons (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the 1 GiB copy used to scale the HBM byte counters")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="instead of the n=20k evaluation, time one round over this many fields")
+    ap.add_argument("--batch-workers", type=int, default=8)
     args = ap.parse_args()
+    if args.batch and args.gpus == 1:
+        batch_bench(args)
+        return
     if args.copy_calibration:
         copy_calibration()
         return

@@ -9,7 +9,6 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
-#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -38,6 +37,7 @@ struct fbt_ctx {
     int device = 0;
     hipStream_t stream = nullptr;  // s0: the caller's stream; the critical path runs here
     hipStream_t stream2 = nullptr; // s1: bulk trailing updates (lookahead), joined back to s0
+    hipStream_t stream3 = nullptr; // s1 of the factorisation: bulk updates on all CUs but a reserve
     hipEvent_t evP = nullptr, evB = nullptr;
     bool own_stream = false;
     int precision = FBT_FP64; // see fbt_precision
@@ -73,8 +73,8 @@ struct fbt_ctx {
 
 namespace {
 
-// CUs kept free of the bulk-update stream (see fbt_create)
-constexpr int BULK_CU_RESERVE = 0;
+// CUs kept free of the factorisation's bulk stream: one per XCD of MI355X
+constexpr int FACT_CU_RESERVE = 8;
 
 // node table followed by the paper-mode coefficient table (one upload)
 constexpr size_t TAB_BYTES = TAB_MAX * sizeof(Node) + PC_SIZE * sizeof(double);
@@ -373,7 +373,7 @@ fbt_status factorize(fbt_ctx *c, const double *th, int mode)
     c->factor_valid = false;
     const int64_t npad = c->npad, ld = c->ld, n = c->n;
     const int T = c->T;
-    hipStream_t s0 = c->stream, s1 = c->stream2;
+    hipStream_t s0 = c->stream, s1 = c->stream3;
     double *A = c->A;
     const double dNB = NB;
     const int mix = c->precision == FBT_MIXED_FP32_ALL; // Cholesky updates in FP32
@@ -381,32 +381,49 @@ fbt_status factorize(fbt_ctx *c, const double *th, int mode)
     launch_init_info(s0, c->info);
     TIMED(c, s0, KC_GEN, 0.0, launch_gen(s0, gp, c->x, c->y, c->z, c->tab, A, c->S2,
                                            c->S2 + npad * ld, mode));
-    TIMED(c, s0, KC_DIAG, 2.0 * dNB * dNB * dNB / 3.0,
-          launch_potrf_diag(s0, A, ld, 0, n, Lk(0), c->logdet, c->info));
-    if (T > 1)
-        TIMED(c, s0, KC_PANEL, std::max(0.0, double(n - NB)) * dNB * dNB,
-              launch_panel(s0, A + NB, ld, npad - NB, Lk(0)));
-    HIPCHK(c, hipEventRecord(c->evP, s0));
+    // Block columns are taken in pairs (b, b + 1).  On s0: diagonal block b,
+    // panel b, update of block column b + 1 by panel b, diagonal block b + 1,
+    // panel b + 1.  The trailing matrix is then updated by both panels at once
+    // (K = 2 NB): s0 updates the next pair of block columns (lookahead) once
+    // s1 has finished the previous bulk update; s1 updates the rest.
+    auto rows_from = [&](int64_t r) { return (double)std::max<int64_t>(0, n - r); };
     HIPCHK(c, hipEventRecord(c->evB, s0));
-    for (int k = 0; k + 1 < T; ++k) {
-        const int64_t r1 = (int64_t)(k + 1) * NB, r2 = r1 + NB, kc = (int64_t)k * NB;
-        const double m1 = std::max<int64_t>(0, n - r1), m2 = std::max<int64_t>(0, n - r2);
-        HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
-        TIMED(c, s0, KC_SYRK, std::max(0.0, 2.0 * m1 * dNB * dNB - dNB * dNB * dNB),
-              launch_update_rect(s0, 1, A + r1 + r1 * ld, nullptr, ld, A + r1 + kc * ld, nullptr,
-                                 ld, A + r1 + kc * ld, ld, npad - r1, mix));
+    for (int b = 0; b < T; b += 2) {
+        const int nb = std::min(2, T - b);
+        const int64_t r0 = (int64_t)b * NB, rn = r0 + (int64_t)nb * NB;
+        const int K = nb * NB;
         TIMED(c, s0, KC_DIAG, 2.0 * dNB * dNB * dNB / 3.0,
-              launch_potrf_diag(s0, A, ld, k + 1, n, Lk(k + 1), c->logdet, c->info));
-        if (k + 2 < T)
-            TIMED(c, s0, KC_PANEL, m2 * dNB * dNB,
-                  launch_panel(s0, A + r2 + r1 * ld, ld, npad - r2, Lk(k + 1)));
-        HIPCHK(c, hipStreamWaitEvent(s1, c->evP, 0));
-        if (k + 2 < T)
-            TIMED(c, s1, KC_SYRK, m2 * m2 * dNB,
-                  launch_update_lower(s1, 1, A + r2 + r2 * ld, nullptr, ld, A + r2 + kc * ld,
-                                      nullptr, ld, A + r2 + kc * ld, ld, T - k - 2, mix));
-        HIPCHK(c, hipEventRecord(c->evB, s1));
+              launch_potrf_diag(s0, A, ld, b, n, Lk(b), c->logdet, c->info));
+        if (b + 1 < T)
+            TIMED(c, s0, KC_PANEL, rows_from(r0 + NB) * dNB * dNB,
+                  launch_panel(s0, A + r0 + NB + r0 * ld, ld, npad - r0 - NB, Lk(b)));
+        if (nb == 2) {
+            const int64_t r1 = r0 + NB;
+            TIMED(c, s0, KC_SYRK, 2.0 * rows_from(r1) * dNB * dNB,
+                  launch_update_rect(s0, 1, A + r1 + r1 * ld, nullptr, ld, A + r1 + r0 * ld, nullptr,
+                                     ld, A + r1 + r0 * ld, ld, npad - r1, NB, NB, mix));
+            TIMED(c, s0, KC_DIAG, 2.0 * dNB * dNB * dNB / 3.0,
+                  launch_potrf_diag(s0, A, ld, b + 1, n, Lk(b + 1), c->logdet, c->info));
+            if (b + 2 < T)
+                TIMED(c, s0, KC_PANEL, rows_from(rn) * dNB * dNB,
+                      launch_panel(s0, A + rn + r1 * ld, ld, npad - rn, Lk(b + 1)));
+        }
         HIPCHK(c, hipEventRecord(c->evP, s0));
+        if (rn >= npad)
+            break;
+        const int64_t la = std::min<int64_t>(2 * NB, npad - rn); // columns of the next pair
+        HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
+        TIMED(c, s0, KC_SYRK, 2.0 * rows_from(rn) * (double)la * K,
+              launch_update_rect(s0, 1, A + rn + rn * ld, nullptr, ld, A + rn + r0 * ld, nullptr,
+                                 ld, A + rn + r0 * ld, ld, npad - rn, la, K, mix));
+        HIPCHK(c, hipStreamWaitEvent(s1, c->evP, 0));
+        const int64_t t0 = rn + la;
+        if (t0 < npad)
+            TIMED(c, s1, KC_SYRK, rows_from(t0) * rows_from(t0) * K,
+                  launch_update_lower(s1, 1, A + t0 + t0 * ld, nullptr, ld, A + t0 + r0 * ld,
+                                      nullptr, ld, A + t0 + r0 * ld, ld, (int)((npad - t0) / NB), K,
+                                      mix));
+        HIPCHK(c, hipEventRecord(c->evB, s1));
     }
     HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
     TIMED(c, s0, KC_RED, 0.0, launch_reduce_loglik(s0, A, ld, n, T, c->logdet, c->out));
@@ -501,33 +518,53 @@ fbt_status derivative_terms(fbt_ctx *c, const double *th, double terms[9])
     }
     HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
 
-    // right solve W = X L'^{-T} (block-lower) with the fused reductions
+    // Right solve W = X L'^{-T} (block-lower) with the fused reductions, block
+    // columns in pairs as in the factorisation: on s0 the panel of block b
+    // (with the trace reductions), the update of block column b + 1 by it and
+    // the panel of block b + 1; then the lookahead update of the next pair of
+    // block columns by both panels (K = 2 NB) on s0 and the rest on s1.
     int64_t groups = 0;
-    TIMED(c, s0, KC_RPANEL, 2.0 * 2.0 * dn * dNB * dNB,
-          launch_panel_reduce(s0, Sa, Sn, ld, 0, 0, npad, Lk(0), n, c->partials));
-    groups += npad / 64;
-    HIPCHK(c, hipEventRecord(c->evP, s0));
     HIPCHK(c, hipEventRecord(c->evB, s0));
-    for (int k = 0; k + 1 < T; ++k) {
-        const int64_t kc = (int64_t)k * NB, r1 = kc + NB, r2 = r1 + NB;
-        const double m1 = std::max<int64_t>(0, n - r1), m2 = std::max<int64_t>(0, n - r2);
-        HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
-        TIMED(c, s0, KC_RUPD, 2.0 * 2.0 * m1 * dNB * dNB,
-              launch_update_rect(s0, 2, Sa + r1 + r1 * ld, Sn + r1 + r1 * ld, ld,
-                                 Sa + r1 + kc * ld, Sn + r1 + kc * ld, ld, A + r1 + kc * ld, ld,
-                                 npad - r1, mix));
-        TIMED(c, s0, KC_RPANEL, 2.0 * 2.0 * m1 * dNB * dNB,
-              launch_panel_reduce(s0, Sa, Sn, ld, r1, r1, npad - r1, Lk(k + 1), n,
+    for (int b = 0; b < T; b += 2) {
+        const int nb = std::min(2, T - b);
+        const int64_t r0 = (int64_t)b * NB, rn = r0 + (int64_t)nb * NB;
+        const int K = nb * NB;
+        const double m0r = std::max<int64_t>(0, n - r0);
+        TIMED(c, s0, KC_RPANEL, 2.0 * 2.0 * m0r * dNB * dNB,
+              launch_panel_reduce(s0, Sa, Sn, ld, r0, r0, npad - r0, Lk(b), n,
                                   c->partials + 8 * groups));
-        groups += (npad - r1) / 64;
-        HIPCHK(c, hipStreamWaitEvent(s1, c->evP, 0));
-        if (k + 2 < T)
-            TIMED(c, s1, KC_RUPD, 2.0 * m2 * m2 * dNB,
-                  launch_update_lower(s1, 2, Sa + r2 + r2 * ld, Sn + r2 + r2 * ld, ld,
-                                      Sa + r2 + kc * ld, Sn + r2 + kc * ld, ld, A + r2 + kc * ld,
-                                      ld, T - k - 2, mix));
-        HIPCHK(c, hipEventRecord(c->evB, s1));
+        groups += (npad - r0) / 64;
+        if (nb == 2) {
+            const int64_t r1 = r0 + NB;
+            const double m1 = std::max<int64_t>(0, n - r1);
+            TIMED(c, s0, KC_RUPD, 2.0 * 2.0 * m1 * dNB * dNB,
+                  launch_update_rect(s0, 2, Sa + r1 + r1 * ld, Sn + r1 + r1 * ld, ld,
+                                     Sa + r1 + r0 * ld, Sn + r1 + r0 * ld, ld, A + r1 + r0 * ld,
+                                     ld, npad - r1, NB, NB, mix));
+            TIMED(c, s0, KC_RPANEL, 2.0 * 2.0 * m1 * dNB * dNB,
+                  launch_panel_reduce(s0, Sa, Sn, ld, r1, r1, npad - r1, Lk(b + 1), n,
+                                      c->partials + 8 * groups));
+            groups += (npad - r1) / 64;
+        }
         HIPCHK(c, hipEventRecord(c->evP, s0));
+        if (rn >= npad)
+            break;
+        const int64_t la = std::min<int64_t>(2 * NB, npad - rn);
+        const double mn = std::max<int64_t>(0, n - rn);
+        HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
+        TIMED(c, s0, KC_RUPD, 2.0 * 2.0 * mn * (double)la * K,
+              launch_update_rect(s0, 2, Sa + rn + rn * ld, Sn + rn + rn * ld, ld,
+                                 Sa + rn + r0 * ld, Sn + rn + r0 * ld, ld, A + rn + r0 * ld, ld,
+                                 npad - rn, la, K, mix));
+        HIPCHK(c, hipStreamWaitEvent(s1, c->evP, 0));
+        const int64_t t0 = rn + la;
+        const double mt = std::max<int64_t>(0, n - t0);
+        if (t0 < npad)
+            TIMED(c, s1, KC_RUPD, 2.0 * mt * mt * K,
+                  launch_update_lower(s1, 2, Sa + t0 + t0 * ld, Sn + t0 + t0 * ld, ld,
+                                      Sa + t0 + r0 * ld, Sn + t0 + r0 * ld, ld, A + t0 + r0 * ld,
+                                      ld, (int)((npad - t0) / NB), K, mix));
+        HIPCHK(c, hipEventRecord(c->evB, s1));
     }
     HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
     TIMED(c, s0, KC_RED, 0.0, launch_reduce_terms(s0, c->partials, groups, c->out));
@@ -729,33 +766,27 @@ fbt_status fbt_create(const fbt_config *cfg, fbt_ctx **out)
         }
         c->own_stream = true;
     }
-    // s1 (the bulk trailing updates) runs on all CUs but `reserve`, spread over
-    // the device, so that the critical-path kernels on s0 (diagonal blocks,
-    // panels) find free CUs instead of queueing behind bulk workgroups.
     {
-        int reserve = BULK_CU_RESERVE;
-        if (const char *e = std::getenv("FBT_BULK_CU_RESERVE"))
-            reserve = std::atoi(e);
+        // The factorisation's bulk stream leaves one CU of every XCD free.  Its
+        // critical path is a single-workgroup kernel (the diagonal block, 144 KB
+        // of LDS and 312 registers per lane) that fits only on a CU no bulk
+        // workgroup occupies; without a reserve it waits for the whole trailing
+        // update to drain.  Workgroups are spread over the XCDs round-robin, so
+        // every XCD needs a free CU.  CU mask bit i is CU i / NXCD of XCD
+        // i % NXCD (measured: clearing bits 0..7 reserves one CU per XCD).
         const int ncu = prop.multiProcessorCount;
-        hipError_t er;
-        if (reserve > 0 && reserve < ncu) {
-            std::vector<uint32_t> mask((ncu + 31) / 32, 0u);
-            for (int i = 0; i < ncu; ++i)
+        std::vector<uint32_t> mask((ncu + 31) / 32, 0u);
+        for (int i = 0; i < ncu; ++i)
+            if (i >= FACT_CU_RESERVE)
                 mask[i / 32] |= 1u << (i % 32);
-            for (int r = 0; r < reserve; ++r) {
-                const int cu = (int)((int64_t)r * ncu / reserve);
-                mask[cu / 32] &= ~(1u << (cu % 32));
-            }
-            er = hipExtStreamCreateWithCUMask(&c->stream2, (uint32_t)mask.size(), mask.data());
-        } else {
-            er = hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking);
-        }
-        if (er != hipSuccess) {
+        if (hipExtStreamCreateWithCUMask(&c->stream3, (uint32_t)mask.size(), mask.data()) !=
+            hipSuccess) {
             fbt_destroy(c);
             return FBT_EDEVICE;
         }
     }
-    if (hipEventCreateWithFlags(&c->evP, hipEventDisableTiming) != hipSuccess ||
+    if (hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->evP, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->evB, hipEventDisableTiming) != hipSuccess) {
         fbt_destroy(c);
         return FBT_EDEVICE;
@@ -789,6 +820,10 @@ void fbt_destroy(fbt_ctx *c)
     if (c->stream2) {
         (void)hipStreamSynchronize(c->stream2);
         (void)hipStreamDestroy(c->stream2);
+    }
+    if (c->stream3) {
+        (void)hipStreamSynchronize(c->stream3);
+        (void)hipStreamDestroy(c->stream3);
     }
     if (c->evP)
         (void)hipEventDestroy(c->evP);

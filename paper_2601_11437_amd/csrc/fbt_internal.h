@@ -63,10 +63,10 @@ void launch_potrf_diag(hipStream_t s, double *A, int64_t lda, int k, int64_t n, 
 void launch_panel(hipStream_t s, double *P, int64_t ld, int64_t rows, const double *Linv);
 void launch_update_lower(hipStream_t s, int nmat, double *C0, double *C1, int64_t ldc,
                          const double *A0, const double *A1, int64_t lda, const double *B,
-                         int64_t ldb, int nblk, int mixed);
+                         int64_t ldb, int nblk, int K, int mixed);
 void launch_update_rect(hipStream_t s, int nmat, double *C0, double *C1, int64_t ldc,
                         const double *A0, const double *A1, int64_t lda, const double *B,
-                        int64_t ldb, int64_t rows, int mixed);
+                        int64_t ldb, int64_t rows, int64_t ncol, int K, int mixed);
 void launch_diag_apply(hipStream_t s, int nmat, double *S, int64_t ld, int64_t krow,
                        const double *Linv, int64_t ncols, int64_t col_shift);
 void launch_update_nn(hipStream_t s, int nmat, double *S, int64_t ld, const double *L,

@@ -695,9 +695,20 @@ template <int WM, int WN, bool BKC> struct TileF {
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[j], a[i], acc[i][j], 0, 0, 0);
         }
     }
-    // C(BM x BN, FP64) -= A(BM x K) * B(BN x K)^T computed in FP32
+    // C(BM x BN, FP64) -= A(BM x K) * B(BN x K)^T computed in FP32; the FP32
+    // sums cover NB-deep slices of K and each slice is added into C in FP64,
+    // so the FP32 accumulation error does not grow with K beyond NB.
     __device__ __forceinline__ static void update(double *C, int64_t ldc, const double *A, int64_t lda,
                                   const double *B, int64_t ldb, int K, float *lds)
+    {
+#pragma unroll 1
+        for (int k0 = 0; k0 < K; k0 += NB)
+            update_slice(C, ldc, A + (int64_t)k0 * lda, lda, BKC ? B + k0 : B + (int64_t)k0 * ldb,
+                         ldb, K - k0 < NB ? K - k0 : NB, lds);
+    }
+    __device__ __forceinline__ static void update_slice(double *C, int64_t ldc, const double *A,
+                                                        int64_t lda, const double *B, int64_t ldb,
+                                                        int K, float *lds)
     {
         const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
         const int wm = wave % WM, wn = wave / WM;
@@ -736,8 +747,9 @@ template <int WM, int WN, bool BKC> struct TileF {
 
 // C -= A * B^T over the block-lower tiles of a trailing matrix of nblk x nblk
 // NB-blocks (128 x 128 tiles; both 128-tiles above the diagonal inside a
-// diagonal NB-block are included).  blockIdx.y selects (C0, A0) or (C1, A1).
-template <bool MIX>
+// diagonal NB-block are included), depth K (one or two panels).  blockIdx.y
+// selects (C0, A0) or (C1, A1).
+template <bool MIX, int K = NB>
 __global__ __launch_bounds__(256) void k_update_lower(double *C0, double *C1, int64_t ldc,
                                                       const double *A0, const double *A1,
                                                       int64_t lda, const double *B, int64_t ldb)
@@ -757,18 +769,19 @@ __global__ __launch_bounds__(256) void k_update_lower(double *C0, double *C1, in
     double *C = (blockIdx.y ? C1 : C0) + m0 + n0 * ldc;
     const double *A = (blockIdx.y ? A1 : A0) + m0;
     if constexpr (MIX) {
-        TF::update(C, ldc, A, lda, B + n0, ldb, NB, (float *)lds);
+        TF::update(C, ldc, A, lda, B + n0, ldb, K, (float *)lds);
     } else {
         d4 acc[4][4];
         TL::load_c(acc, C, ldc);
-        TL::run(acc, A, lda, B + n0, ldb, NB, lds);
+        TL::run(acc, A, lda, B + n0, ldb, K, lds);
         TL::store_c(acc, C, ldc);
     }
 }
 
-// C -= A * B^T on a rectangle of rows x NB (128 x 128 tiles): the next block
-// column of a trailing update (lookahead).  blockIdx.z selects the matrix.
-template <bool MIX>
+// C -= A * B^T on a rectangle of rows x ncol (128 x 128 tiles, depth K): the
+// next block column(s) of a trailing update (lookahead).  blockIdx.z selects
+// the matrix.
+template <bool MIX, int K = NB>
 __global__ __launch_bounds__(256) void k_update_rect(double *C0, double *C1, int64_t ldc,
                                                      const double *A0, const double *A1,
                                                      int64_t lda, const double *B, int64_t ldb)
@@ -780,40 +793,55 @@ __global__ __launch_bounds__(256) void k_update_rect(double *C0, double *C1, int
     double *C = (blockIdx.z ? C1 : C0) + m0 + n0 * ldc;
     const double *A = (blockIdx.z ? A1 : A0) + m0;
     if constexpr (MIX) {
-        TF::update(C, ldc, A, lda, B + n0, ldb, NB, (float *)lds);
+        TF::update(C, ldc, A, lda, B + n0, ldb, K, (float *)lds);
     } else {
         d4 acc[4][4];
         TL::load_c(acc, C, ldc);
-        TL::run(acc, A, lda, B + n0, ldb, NB, lds);
+        TL::run(acc, A, lda, B + n0, ldb, K, lds);
         TL::store_c(acc, C, ldc);
     }
 }
 
+// Both launchers take K = NB or 2 NB.  The FP32 form applies two panels as
+// two NB-deep launches (its NB-deep kernel keeps four workgroups per CU);
+// A and B then advance by NB columns.
 void launch_update_rect(hipStream_t s, int nmat, double *C0, double *C1, int64_t ldc,
                         const double *A0, const double *A1, int64_t lda, const double *B,
-                        int64_t ldb, int64_t rows, int mixed)
+                        int64_t ldb, int64_t rows, int64_t ncol, int K, int mixed)
 {
-    if (rows <= 0)
+    if (rows <= 0 || ncol <= 0 || (K != NB && K != 2 * NB))
         return;
-    const dim3 g((unsigned)(rows / 128), NB / 128, nmat);
-    if (mixed)
-        hipLaunchKernelGGL(k_update_rect<true>, g, dim3(256), 0, s, C0, C1, ldc, A0, A1, lda, B, ldb);
-    else
-        hipLaunchKernelGGL(k_update_rect<false>, g, dim3(256), 0, s, C0, C1, ldc, A0, A1, lda, B, ldb);
+    const dim3 g((unsigned)(rows / 128), (unsigned)(ncol / 128), nmat);
+    if (mixed) {
+        for (int p = 0; p < K / NB; ++p) {
+            const int64_t o = (int64_t)p * NB;
+            hipLaunchKernelGGL(k_update_rect<true>, g, dim3(256), 0, s, C0, C1, ldc, A0 + o * lda,
+                               A1 ? A1 + o * lda : nullptr, lda, B + o * ldb, ldb);
+        }
+        return;
+    }
+    auto kern = K == 2 * NB ? k_update_rect<false, 2 * NB> : k_update_rect<false, NB>;
+    hipLaunchKernelGGL(kern, g, dim3(256), 0, s, C0, C1, ldc, A0, A1, lda, B, ldb);
 }
 
 void launch_update_lower(hipStream_t s, int nmat, double *C0, double *C1, int64_t ldc,
                          const double *A0, const double *A1, int64_t lda, const double *B,
-                         int64_t ldb, int nblk, int mixed)
+                         int64_t ldb, int nblk, int K, int mixed)
 {
-    if (nblk <= 0)
+    if (nblk <= 0 || (K != NB && K != 2 * NB))
         return;
     const int64_t pairs = (int64_t)nblk * (nblk + 1) / 2;
     const dim3 g((unsigned)(4 * pairs), nmat);
-    if (mixed)
-        hipLaunchKernelGGL(k_update_lower<true>, g, dim3(256), 0, s, C0, C1, ldc, A0, A1, lda, B, ldb);
-    else
-        hipLaunchKernelGGL(k_update_lower<false>, g, dim3(256), 0, s, C0, C1, ldc, A0, A1, lda, B, ldb);
+    if (mixed) {
+        for (int p = 0; p < K / NB; ++p) {
+            const int64_t o = (int64_t)p * NB;
+            hipLaunchKernelGGL(k_update_lower<true>, g, dim3(256), 0, s, C0, C1, ldc,
+                               A0 + o * lda, A1 ? A1 + o * lda : nullptr, lda, B + o * ldb, ldb);
+        }
+        return;
+    }
+    auto kern = K == 2 * NB ? k_update_lower<false, 2 * NB> : k_update_lower<false, NB>;
+    hipLaunchKernelGGL(kern, g, dim3(256), 0, s, C0, C1, ldc, A0, A1, lda, B, ldb);
 }
 
 // Panel solve of the factorisation: P (rows x NB, in place) = P Linv^T.
@@ -883,7 +911,7 @@ void launch_diag_apply(hipStream_t s, int nmat, double *S, int64_t ld, int64_t k
 // Left solve, update below the diagonal block(s):
 // S[r0 + 128 y, cols] -= L[r0 + 128 y, krow:krow+K] * S[krow:krow+K, cols]
 // (K = NB for one panel, 2 NB for two consecutive panels at once).
-template <bool MIX, int K>
+template <bool MIX, int K = NB>
 __global__ __launch_bounds__(256) void k_update_nn(double *S, int64_t ld, const double *L,
                                                    int64_t lda, int64_t r0, int64_t krow,
                                                    int64_t half_tiles, int64_t col_shift)
@@ -913,10 +941,16 @@ void launch_update_nn(hipStream_t s, int nmat, double *S, int64_t ld, const doub
     if (rows <= 0 || half <= 0 || (K != NB && K != 2 * NB))
         return;
     const dim3 g((unsigned)(nmat * half), (unsigned)(rows / 128));
-    // the depth K is a template parameter: a known trip count keeps the
-    // main loop as fast as the fixed-depth form
-    auto kern = mixed ? (K == 2 * NB ? k_update_nn<true, 2 * NB> : k_update_nn<true, NB>)
-                      : (K == 2 * NB ? k_update_nn<false, 2 * NB> : k_update_nn<false, NB>);
+    // The depth K is a template parameter (a known trip count keeps the main
+    // loop as fast as the fixed-depth form).  The FP32 form applies two panels
+    // as two NB-deep launches: its NB-deep kernel keeps four workgroups per CU.
+    if (mixed) {
+        for (int p = 0; p < K / NB; ++p)
+            hipLaunchKernelGGL(k_update_nn<true>, g, dim3(256), 0, s, S, ld, L, lda, r0,
+                               krow + p * NB, half, col_shift);
+        return;
+    }
+    auto kern = K == 2 * NB ? k_update_nn<false, 2 * NB> : k_update_nn<false, NB>;
     hipLaunchKernelGGL(kern, g, dim3(256), 0, s, S, ld, L, lda, r0, krow, half, col_shift);
 }
 
@@ -950,7 +984,6 @@ __global__ __launch_bounds__(256) void k_panel_reduce(double *Xa, double *Xn, in
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t m0 = r0 + (int64_t)blockIdx.x * 64;
     d4 acc[4][4];
-    double wa[4][4][4];
     double s[7] = {0, 0, 0, 0, 0, 0, 0}; // t_a, t_n, u_a, u_n, F_aa, F_an, F_nn
     TL::zero(acc);
     TL::run(acc, Xa + m0 + kcol * ld, ld, Linv, NB, NB, lds);
@@ -959,21 +992,22 @@ __global__ __launch_bounds__(256) void k_panel_reduce(double *Xa, double *Xn, in
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                wa[i][j][r] = acc[i][j][r];
+            for (int r = 0; r < 4; ++r)
                 Xa[m0 + TL::row(i, lane, 0) + (kcol + TL::col(j, r, lane, wave)) * ld] = acc[i][j][r];
-            }
     TL::zero(acc);
     TL::run(acc, Xn + m0 + kcol * ld, ld, Linv, NB, NB, lds);
+    // W_alpha is read back by the lane that stored it (program order makes its
+    // own stores visible), which keeps the workgroup small enough to share a
+    // CU with a trailing-update workgroup.
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const double vn = acc[i][j][r], va = wa[i][j][r];
                 const int64_t a = m0 + TL::row(i, lane, 0);
                 const int64_t b = kcol + TL::col(j, r, lane, wave);
+                const double vn = acc[i][j][r], va = Xa[a + b * ld];
                 Xn[a + b * ld] = vn;
                 if (a < n && b < n) {
                     const double w = (a / NB == b / NB) ? 1.0 : 2.0;

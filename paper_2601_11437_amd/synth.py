@@ -114,3 +114,25 @@ def grid_workload(i_beta: int, i_nu: int):
     nus = (0.5, 1.0, 2.5)
     return dict(n=10000, theta_true=(1.0, betas[i_beta], nus[i_nu]), design="grid",
                 seed=1000 + 3 * i_beta + i_nu)
+
+
+def batch_workload(nf: int = 256, seed: int = 5000, n_range=(500, 4000),
+                   theta_sim=(1.0, 0.1, 0.5)):
+    """Many independent fields: n_f ~ U[n_range] uniform points each, data one
+    realisation at theta_sim (seed seed + 1 + f), and an evaluation point
+    theta_f uniform in sigma2 in [0.5, 2], alpha in [0.02, 0.3], nu in
+    [0.3, 2.5].  Returns (fields [(locs, z)], thetas (nf x 3)); thetas whose
+    covariance is not positive definite are redrawn by the caller with
+    batch_redraw_thetas."""
+    gen = rng(seed)
+    ns = gen.integers(n_range[0], n_range[1] + 1, nf)
+    fields = [dataset(int(n), theta_sim, seed + 1 + f)[:2] for f, n in enumerate(ns)]
+    return fields, batch_redraw_thetas(np.zeros((nf, 3)), np.ones(nf, bool), gen)
+
+
+def batch_redraw_thetas(thetas, which, gen):
+    """Redraw the evaluation points of the fields flagged in `which`."""
+    thetas = np.array(thetas, dtype=np.float64)
+    for f in np.flatnonzero(which):
+        thetas[f] = (gen.uniform(0.5, 2.0), gen.uniform(0.02, 0.3), gen.uniform(0.3, 2.5))
+    return thetas

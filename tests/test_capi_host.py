@@ -2,6 +2,7 @@
 the L9 design of Table 1, argument errors, and the Fisher-BT driver
 (Algorithm 1) of the library against the oracle's driver on the same
 evaluators."""
+import ctypes
 import json
 import math
 import os
@@ -49,7 +50,31 @@ def test_null_arguments_are_rejected():
     assert L.fbt_create(None, None) == fbt.EINVAL
     assert L.fbt_fit_evaluator(None, None, None) == fbt.EINVAL
     assert L.fbt_set_timing(None, 1) == fbt.EINVAL
+    assert L.fbt_set_sigma_nu_mode(None, 0) == fbt.EINVAL
+    assert L.fbt_set_precision(None, 0) == fbt.EINVAL
     L.fbt_destroy(None)                      # NULL-safe
+    # batch entry points
+    cfg = fbt.Config(0, 0, 0, None)
+    assert L.fbt_batch_create(None, 1, None) == fbt.EINVAL
+    assert L.fbt_batch_create(ctypes.byref(cfg), 0, ctypes.byref(ctypes.c_void_p())) == fbt.EINVAL
+    assert L.fbt_batch_set_fields(None, 0, None, None, None) == fbt.EINVAL
+    assert L.fbt_batch_eval(None, None, None, None, None, None, None) == fbt.EINVAL
+    L.fbt_batch_destroy(None)                # NULL-safe
+
+
+def test_batch_create_without_gpu_fails_cleanly():
+    try:
+        import torch
+
+        if torch.cuda.device_count() > 0:
+            pytest.skip("a GPU is present")
+    except ImportError:
+        pass
+    L = fbt.lib()
+    cfg = fbt.Config(0, 0, 0, None)
+    h = ctypes.c_void_p()
+    assert L.fbt_batch_create(ctypes.byref(cfg), 2, ctypes.byref(h)) == fbt.EDEVICE
+    assert not h.value
 
 
 def test_l9_design_matches_table1():
