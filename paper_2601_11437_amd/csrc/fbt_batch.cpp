@@ -1,14 +1,16 @@
-// Batched evaluation over many independent fields: a pool of contexts (each
-// with its own pair of HIP streams and its own device buffers, sized once for
-// the largest field) driven by host worker threads.  Workers take fields from
-// one shared queue ordered by decreasing n (longest processing time first), so
-// the evaluations of different fields overlap on the device.  Every field's
-// evaluation is exactly the single-context one (same kernels, same fixed
-// reduction order), so results do not depend on the number of workers or on
-// which worker took the field.
+// Batched evaluation over many independent fields.  Fields of the same padded
+// order and mode are grouped so that every kernel launch advances one block
+// step of all of them (the latency-bound diagonal-block steps are shared);
+// groups are spread over a pool of worker contexts (each with its own HIP
+// streams and device buffers) driven by host threads, largest work first.
+// Every field's arithmetic is exactly the single-context evaluation (the
+// group only offsets each field's buffers), so results do not depend on the
+// grouping, the number of workers or which worker took the field.
 #include "fisherbt.h"
+#include "fbt_internal.h"
 
 #include <algorithm>
+#include <map>
 #include <atomic>
 #include <cstring>
 #include <mutex>
@@ -16,6 +18,9 @@
 #include <string>
 #include <thread>
 #include <vector>
+
+// device memory one batched group may hold (its three matrices per field)
+constexpr size_t GROUP_BYTES = (size_t)8 << 30;
 
 struct fbt_batch {
     std::vector<fbt_ctx *> ctx;
@@ -95,37 +100,94 @@ fbt_status fbt_batch_eval(fbt_batch *b, const double *thetas, const int32_t *mod
         if (mode[f] == 2 && !fisher)
             return FBT_EINVAL;
     }
-    std::atomic<int32_t> next(0);
+    // Tasks: fields of the same padded order and mode (1, 2) form groups whose
+    // every launch covers all of them; a group holds at most GROUP_BYTES of
+    // matrices.  Adjoint-mode fields (3) run one by one.
+    struct Task {
+        int mode;
+        std::vector<int32_t> fields;
+        double cost;
+    };
+    std::map<std::pair<int, int64_t>, std::vector<int32_t>> buckets;
+    std::vector<Task> tasks;
+    for (int32_t f : b->order) {
+        status[f] = FBT_OK;
+        if (mode[f] == 0)
+            continue;
+        const int64_t npad = 256 * ((b->n[f] + 1 + 255) / 256);
+        if (mode[f] == 3)
+            tasks.push_back({3, {f}, (double)npad * npad * npad});
+        else
+            buckets[{mode[f], npad}].push_back(f);
+    }
+    for (auto &kv : buckets) {
+        const int64_t npad = kv.first.second;
+        const size_t per = (size_t)npad * npad * 24;
+        const size_t gmax = std::max<size_t>(1, GROUP_BYTES / per);
+        const double unit = (double)npad * npad * npad * (kv.first.first == 2 ? 9.0 : 1.0);
+        for (size_t i = 0; i < kv.second.size(); i += gmax) {
+            Task t{kv.first.first, {}, 0.0};
+            for (size_t j = i; j < std::min(kv.second.size(), i + gmax); ++j)
+                t.fields.push_back(kv.second[j]);
+            t.cost = unit * (double)t.fields.size();
+            tasks.push_back(std::move(t));
+        }
+    }
+    std::stable_sort(tasks.begin(), tasks.end(),
+                     [](const Task &a, const Task &c) { return a.cost > c.cost; });
+    std::atomic<size_t> next(0);
     std::mutex mu;
     fbt_status fatal = FBT_OK;
     auto work = [&](fbt_ctx *c) {
         for (;;) {
-            const int32_t i = next.fetch_add(1);
-            if (i >= nf)
+            const size_t i = next.fetch_add(1);
+            if (i >= tasks.size())
                 return;
-            const int32_t f = b->order[i];
-            if (mode[f] == 0) {
-                status[f] = FBT_OK;
-                continue;
+            const Task &t = tasks[i];
+            fbt_status st = FBT_OK;
+            if (t.mode == 3) {
+                const int32_t f = t.fields[0];
+                st = fbt_set_data(c, b->n[f], b->locs[f].data(), b->z[f].data());
+                if (st == FBT_OK)
+                    st = fbt_grad(c, thetas + 3 * f, loglik + f, score + 3 * f, nullptr);
+                status[f] = st;
+            } else {
+                const int G = (int)t.fields.size();
+                std::vector<int64_t> gn(G);
+                std::vector<const double *> gl(G), gz(G);
+                std::vector<double> gth(3 * G), gll(G), gsc(3 * G), gfi(9 * G);
+                std::vector<int32_t> gst(G);
+                for (int k = 0; k < G; ++k) {
+                    const int32_t f = t.fields[k];
+                    gn[k] = b->n[f];
+                    gl[k] = b->locs[f].data();
+                    gz[k] = b->z[f].data();
+                    std::memcpy(&gth[3 * k], thetas + 3 * f, 3 * sizeof(double));
+                }
+                st = fbt::group_run(c, G, gn.data(), gl.data(), gz.data(), gth.data(), t.mode,
+                                    gll.data(), gsc.data(), gfi.data(), gst.data());
+                for (int k = 0; k < G && st == FBT_OK; ++k) {
+                    const int32_t f = t.fields[k];
+                    status[f] = gst[k];
+                    if (gst[k] != FBT_OK)
+                        continue;
+                    loglik[f] = gll[k];
+                    if (t.mode == 2) {
+                        std::memcpy(score + 3 * f, &gsc[3 * k], 3 * sizeof(double));
+                        std::memcpy(fisher + 9 * f, &gfi[9 * k], 9 * sizeof(double));
+                    }
+                }
+                if (st != FBT_OK)
+                    for (int32_t f : t.fields)
+                        status[f] = st;
             }
-            fbt_status st = fbt_set_data(c, b->n[f], b->locs[f].data(), b->z[f].data());
-            const double *th = thetas + 3 * f;
-            if (st == FBT_OK) {
-                if (mode[f] == 1)
-                    st = fbt_loglik(c, th, loglik + f);
-                else if (mode[f] == 2)
-                    st = fbt_eval(c, th, loglik + f, score + 3 * f, fisher + 9 * f);
-                else
-                    st = fbt_grad(c, th, loglik + f, score + 3 * f, nullptr);
-            }
-            status[f] = st;
             if (st == FBT_EDEVICE || st == FBT_ENOMEM) {
                 std::lock_guard<std::mutex> g(mu);
                 if (fatal == FBT_OK) {
                     fatal = st;
-                    b->err = "field " + std::to_string(f) + ": " + fbt_last_error(c);
+                    b->err = std::string("batch: ") + fbt_last_error(c);
                 }
-                next.store(nf); // stop handing out fields
+                next.store(tasks.size()); // stop handing out tasks
                 return;
             }
         }

@@ -53,11 +53,21 @@ struct fbt_ctx {
     double *Linv = nullptr, *logdet = nullptr, *partials = nullptr, *out = nullptr;
     double *wv = nullptr; // w = Sigma^{-1} Z (adjoint gradient)
     int *info = nullptr;
-    Node *tab = nullptr;
+    Node *tab = nullptr;   // per field: node table + paper-mode coefficients (TAB_BYTES)
     Node *h_tab = nullptr; // pinned staging
     double *h_out = nullptr;
     int *h_info = nullptr;
-    size_t alloc_npad = 0;
+    size_t cap[24] = {0};  // allocated bytes per buffer (buffers only grow)
+
+    // fields held: 1 for the single-field API; G > 1 inside a batched group
+    int G = 1;
+    Fields F{};
+    int64_t *d_nf = nullptr;       // per-field n (device)
+    GenParams *d_gpa = nullptr;    // per-field generation parameters (device)
+    GenParams *h_gpa = nullptr;    // pinned staging
+    std::vector<int64_t> nf;       // per-field n (host)
+    std::vector<int> fst;          // per-field status of the last group call
+    std::vector<double> fout;      // per-field {log det, y^T y}
 
     bool factor_valid = false;
     double factor_theta[3] = {0, 0, 0};
@@ -196,19 +206,23 @@ void paper_coefficients(const GenParams &gp, double *pc)
 }
 
 // Quadrature tables and prefactors for theta (see the generation kernel).
-GenParams setup_theta(fbt_ctx *c, const double *th)
+GenParams setup_theta(fbt_ctx *c, const double *th, int f, int64_t n)
 {
     GenParams gp;
     std::memset(&gp, 0, sizeof(gp));
+    Node *htab = reinterpret_cast<Node *>(reinterpret_cast<char *>(c->h_tab) + f * TAB_BYTES);
+    const Node *dtab =
+        reinterpret_cast<const Node *>(reinterpret_cast<const char *>(c->tab) + f * TAB_BYTES);
     gp.sigma2 = th[0];
     gp.alpha = th[1];
     gp.nu = th[2];
     gp.abs_nu = std::fabs(th[2]);
     gp.cnu = std::exp((1.0 - gp.nu) * std::log(2.0) - std::lgamma(gp.nu));
     gp.log2_psi = std::log(2.0) + digamma(gp.nu);
-    gp.n = c->n;
+    gp.n = n;
     gp.npad = c->npad;
     gp.ld = c->ld;
+    gp.tab = dtab;
     const bool paper = c->sigma_nu_mode == FBT_SIGMA_NU_PAPER;
     gp.paper = paper ? 1 : 0;
     gp.fd_small = std::fabs(gp.nu - std::nearbyint(gp.nu)) > 1e-6 ? 0 : 1;
@@ -226,7 +240,7 @@ GenParams setup_theta(fbt_ctx *c, const double *th)
         for (int j = 0; j < len; ++j) {
             const double t = j * h, w = (j == 0) ? 0.5 * h : h;
             const double sh = std::sinh(0.5 * t);
-            Node &nd = c->h_tab[off + j];
+            Node &nd = htab[off + j];
             nd.cm1 = 2.0 * sh * sh;
             nd.wk = w * std::cosh(gp.nu * t);
             nd.wk1 = w * std::cosh((gp.nu - 1.0) * t);
@@ -236,9 +250,9 @@ GenParams setup_theta(fbt_ctx *c, const double *th)
         }
         off += maxlen;
     }
-    gp.pc = reinterpret_cast<const double *>(c->tab + TAB_MAX);
+    gp.pc = reinterpret_cast<const double *>(dtab + TAB_MAX);
     if (paper)
-        paper_coefficients(gp, reinterpret_cast<double *>(c->h_tab + TAB_MAX));
+        paper_coefficients(gp, reinterpret_cast<double *>(htab + TAB_MAX));
     return gp;
 }
 
@@ -291,68 +305,112 @@ void tcollect(fbt_ctx *c)
 
 void free_buffers(fbt_ctx *c)
 {
-    (void)hipFree(c->x);
-    (void)hipFree(c->y);
-    (void)hipFree(c->z);
-    (void)hipFree(c->A);
-    (void)hipFree(c->S2);
-    (void)hipFree(c->Linv);
-    (void)hipFree(c->logdet);
-    (void)hipFree(c->partials);
-    (void)hipFree(c->out);
-    (void)hipFree(c->wv);
-    (void)hipFree(c->info);
-    (void)hipFree(c->tab);
-    c->x = c->y = c->z = c->A = c->S2 = c->Linv = c->logdet = c->partials = c->out = nullptr;
-    c->wv = nullptr;
-    c->info = nullptr;
-    c->tab = nullptr;
-    c->alloc_npad = 0;
+    void **dev[] = {(void **)&c->x,        (void **)&c->y,    (void **)&c->z,
+                    (void **)&c->A,        (void **)&c->S2,   (void **)&c->Linv,
+                    (void **)&c->logdet,   (void **)&c->partials, (void **)&c->out,
+                    (void **)&c->wv,       (void **)&c->info, (void **)&c->tab,
+                    (void **)&c->d_nf,     (void **)&c->d_gpa};
+    for (void **p : dev) {
+        (void)hipFree(*p);
+        *p = nullptr;
+    }
+    void **host[] = {(void **)&c->h_tab, (void **)&c->h_out, (void **)&c->h_info,
+                     (void **)&c->h_gpa};
+    for (void **p : host) {
+        if (*p)
+            (void)hipHostFree(*p);
+        *p = nullptr;
+    }
+    std::memset(c->cap, 0, sizeof(c->cap));
+}
+
+// Buffers for G fields of up to nmax observations each (same padded order);
+// a buffer is reallocated only when it must grow.
+fbt_status alloc_fields(fbt_ctx *c, int64_t nmax, int G)
+{
+    const int64_t npad = NB * ((nmax + 1 + NB - 1) / NB);
+    const int T = (int)(npad / NB);
+    const size_t ld = (size_t)npad, g = (size_t)G;
+    const size_t part = (size_t)T * (size_t)(npad / 64) * 8;
+    c->factor_valid = false;
+    struct {
+        void **p;
+        size_t bytes;
+        bool host;
+    } req[] = {
+        {(void **)&c->x, g * ld * 8, false},          {(void **)&c->y, g * ld * 8, false},
+        {(void **)&c->z, g * ld * 8, false},          {(void **)&c->A, g * ld * ld * 8, false},
+        {(void **)&c->S2, g * ld * ld * 16, false},
+        {(void **)&c->Linv, g * (size_t)T * NB * NB * 8, false},
+        {(void **)&c->logdet, g * (size_t)T * 8, false}, {(void **)&c->partials, g * part * 8, false},
+        {(void **)&c->out, g * 16 * 8, false},        {(void **)&c->info, std::max<size_t>(64, g * 4), false},
+        {(void **)&c->wv, g * ld * 8, false},         {(void **)&c->tab, g * TAB_BYTES, false},
+        {(void **)&c->d_nf, g * 8, false},            {(void **)&c->d_gpa, g * sizeof(GenParams), false},
+        {(void **)&c->h_tab, g * TAB_BYTES, true},    {(void **)&c->h_out, g * 16 * 8, true},
+        {(void **)&c->h_info, std::max<size_t>(64, g * 4), true},
+        {(void **)&c->h_gpa, g * sizeof(GenParams), true},
+    };
+    static_assert(sizeof(req) / sizeof(req[0]) <= 24, "capacity slots");
+    int i = 0;
+    for (auto &r : req) {
+        if (r.bytes > c->cap[i]) {
+            if (r.host) {
+                if (*r.p)
+                    (void)hipHostFree(*r.p);
+            } else {
+                (void)hipFree(*r.p);
+            }
+            *r.p = nullptr;
+            c->cap[i] = 0;
+            const hipError_t e = r.host ? hipHostMalloc(r.p, r.bytes, hipHostMallocDefault)
+                                        : hipMalloc(r.p, r.bytes);
+            if (e != hipSuccess) {
+                free_buffers(c);
+                return fail(c, FBT_ENOMEM, "device allocation failed (npad = " +
+                                               std::to_string(npad) + ", fields = " +
+                                               std::to_string(G) + ")");
+            }
+            c->cap[i] = r.bytes;
+        }
+        ++i;
+    }
+    c->G = G;
+    c->n = nmax;
+    c->npad = npad;
+    c->ld = npad;
+    c->T = T;
+    c->ncols = 128 * ((nmax + 127) / 128);
+    c->F.count = G;
+    c->F.sA = npad * npad;
+    c->F.sS2 = 2 * npad * npad;
+    c->F.sLinv = (int64_t)T * NB * NB;
+    c->F.sVec = npad;
+    c->F.sPart = (int64_t)part;
+    c->F.sLog = T;
+    c->F.n = G > 1 ? c->d_nf : nullptr;
+    c->fst.assign(G, FBT_OK);
+    c->fout.assign(2 * g, 0.0);
+    return FBT_OK;
 }
 
 fbt_status alloc_for(fbt_ctx *c, int64_t n)
 {
-    const int64_t npad = NB * ((n + 1 + NB - 1) / NB);
-    c->factor_valid = false;
-    if ((size_t)npad > c->alloc_npad) { // buffers only grow (a smaller n reuses them)
-        free_buffers(c);
-        const size_t ld = (size_t)npad;
-        const int T = (int)(npad / NB);
-        const size_t part = (size_t)T * (size_t)(npad / 64) * 8;
-        struct {
-            void **p;
-            size_t bytes;
-        } req[] = {
-            {(void **)&c->x, ld * 8},           {(void **)&c->y, ld * 8},
-            {(void **)&c->z, ld * 8},           {(void **)&c->A, ld * ld * 8},
-            {(void **)&c->S2, ld * ld * 16},  {(void **)&c->Linv, (size_t)T * NB * NB * 8},
-            {(void **)&c->logdet, (size_t)T * 8}, {(void **)&c->partials, part * 8},
-            {(void **)&c->out, 16 * 8},         {(void **)&c->info, 64},
-            {(void **)&c->wv, ld * 8},
-            {(void **)&c->tab, TAB_BYTES},
-        };
-        for (auto &r : req) {
-            if (hipMalloc(r.p, r.bytes) != hipSuccess) {
-                free_buffers(c);
-                return fail(c, FBT_ENOMEM, "device allocation failed (npad = " +
-                                               std::to_string(npad) + ")");
-            }
-        }
-        c->alloc_npad = npad;
-    }
-    c->n = n;
-    c->npad = npad;
-    c->ld = npad;
-    c->T = (int)(npad / NB);
-    c->ncols = 128 * ((n + 127) / 128);
-    return FBT_OK;
+    c->nf.assign(1, n);
+    return alloc_fields(c, n, 1);
 }
 
+// Quadrature tables for the G fields' theta (th: G x 3), uploaded at once;
+// *gp receives field 0's parameters (the by-value launch argument).
 fbt_status upload_theta(fbt_ctx *c, const double *th, GenParams *gp)
 {
-    *gp = setup_theta(c, th);
-    HIPCHK(c, hipMemcpyAsync(c->tab, c->h_tab, TAB_BYTES, hipMemcpyHostToDevice,
+    for (int f = 0; f < c->G; ++f)
+        c->h_gpa[f] = setup_theta(c, th + 3 * f, f, c->G > 1 ? c->nf[f] : c->n);
+    *gp = c->h_gpa[0];
+    HIPCHK(c, hipMemcpyAsync(c->tab, c->h_tab, (size_t)c->G * TAB_BYTES, hipMemcpyHostToDevice,
                              c->stream));
+    if (c->G > 1)
+        HIPCHK(c, hipMemcpyAsync(c->d_gpa, c->h_gpa, (size_t)c->G * sizeof(GenParams),
+                                 hipMemcpyHostToDevice, c->stream));
     return FBT_OK;
 }
 
@@ -378,8 +436,8 @@ fbt_status factorize(fbt_ctx *c, const double *th, int mode)
     const double dNB = NB;
     const int mix = c->precision == FBT_MIXED_FP32_ALL; // Cholesky updates in FP32
     auto Lk = [&](int k) { return c->Linv + (size_t)k * NB * NB; };
-    launch_init_info(s0, c->info);
-    TIMED(c, s0, KC_GEN, 0.0, launch_gen(s0, gp, c->x, c->y, c->z, c->tab, A, c->S2,
+    launch_init_info(s0, c->info, c->G);
+    TIMED(c, s0, KC_GEN, 0.0, launch_gen(s0, gp, c->d_gpa, c->F, c->x, c->y, c->z, A, c->S2,
                                            c->S2 + npad * ld, mode));
     // Block columns are taken in pairs (b, b + 1).  On s0: diagonal block b,
     // panel b, update of block column b + 1 by panel b, diagonal block b + 1,
@@ -393,20 +451,20 @@ fbt_status factorize(fbt_ctx *c, const double *th, int mode)
         const int64_t r0 = (int64_t)b * NB, rn = r0 + (int64_t)nb * NB;
         const int K = nb * NB;
         TIMED(c, s0, KC_DIAG, 2.0 * dNB * dNB * dNB / 3.0,
-              launch_potrf_diag(s0, A, ld, b, n, Lk(b), c->logdet, c->info));
+              launch_potrf_diag(s0, c->F, A, ld, b, n, Lk(b), c->logdet, c->info));
         if (b + 1 < T)
             TIMED(c, s0, KC_PANEL, rows_from(r0 + NB) * dNB * dNB,
-                  launch_panel(s0, A + r0 + NB + r0 * ld, ld, npad - r0 - NB, Lk(b)));
+                  launch_panel(s0, c->F, A + r0 + NB + r0 * ld, ld, npad - r0 - NB, Lk(b)));
         if (nb == 2) {
             const int64_t r1 = r0 + NB;
             TIMED(c, s0, KC_SYRK, 2.0 * rows_from(r1) * dNB * dNB,
-                  launch_update_rect(s0, 1, A + r1 + r1 * ld, nullptr, ld, A + r1 + r0 * ld, nullptr,
+                  launch_update_rect(s0, c->F, c->F.sA, c->F.sA, 1, A + r1 + r1 * ld, nullptr, ld, A + r1 + r0 * ld, nullptr,
                                      ld, A + r1 + r0 * ld, ld, npad - r1, NB, NB, mix));
             TIMED(c, s0, KC_DIAG, 2.0 * dNB * dNB * dNB / 3.0,
-                  launch_potrf_diag(s0, A, ld, b + 1, n, Lk(b + 1), c->logdet, c->info));
+                  launch_potrf_diag(s0, c->F, A, ld, b + 1, n, Lk(b + 1), c->logdet, c->info));
             if (b + 2 < T)
                 TIMED(c, s0, KC_PANEL, rows_from(rn) * dNB * dNB,
-                      launch_panel(s0, A + rn + r1 * ld, ld, npad - rn, Lk(b + 1)));
+                      launch_panel(s0, c->F, A + rn + r1 * ld, ld, npad - rn, Lk(b + 1)));
         }
         HIPCHK(c, hipEventRecord(c->evP, s0));
         if (rn >= npad)
@@ -414,23 +472,36 @@ fbt_status factorize(fbt_ctx *c, const double *th, int mode)
         const int64_t la = std::min<int64_t>(2 * NB, npad - rn); // columns of the next pair
         HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
         TIMED(c, s0, KC_SYRK, 2.0 * rows_from(rn) * (double)la * K,
-              launch_update_rect(s0, 1, A + rn + rn * ld, nullptr, ld, A + rn + r0 * ld, nullptr,
+              launch_update_rect(s0, c->F, c->F.sA, c->F.sA, 1, A + rn + rn * ld, nullptr, ld, A + rn + r0 * ld, nullptr,
                                  ld, A + rn + r0 * ld, ld, npad - rn, la, K, mix));
         HIPCHK(c, hipStreamWaitEvent(s1, c->evP, 0));
         const int64_t t0 = rn + la;
         if (t0 < npad)
             TIMED(c, s1, KC_SYRK, rows_from(t0) * rows_from(t0) * K,
-                  launch_update_lower(s1, 1, A + t0 + t0 * ld, nullptr, ld, A + t0 + r0 * ld,
+                  launch_update_lower(s1, c->F, c->F.sA, c->F.sA, 1, A + t0 + t0 * ld, nullptr, ld, A + t0 + r0 * ld,
                                       nullptr, ld, A + t0 + r0 * ld, ld, (int)((npad - t0) / NB), K,
                                       mix));
         HIPCHK(c, hipEventRecord(c->evB, s1));
     }
     HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
-    TIMED(c, s0, KC_RED, 0.0, launch_reduce_loglik(s0, A, ld, n, T, c->logdet, c->out));
-    HIPCHK(c, hipMemcpyAsync(c->h_out, c->out, 2 * sizeof(double), hipMemcpyDeviceToHost, s0));
-    HIPCHK(c, hipMemcpyAsync(c->h_info, c->info, sizeof(int), hipMemcpyDeviceToHost, s0));
+    TIMED(c, s0, KC_RED, 0.0, launch_reduce_loglik(s0, c->F, A, ld, n, T, c->logdet, c->out));
+    HIPCHK(c, hipMemcpyAsync(c->h_out, c->out, (size_t)c->G * 16 * sizeof(double),
+                             hipMemcpyDeviceToHost, s0));
+    HIPCHK(c, hipMemcpyAsync(c->h_info, c->info, (size_t)c->G * sizeof(int), hipMemcpyDeviceToHost,
+                             s0));
     HIPCHK(c, hipStreamSynchronize(s0));
     tcollect(c);
+    // per-field status and results (also for one field: batched groups read them)
+    for (int f = 0; f < c->G; ++f) {
+        const double ld_ = c->h_out[16 * f], q = c->h_out[16 * f + 1];
+        c->fout[2 * f] = ld_;
+        c->fout[2 * f + 1] = q;
+        c->fst[f] = c->h_info[f] != 0x7fffffff                      ? FBT_ENOTPD
+                    : (!std::isfinite(ld_) || !std::isfinite(q)) ? FBT_ENONFINITE
+                                                                 : FBT_OK;
+    }
+    if (c->G > 1)
+        return FBT_OK;
     if (c->h_info[0] != 0x7fffffff) {
         c->notpd = c->h_info[0];
         return fail(c, FBT_ENOTPD, "Sigma(theta) is not positive definite: pivot " +
@@ -465,7 +536,7 @@ fbt_status derivative_terms(fbt_ctx *c, const double *th, double terms[9])
         GenParams gp;
         if ((st = upload_theta(c, th, &gp)) != FBT_OK)
             return st;
-        TIMED(c, s0, KC_GEN, 0.0, launch_gen(s0, gp, c->x, c->y, c->z, c->tab, c->A, c->S2,
+        TIMED(c, s0, KC_GEN, 0.0, launch_gen(s0, gp, c->d_gpa, c->F, c->x, c->y, c->z, c->A, c->S2,
                                                c->S2 + c->npad * c->ld, GEN_DERIV));
     } else if ((st = factorize(c, th, GEN_ALL)) != FBT_OK) {
         return st;
@@ -495,12 +566,12 @@ fbt_status derivative_terms(fbt_ctx *c, const double *th, double terms[9])
         const int64_t r0 = (int64_t)b * NB, rn = r0 + (int64_t)nb * NB;
         const int K = nb * NB;
         TIMED(c, s0, KC_LAPPLY, 2.0 * dn * dNB * dNB,
-              launch_diag_apply(s0, 2, c->S2, ld, r0, Lk(b), ncols, npad));
+              launch_diag_apply(s0, c->F, c->F.sS2, 2, c->S2, ld, r0, Lk(b), ncols, npad));
         if (nb == 2) {
             TIMED(c, s0, KC_LUPD, 2.0 * real_rows(r0 + NB, NB) * dNB * 2.0 * dn,
-                  launch_update_nn(s0, 2, c->S2, ld, A, ld, r0 + NB, r0, NB, ncols, npad, NB, mix));
+                  launch_update_nn(s0, c->F, c->F.sS2, 2, c->S2, ld, A, ld, r0 + NB, r0, NB, ncols, npad, NB, mix));
             TIMED(c, s0, KC_LAPPLY, 2.0 * dn * dNB * dNB,
-                  launch_diag_apply(s0, 2, c->S2, ld, r0 + NB, Lk(b + 1), ncols, npad));
+                  launch_diag_apply(s0, c->F, c->F.sS2, 2, c->S2, ld, r0 + NB, Lk(b + 1), ncols, npad));
         }
         HIPCHK(c, hipEventRecord(c->evP, s0));
         if (rn >= npad)
@@ -508,11 +579,11 @@ fbt_status derivative_terms(fbt_ctx *c, const double *th, double terms[9])
         const int64_t la = std::min<int64_t>(2 * NB, npad - rn); // rows of the next pair
         HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
         TIMED(c, s0, KC_LUPD, 2.0 * real_rows(rn, la) * K * 2.0 * dn,
-              launch_update_nn(s0, 2, c->S2, ld, A, ld, rn, r0, la, ncols, npad, K, mix));
+              launch_update_nn(s0, c->F, c->F.sS2, 2, c->S2, ld, A, ld, rn, r0, la, ncols, npad, K, mix));
         HIPCHK(c, hipStreamWaitEvent(s1, c->evP, 0));
         if (rn + la < npad)
             TIMED(c, s1, KC_LUPD, 2.0 * real_rows(rn + la, npad) * K * 2.0 * dn,
-                  launch_update_nn(s1, 2, c->S2, ld, A, ld, rn + la, r0, npad - rn - la, ncols,
+                  launch_update_nn(s1, c->F, c->F.sS2, 2, c->S2, ld, A, ld, rn + la, r0, npad - rn - la, ncols,
                                    npad, K, mix));
         HIPCHK(c, hipEventRecord(c->evB, s1));
     }
@@ -531,18 +602,18 @@ fbt_status derivative_terms(fbt_ctx *c, const double *th, double terms[9])
         const int K = nb * NB;
         const double m0r = std::max<int64_t>(0, n - r0);
         TIMED(c, s0, KC_RPANEL, 2.0 * 2.0 * m0r * dNB * dNB,
-              launch_panel_reduce(s0, Sa, Sn, ld, r0, r0, npad - r0, Lk(b), n,
+              launch_panel_reduce(s0, c->F, Sa, Sn, ld, r0, r0, npad - r0, Lk(b), n,
                                   c->partials + 8 * groups));
         groups += (npad - r0) / 64;
         if (nb == 2) {
             const int64_t r1 = r0 + NB;
             const double m1 = std::max<int64_t>(0, n - r1);
             TIMED(c, s0, KC_RUPD, 2.0 * 2.0 * m1 * dNB * dNB,
-                  launch_update_rect(s0, 2, Sa + r1 + r1 * ld, Sn + r1 + r1 * ld, ld,
+                  launch_update_rect(s0, c->F, c->F.sS2, c->F.sA, 2, Sa + r1 + r1 * ld, Sn + r1 + r1 * ld, ld,
                                      Sa + r1 + r0 * ld, Sn + r1 + r0 * ld, ld, A + r1 + r0 * ld,
                                      ld, npad - r1, NB, NB, mix));
             TIMED(c, s0, KC_RPANEL, 2.0 * 2.0 * m1 * dNB * dNB,
-                  launch_panel_reduce(s0, Sa, Sn, ld, r1, r1, npad - r1, Lk(b + 1), n,
+                  launch_panel_reduce(s0, c->F, Sa, Sn, ld, r1, r1, npad - r1, Lk(b + 1), n,
                                       c->partials + 8 * groups));
             groups += (npad - r1) / 64;
         }
@@ -553,7 +624,7 @@ fbt_status derivative_terms(fbt_ctx *c, const double *th, double terms[9])
         const double mn = std::max<int64_t>(0, n - rn);
         HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
         TIMED(c, s0, KC_RUPD, 2.0 * 2.0 * mn * (double)la * K,
-              launch_update_rect(s0, 2, Sa + rn + rn * ld, Sn + rn + rn * ld, ld,
+              launch_update_rect(s0, c->F, c->F.sS2, c->F.sA, 2, Sa + rn + rn * ld, Sn + rn + rn * ld, ld,
                                  Sa + rn + r0 * ld, Sn + rn + r0 * ld, ld, A + rn + r0 * ld, ld,
                                  npad - rn, la, K, mix));
         HIPCHK(c, hipStreamWaitEvent(s1, c->evP, 0));
@@ -561,16 +632,30 @@ fbt_status derivative_terms(fbt_ctx *c, const double *th, double terms[9])
         const double mt = std::max<int64_t>(0, n - t0);
         if (t0 < npad)
             TIMED(c, s1, KC_RUPD, 2.0 * mt * mt * K,
-                  launch_update_lower(s1, 2, Sa + t0 + t0 * ld, Sn + t0 + t0 * ld, ld,
+                  launch_update_lower(s1, c->F, c->F.sS2, c->F.sA, 2, Sa + t0 + t0 * ld, Sn + t0 + t0 * ld, ld,
                                       Sa + t0 + r0 * ld, Sn + t0 + r0 * ld, ld, A + t0 + r0 * ld,
                                       ld, (int)((npad - t0) / NB), K, mix));
         HIPCHK(c, hipEventRecord(c->evB, s1));
     }
     HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
-    TIMED(c, s0, KC_RED, 0.0, launch_reduce_terms(s0, c->partials, groups, c->out));
-    HIPCHK(c, hipMemcpyAsync(c->h_out, c->out, 9 * sizeof(double), hipMemcpyDeviceToHost, s0));
+    TIMED(c, s0, KC_RED, 0.0, launch_reduce_terms(s0, c->F, c->partials, groups, c->out));
+    HIPCHK(c, hipMemcpyAsync(c->h_out, c->out, (size_t)c->G * 16 * sizeof(double),
+                             hipMemcpyDeviceToHost, s0));
     HIPCHK(c, hipStreamSynchronize(s0));
     tcollect(c);
+    if (c->G > 1) { // a batched group: terms[9 f + i] per field
+        for (int f = 0; f < c->G; ++f) {
+            terms[9 * f] = c->fout[2 * f];
+            terms[9 * f + 1] = c->fout[2 * f + 1];
+            for (int i = 2; i < 9; ++i)
+                terms[9 * f + i] = c->h_out[16 * f + i];
+            if (c->fst[f] == FBT_OK)
+                for (int i = 0; i < 9; ++i)
+                    if (!std::isfinite(terms[9 * f + i]))
+                        c->fst[f] = FBT_ENONFINITE;
+        }
+        return FBT_OK;
+    }
     // the derivative matrices were overwritten; the factor itself is intact
     terms[0] = c->factor_out[0];
     terms[1] = c->factor_out[1];
@@ -591,6 +676,8 @@ fbt_status derivative_terms(fbt_ctx *c, const double *th, double terms[9])
 fbt_status adjoint_terms(fbt_ctx *c, const double *th, double g[2])
 {
     fbt_status st;
+    if (c->G != 1)
+        return fail(c, FBT_EINVAL, "internal: the adjoint path takes one field");
     hipStream_t s0 = c->stream, s1 = c->stream2;
     if (!same_theta(c, th) && (st = factorize(c, th, GEN_SIGMA)) != FBT_OK)
         return st;
@@ -607,7 +694,7 @@ fbt_status adjoint_terms(fbt_ctx *c, const double *th, double g[2])
 
     TIMED(c, s0, KC_ADJ, 0.0, launch_fill_identity(s0, X, ld, npad, ncols));
     TIMED(c, s0, KC_INV, 2.0 * dNB * dNB * (double)cols(0),
-          launch_diag_apply(s0, 1, X, ld, 0, Lk(0), cols(0), 0));
+          launch_diag_apply(s0, c->F, c->F.sS2, 1, X, ld, 0, Lk(0), cols(0), 0));
     HIPCHK(c, hipEventRecord(c->evP, s0));
     HIPCHK(c, hipEventRecord(c->evB, s0));
     for (int k = 0; k + 1 < T; ++k) {
@@ -615,13 +702,13 @@ fbt_status adjoint_terms(fbt_ctx *c, const double *th, double g[2])
         const int64_t ck = cols(k);
         HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
         TIMED(c, s0, KC_INV, 2.0 * dNB * dNB * (double)ck,
-              launch_update_nn(s0, 1, X, ld, A, ld, r1, kc, NB, ck, 0, NB, 0));
+              launch_update_nn(s0, c->F, c->F.sS2, 1, X, ld, A, ld, r1, kc, NB, ck, 0, NB, 0));
         TIMED(c, s0, KC_INV, 2.0 * dNB * dNB * (double)cols(k + 1),
-              launch_diag_apply(s0, 1, X, ld, r1, Lk(k + 1), cols(k + 1), 0));
+              launch_diag_apply(s0, c->F, c->F.sS2, 1, X, ld, r1, Lk(k + 1), cols(k + 1), 0));
         HIPCHK(c, hipStreamWaitEvent(s1, c->evP, 0));
         if (k + 2 < T)
             TIMED(c, s1, KC_INV, 2.0 * (double)(npad - r2) * dNB * (double)ck,
-                  launch_update_nn(s1, 1, X, ld, A, ld, r2, kc, npad - r2, ck, 0, NB, 0));
+                  launch_update_nn(s1, c->F, c->F.sS2, 1, X, ld, A, ld, r2, kc, npad - r2, ck, 0, NB, 0));
         HIPCHK(c, hipEventRecord(c->evB, s1));
         HIPCHK(c, hipEventRecord(c->evP, s0));
     }
@@ -653,6 +740,21 @@ fbt_status adjoint_terms(fbt_ctx *c, const double *th, double g[2])
 double loglik_from(int64_t n, double logdet, double quad)
 {
     return -0.5 * (double)n * std::log(2.0 * M_PI) - 0.5 * logdet - 0.5 * quad;
+}
+
+// Eq. (1)-(3) from the nine terms (Algorithm 3, steps 2-4)
+void assemble(int64_t nobs, const double *theta, const double *t, double *loglik, double *score,
+              double *fisher)
+{
+    const double s2 = theta[0], n = (double)nobs;
+    *loglik = loglik_from(nobs, t[0], t[1]);
+    score[0] = (t[1] - n) / (2.0 * s2);
+    score[1] = -0.5 * t[2] + 0.5 * t[4];
+    score[2] = -0.5 * t[3] + 0.5 * t[5];
+    const double I00 = n / (2.0 * s2 * s2), I01 = t[2] / (2.0 * s2), I02 = t[3] / (2.0 * s2);
+    const double I11 = 0.5 * t[6], I12 = 0.5 * t[7], I22 = 0.5 * t[8];
+    const double F[9] = {I00, I01, I02, I01, I11, I12, I02, I12, I22};
+    std::memcpy(fisher, F, sizeof(F));
 }
 
 fbt_status check_call(fbt_ctx *c, const double *th)
@@ -712,6 +814,75 @@ fbt_status set_data_common(fbt_ctx *c, int64_t n, const double *locs, const doub
 }
 
 } // namespace
+
+// Batched group: G fields of the same padded order evaluated together, every
+// launch covering all of them (field f's buffers at f times the strides).
+// mode 1: log-likelihood (Algorithm 2); mode 2: log-likelihood, score and
+// Fisher (Algorithm 3).  Per-field status in status[f]; a field's outputs are
+// written only when its status is FBT_OK.  The arithmetic of each field is
+// exactly that of a single-field evaluation.
+fbt_status fbt::group_run(fbt_ctx *c, int G, const int64_t *n, const double *const *locs,
+                          const double *const *z, const double *thetas, int mode, double *loglik,
+                          double *score, double *fisher, int32_t *status)
+{
+    if (!c || G < 1 || !n || !locs || !z || !thetas || !loglik || !status ||
+        (mode == 2 && (!score || !fisher)) || (mode != 1 && mode != 2))
+        return FBT_EINVAL;
+    c->err.clear();
+    if (hipSetDevice(c->device) != hipSuccess)
+        return fail(c, FBT_EDEVICE, "hipSetDevice failed");
+    int64_t nmax = 0;
+    for (int f = 0; f < G; ++f)
+        nmax = std::max(nmax, n[f]);
+    const int64_t npad = NB * ((nmax + 1 + NB - 1) / NB);
+    for (int f = 0; f < G; ++f)
+        if (n[f] < 1 || NB * ((n[f] + 1 + NB - 1) / NB) != npad)
+            return fail(c, FBT_EINVAL, "group fields must share the padded order");
+    fbt_status st = alloc_fields(c, nmax, G);
+    if (st != FBT_OK)
+        return st;
+    c->nf.assign(n, n + G);
+    // data, padded per field; invalid theta is replaced by a harmless one and reported
+    std::vector<double> xs((size_t)G * npad, 0.0), ys((size_t)G * npad, 0.0), zs((size_t)G * npad, 0.0);
+    std::vector<double> th(thetas, thetas + 3 * (size_t)G);
+    std::vector<int> bad(G, 0);
+    for (int f = 0; f < G; ++f) {
+        for (int64_t i = 0; i < n[f]; ++i) {
+            xs[(size_t)f * npad + i] = locs[f][2 * i];
+            ys[(size_t)f * npad + i] = locs[f][2 * i + 1];
+            zs[(size_t)f * npad + i] = z[f][i];
+        }
+        if (!theta_ok(&th[3 * f])) {
+            bad[f] = 1;
+            th[3 * f] = 1.0;
+            th[3 * f + 1] = 0.1;
+            th[3 * f + 2] = 0.5;
+        }
+    }
+    HIPCHK(c, hipMemcpyAsync(c->x, xs.data(), xs.size() * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->y, ys.data(), ys.size() * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->z, zs.data(), zs.size() * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_nf, n, (size_t)G * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::vector<double> terms((size_t)G * 9);
+    if (mode == 1)
+        st = factorize(c, th.data(), GEN_SIGMA);
+    else
+        st = derivative_terms(c, th.data(), terms.data());
+    if (st != FBT_OK)
+        return st;
+    for (int f = 0; f < G; ++f) {
+        status[f] = bad[f] ? FBT_EINVAL : c->fst[f];
+        if (status[f] != FBT_OK)
+            continue;
+        if (mode == 1)
+            loglik[f] = loglik_from(n[f], c->fout[2 * f], c->fout[2 * f + 1]);
+        else
+            assemble(n[f], &th[3 * f], &terms[9 * f], loglik + f, score + 3 * f, fisher + 9 * f);
+    }
+    c->factor_valid = false;
+    return FBT_OK;
+}
 
 // =========================================================================
 // C ABI
@@ -790,12 +961,6 @@ fbt_status fbt_create(const fbt_config *cfg, fbt_ctx **out)
         hipEventCreateWithFlags(&c->evB, hipEventDisableTiming) != hipSuccess) {
         fbt_destroy(c);
         return FBT_EDEVICE;
-    }
-    if (hipHostMalloc((void **)&c->h_tab, TAB_BYTES, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&c->h_out, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&c->h_info, 16 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
-        fbt_destroy(c);
-        return FBT_ENOMEM;
     }
     *out = c;
     return FBT_OK;
@@ -882,16 +1047,7 @@ fbt_status fbt_eval(fbt_ctx *ctx, const double theta[3], double *loglik, double 
     double t[9];
     if ((st = derivative_terms(ctx, theta, t)) != FBT_OK)
         return st;
-    const double s2 = theta[0], n = (double)ctx->n;
-    *loglik = loglik_from(ctx->n, t[0], t[1]);
-    // Algorithm 3, steps 2-4
-    score[0] = (t[1] - n) / (2.0 * s2);
-    score[1] = -0.5 * t[2] + 0.5 * t[4];
-    score[2] = -0.5 * t[3] + 0.5 * t[5];
-    const double I00 = n / (2.0 * s2 * s2), I01 = t[2] / (2.0 * s2), I02 = t[3] / (2.0 * s2);
-    const double I11 = 0.5 * t[6], I12 = 0.5 * t[7], I22 = 0.5 * t[8];
-    const double F[9] = {I00, I01, I02, I01, I11, I12, I02, I12, I22};
-    std::memcpy(fisher, F, sizeof(F));
+    assemble(ctx->n, theta, t, loglik, score, fisher);
     return FBT_OK;
 }
 
@@ -934,7 +1090,7 @@ fbt_status fbt_covariance(fbt_ctx *ctx, const double theta[3], int32_t which, do
         return st;
     ctx->factor_valid = false;
     const int64_t n = ctx->n, npad = ctx->npad, dld = ctx->ld;
-    launch_gen(ctx->stream, gp, ctx->x, ctx->y, ctx->z, ctx->tab, ctx->A, ctx->S2,
+    launch_gen(ctx->stream, gp, ctx->d_gpa, ctx->F, ctx->x, ctx->y, ctx->z, ctx->A, ctx->S2,
                ctx->S2 + npad * dld, which == 0 ? GEN_SIGMA : GEN_DERIV);
     const double *src = which == 0 ? ctx->A : (which == 1 ? ctx->S2 : ctx->S2 + npad * dld);
     HIPCHK(ctx, hipMemcpy2DAsync(out, ld * 8, src, dld * 8, n * 8, n, hipMemcpyDeviceToHost,

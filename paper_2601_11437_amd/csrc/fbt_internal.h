@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "fisherbt.h"
+
 namespace fbt {
 
 constexpr int NB = 256;        // block size of the tiled factorisation and solves
@@ -47,6 +49,7 @@ struct GenParams {
     int fd_small;      // paper mode: nu within 1e-6 of an integer (case 5 for x < 8.5)
     int fd_large;      // paper mode: nu + 1/2 within 1e-6 of an integer (case 5 for x >= 30)
     const double *pc;  // paper mode coefficient table (device, PC_SIZE doubles)
+    const Node *tab;   // quadrature node table (device, TAB_MAX nodes)
     int64_t n;         // observations
     int64_t npad;      // padded order (multiple of NB, > n)
     int64_t ld;        // leading dimension of the matrices
@@ -54,30 +57,56 @@ struct GenParams {
 
 enum GenMode { GEN_SIGMA = 1, GEN_DERIV = 2, GEN_ALL = 3 };
 
-// kernel launchers (fbt_kernels.hip); all asynchronous on `s`
-void launch_gen(hipStream_t s, const GenParams &gp, const double *xs, const double *ys,
-                const double *z, const Node *tab, double *S, double *Sa, double *Sn, int mode);
-void launch_init_info(hipStream_t s, int *info);
-void launch_potrf_diag(hipStream_t s, double *A, int64_t lda, int k, int64_t n, double *Linv,
-                       double *logdet_part, int *info);
-void launch_panel(hipStream_t s, double *P, int64_t ld, int64_t rows, const double *Linv);
-void launch_update_lower(hipStream_t s, int nmat, double *C0, double *C1, int64_t ldc,
-                         const double *A0, const double *A1, int64_t lda, const double *B,
-                         int64_t ldb, int nblk, int K, int mixed);
-void launch_update_rect(hipStream_t s, int nmat, double *C0, double *C1, int64_t ldc,
-                        const double *A0, const double *A1, int64_t lda, const double *B,
-                        int64_t ldb, int64_t rows, int64_t ncol, int K, int mixed);
-void launch_diag_apply(hipStream_t s, int nmat, double *S, int64_t ld, int64_t krow,
-                       const double *Linv, int64_t ncols, int64_t col_shift);
-void launch_update_nn(hipStream_t s, int nmat, double *S, int64_t ld, const double *L,
-                      int64_t lda, int64_t r0, int64_t krow, int64_t rows, int64_t ncols,
-                      int64_t col_shift, int K, int mixed);
-void launch_panel_reduce(hipStream_t s, double *Xa, double *Xn, int64_t ld, int64_t r0,
-                         int64_t kcol, int64_t rows, const double *Linv, int64_t n,
+// Field batching.  One launch can cover `count` independent fields of the same
+// padded order whose buffers are laid out one after another with uniform
+// strides (in elements): field f (blockIdx.z, or the dimension a kernel
+// documents) uses each pointer offset by f times the stride of its buffer.
+// A single field is count = 1 with all offsets zero.
+struct Fields {
+    int count;
+    int64_t sA;    // factor / covariance matrix (npad x npad)
+    int64_t sS2;   // derivative pair (npad x 2 npad)
+    int64_t sLinv; // diagonal-block inverses (T NB^2)
+    int64_t sVec;  // npad-vectors (locations, observations, w)
+    int64_t sPart; // partial sums
+    int64_t sLog;  // log-det partials (T)
+    const int64_t *n; // per-field n (device; nullptr: the launch's n for every field)
+};
+
+// kernel launchers (fbt_kernels.hip); all asynchronous on `s`.  Launchers
+// with a `Fields` argument process F.count fields (see above); gpa then holds
+// one GenParams per field (device memory for count > 1).
+void launch_gen(hipStream_t s, const GenParams &gp, const GenParams *gpa, const Fields &F,
+                const double *xs, const double *ys, const double *z, double *S, double *Sa,
+                double *Sn, int mode);
+void launch_init_info(hipStream_t s, int *info, int count);
+void launch_potrf_diag(hipStream_t s, const Fields &F, double *A, int64_t lda, int k, int64_t n,
+                       double *Linv, double *logdet_part, int *info);
+void launch_panel(hipStream_t s, const Fields &F, double *P, int64_t ld, int64_t rows,
+                  const double *Linv);
+// sC: stride of C0/C1/A0/A1 (F.sA or F.sS2), sB: stride of B (F.sA)
+void launch_update_lower(hipStream_t s, const Fields &F, int64_t sC, int64_t sB, int nmat,
+                         double *C0, double *C1, int64_t ldc, const double *A0,
+                         const double *A1, int64_t lda, const double *B, int64_t ldb, int nblk,
+                         int K, int mixed);
+void launch_update_rect(hipStream_t s, const Fields &F, int64_t sC, int64_t sB, int nmat,
+                        double *C0, double *C1, int64_t ldc, const double *A0, const double *A1,
+                        int64_t lda, const double *B, int64_t ldb, int64_t rows, int64_t ncol,
+                        int K, int mixed);
+// sS: stride of S (F.sS2, or F.sA for the adjoint's inverse)
+void launch_diag_apply(hipStream_t s, const Fields &F, int64_t sS, int nmat, double *S,
+                       int64_t ld, int64_t krow, const double *Linv, int64_t ncols,
+                       int64_t col_shift);
+void launch_update_nn(hipStream_t s, const Fields &F, int64_t sS, int nmat, double *S, int64_t ld,
+                      const double *L, int64_t lda, int64_t r0, int64_t krow, int64_t rows,
+                      int64_t ncols, int64_t col_shift, int K, int mixed);
+void launch_panel_reduce(hipStream_t s, const Fields &F, double *Xa, double *Xn, int64_t ld,
+                         int64_t r0, int64_t kcol, int64_t rows, const double *Linv, int64_t n,
                          double *partials);
-void launch_reduce_loglik(hipStream_t s, const double *A, int64_t lda, int64_t n, int T,
-                          const double *logdet_part, double *out);
-void launch_reduce_terms(hipStream_t s, const double *partials, int64_t count, double *out);
+void launch_reduce_loglik(hipStream_t s, const Fields &F, const double *A, int64_t lda,
+                          int64_t n, int T, const double *logdet_part, double *out);
+void launch_reduce_terms(hipStream_t s, const Fields &F, const double *partials, int64_t count,
+                         double *out);
 // adjoint gradient
 void launch_fill_identity(hipStream_t s, double *X, int64_t ld, int64_t rows, int64_t ncols);
 void launch_lauum(hipStream_t s, double *P, const double *X, int64_t ld, int64_t npad,
@@ -86,5 +115,11 @@ void launch_extract_w(hipStream_t s, const double *X, int64_t ld, int64_t n, dou
 void launch_adjoint(hipStream_t s, const GenParams &gp, const double *xs, const double *ys,
                     const Node *tab, const double *P, const double *w, double *part);
 void launch_reduce_pairs(hipStream_t s, const double *part, int64_t count, double *out);
+
+// Batched group of fields of one padded order (fbt_engine.hip), used by the
+// batch executor; see the definition for the contract.
+fbt_status group_run(fbt_ctx *c, int G, const int64_t *n, const double *const *locs,
+                     const double *const *z, const double *thetas, int mode, double *loglik,
+                     double *score, double *fisher, int32_t *status);
 
 }  // namespace fbt

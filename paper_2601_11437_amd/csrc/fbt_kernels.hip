@@ -158,14 +158,23 @@ __device__ __forceinline__ void matern3(const GenParams &gp, const Node *tab, do
                                         gp.log2_psi * exp(gp.nu * lx - x) * sk);
 }
 
-__global__ __launch_bounds__(256) void k_gen(GenParams gp, const double *__restrict__ xs,
+__global__ __launch_bounds__(256) void k_gen(GenParams gp1, const GenParams *__restrict__ gpa,
+                                             Fields F, const double *__restrict__ xs,
                                              const double *__restrict__ ys,
-                                             const double *__restrict__ z,
-                                             const Node *__restrict__ gtab, double *__restrict__ S,
+                                             const double *__restrict__ z, double *__restrict__ S,
                                              double *__restrict__ Sa, double *__restrict__ Sn,
                                              int mode)
 {
     __shared__ Node tab[TAB_MAX];
+    const int f = blockIdx.y; // field
+    const GenParams gp = gpa ? gpa[f] : gp1;
+    const Node *__restrict__ gtab = gp.tab;
+    xs += f * F.sVec;
+    ys += f * F.sVec;
+    z += f * F.sVec;
+    S += f * F.sA;
+    Sa += f * F.sS2;
+    Sn += f * F.sS2;
     const int t = threadIdx.x;
     const int ntab = gp.off[NLEV - 1] + gp.len[NLEV - 1];
     for (int i = t; i < ntab; i += 256)
@@ -217,13 +226,14 @@ __global__ __launch_bounds__(256) void k_gen(GenParams gp, const double *__restr
     }
 }
 
-void launch_gen(hipStream_t s, const GenParams &gp, const double *xs, const double *ys,
-                const double *z, const Node *tab, double *S, double *Sa, double *Sn, int mode)
+void launch_gen(hipStream_t s, const GenParams &gp, const GenParams *gpa, const Fields &F,
+                const double *xs, const double *ys, const double *z, double *S, double *Sa,
+                double *Sn, int mode)
 {
     const int64_t nt = gp.npad / GT;
     const int64_t pairs = nt * (nt + 1) / 2;
-    hipLaunchKernelGGL(k_gen, dim3((unsigned)pairs), dim3(256), 0, s, gp, xs, ys, z, tab, S, Sa,
-                       Sn, mode);
+    hipLaunchKernelGGL(k_gen, dim3((unsigned)pairs, F.count), dim3(256), 0, s, gp,
+                       F.count > 1 ? gpa : nullptr, F, xs, ys, z, S, Sa, Sn, mode);
 }
 
 // ---------------------------------------------------------------------------
@@ -253,11 +263,17 @@ constexpr int LPS = PW + 1; // LDS row stride of the panel and of D_p
 constexpr int XPS = NB + 1; // LDS row stride of X_p (PW x NB)
 constexpr int DT = 256;     // threads of the diagonal kernel
 
-__global__ __launch_bounds__(DT) void k_potrf_diag(double *__restrict__ A, int64_t lda, int kblk,
-                                                   int64_t n, double *__restrict__ Linv,
+__global__ __launch_bounds__(DT) void k_potrf_diag(Fields F, double *__restrict__ A, int64_t lda,
+                                                   int kblk, int64_t n1, double *__restrict__ Linv,
                                                    double *__restrict__ logdet_part,
                                                    int *__restrict__ info)
 {
+    const int f = blockIdx.x; // field
+    A += f * F.sA;
+    Linv += f * F.sLinv;
+    logdet_part += f * F.sLog;
+    info += f;
+    const int64_t n = F.n ? F.n[f] : n1;
     __shared__ double Lp[NB * LPS];
     __shared__ double Xp[PW * XPS];
     __shared__ double Dp[PW * LPS];
@@ -438,22 +454,25 @@ __global__ __launch_bounds__(DT) void k_potrf_diag(double *__restrict__ A, int64
     }
 }
 
-__global__ void k_init_info(int *info)
+__global__ __launch_bounds__(256) void k_init_info(int *info, int count)
 {
-    if (threadIdx.x == 0)
-        info[0] = 0x7fffffff;
+    const int f = blockIdx.x * 256 + threadIdx.x;
+    if (f < count)
+        info[f] = 0x7fffffff;
 }
 
-void launch_init_info(hipStream_t s, int *info)
+void launch_init_info(hipStream_t s, int *info, int count)
 {
-    hipLaunchKernelGGL(k_init_info, dim3(1), dim3(64), 0, s, info);
+    hipLaunchKernelGGL(k_init_info, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, info,
+                       count);
 }
 
-void launch_potrf_diag(hipStream_t s, double *A, int64_t lda, int k, int64_t n, double *Linv,
-                       double *logdet_part, int *info)
+// one workgroup per field
+void launch_potrf_diag(hipStream_t s, const Fields &F, double *A, int64_t lda, int k, int64_t n,
+                       double *Linv, double *logdet_part, int *info)
 {
-    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(DT), 0, s, A, lda, k, n, Linv, logdet_part,
-                       info);
+    hipLaunchKernelGGL(k_potrf_diag, dim3((unsigned)F.count), dim3(DT), 0, s, F, A, lda, k, n,
+                       Linv, logdet_part, info);
 }
 
 // ---------------------------------------------------------------------------
@@ -750,7 +769,8 @@ template <int WM, int WN, bool BKC> struct TileF {
 // diagonal NB-block are included), depth K (one or two panels).  blockIdx.y
 // selects (C0, A0) or (C1, A1).
 template <bool MIX, int K = NB>
-__global__ __launch_bounds__(256) void k_update_lower(double *C0, double *C1, int64_t ldc,
+__global__ __launch_bounds__(256) void k_update_lower(int nmat, int64_t sC, int64_t sB,
+                                                      double *C0, double *C1, int64_t ldc,
                                                       const double *A0, const double *A1,
                                                       int64_t lda, const double *B, int64_t ldb)
 {
@@ -766,8 +786,10 @@ __global__ __launch_bounds__(256) void k_update_lower(double *C0, double *C1, in
         --I;
     const int64_t J = p - I * (I + 1) / 2;
     const int64_t m0 = I * NB + 128 * (s >> 1), n0 = J * NB + 128 * (s & 1);
-    double *C = (blockIdx.y ? C1 : C0) + m0 + n0 * ldc;
-    const double *A = (blockIdx.y ? A1 : A0) + m0;
+    const int mat = blockIdx.y % nmat, f = blockIdx.y / nmat; // matrix, field
+    double *C = (mat ? C1 : C0) + f * sC + m0 + n0 * ldc;
+    const double *A = (mat ? A1 : A0) + f * sC + m0;
+    B += f * sB;
     if constexpr (MIX) {
         TF::update(C, ldc, A, lda, B + n0, ldb, K, (float *)lds);
     } else {
@@ -782,16 +804,19 @@ __global__ __launch_bounds__(256) void k_update_lower(double *C0, double *C1, in
 // next block column(s) of a trailing update (lookahead).  blockIdx.z selects
 // the matrix.
 template <bool MIX, int K = NB>
-__global__ __launch_bounds__(256) void k_update_rect(double *C0, double *C1, int64_t ldc,
-                                                     const double *A0, const double *A1,
-                                                     int64_t lda, const double *B, int64_t ldb)
+__global__ __launch_bounds__(256) void k_update_rect(int nmat, int64_t sC, int64_t sB, double *C0,
+                                                     double *C1, int64_t ldc, const double *A0,
+                                                     const double *A1, int64_t lda,
+                                                     const double *B, int64_t ldb)
 {
     using TL = Tile<2, 2, false, true>;
     using TF = TileF<2, 2, false>;
     __shared__ double lds[MIX ? (TF::LDS + 1) / 2 : TL::LDS];
     const int64_t m0 = 128 * (int64_t)blockIdx.x, n0 = 128 * (int64_t)blockIdx.y;
-    double *C = (blockIdx.z ? C1 : C0) + m0 + n0 * ldc;
-    const double *A = (blockIdx.z ? A1 : A0) + m0;
+    const int mat = blockIdx.z % nmat, f = blockIdx.z / nmat; // matrix, field
+    double *C = (mat ? C1 : C0) + f * sC + m0 + n0 * ldc;
+    const double *A = (mat ? A1 : A0) + f * sC + m0;
+    B += f * sB;
     if constexpr (MIX) {
         TF::update(C, ldc, A, lda, B + n0, ldb, K, (float *)lds);
     } else {
@@ -805,52 +830,57 @@ __global__ __launch_bounds__(256) void k_update_rect(double *C0, double *C1, int
 // Both launchers take K = NB or 2 NB.  The FP32 form applies two panels as
 // two NB-deep launches (its NB-deep kernel keeps four workgroups per CU);
 // A and B then advance by NB columns.
-void launch_update_rect(hipStream_t s, int nmat, double *C0, double *C1, int64_t ldc,
-                        const double *A0, const double *A1, int64_t lda, const double *B,
-                        int64_t ldb, int64_t rows, int64_t ncol, int K, int mixed)
+void launch_update_rect(hipStream_t s, const Fields &F, int64_t sC, int64_t sB, int nmat,
+                        double *C0, double *C1, int64_t ldc, const double *A0, const double *A1,
+                        int64_t lda, const double *B, int64_t ldb, int64_t rows, int64_t ncol,
+                        int K, int mixed)
 {
     if (rows <= 0 || ncol <= 0 || (K != NB && K != 2 * NB))
         return;
-    const dim3 g((unsigned)(rows / 128), (unsigned)(ncol / 128), nmat);
+    const dim3 g((unsigned)(rows / 128), (unsigned)(ncol / 128), (unsigned)(nmat * F.count));
     if (mixed) {
         for (int p = 0; p < K / NB; ++p) {
             const int64_t o = (int64_t)p * NB;
-            hipLaunchKernelGGL(k_update_rect<true>, g, dim3(256), 0, s, C0, C1, ldc, A0 + o * lda,
-                               A1 ? A1 + o * lda : nullptr, lda, B + o * ldb, ldb);
-        }
-        return;
-    }
-    auto kern = K == 2 * NB ? k_update_rect<false, 2 * NB> : k_update_rect<false, NB>;
-    hipLaunchKernelGGL(kern, g, dim3(256), 0, s, C0, C1, ldc, A0, A1, lda, B, ldb);
-}
-
-void launch_update_lower(hipStream_t s, int nmat, double *C0, double *C1, int64_t ldc,
-                         const double *A0, const double *A1, int64_t lda, const double *B,
-                         int64_t ldb, int nblk, int K, int mixed)
-{
-    if (nblk <= 0 || (K != NB && K != 2 * NB))
-        return;
-    const int64_t pairs = (int64_t)nblk * (nblk + 1) / 2;
-    const dim3 g((unsigned)(4 * pairs), nmat);
-    if (mixed) {
-        for (int p = 0; p < K / NB; ++p) {
-            const int64_t o = (int64_t)p * NB;
-            hipLaunchKernelGGL(k_update_lower<true>, g, dim3(256), 0, s, C0, C1, ldc,
+            hipLaunchKernelGGL(k_update_rect<true>, g, dim3(256), 0, s, nmat, sC, sB, C0, C1, ldc,
                                A0 + o * lda, A1 ? A1 + o * lda : nullptr, lda, B + o * ldb, ldb);
         }
         return;
     }
+    auto kern = K == 2 * NB ? k_update_rect<false, 2 * NB> : k_update_rect<false, NB>;
+    hipLaunchKernelGGL(kern, g, dim3(256), 0, s, nmat, sC, sB, C0, C1, ldc, A0, A1, lda, B, ldb);
+}
+
+void launch_update_lower(hipStream_t s, const Fields &F, int64_t sC, int64_t sB, int nmat,
+                         double *C0, double *C1, int64_t ldc, const double *A0,
+                         const double *A1, int64_t lda, const double *B, int64_t ldb, int nblk,
+                         int K, int mixed)
+{
+    if (nblk <= 0 || (K != NB && K != 2 * NB))
+        return;
+    const int64_t pairs = (int64_t)nblk * (nblk + 1) / 2;
+    const dim3 g((unsigned)(4 * pairs), (unsigned)(nmat * F.count));
+    if (mixed) {
+        for (int p = 0; p < K / NB; ++p) {
+            const int64_t o = (int64_t)p * NB;
+            hipLaunchKernelGGL(k_update_lower<true>, g, dim3(256), 0, s, nmat, sC, sB, C0, C1,
+                               ldc, A0 + o * lda, A1 ? A1 + o * lda : nullptr, lda, B + o * ldb,
+                               ldb);
+        }
+        return;
+    }
     auto kern = K == 2 * NB ? k_update_lower<false, 2 * NB> : k_update_lower<false, NB>;
-    hipLaunchKernelGGL(kern, g, dim3(256), 0, s, C0, C1, ldc, A0, A1, lda, B, ldb);
+    hipLaunchKernelGGL(kern, g, dim3(256), 0, s, nmat, sC, sB, C0, C1, ldc, A0, A1, lda, B, ldb);
 }
 
 // Panel solve of the factorisation: P (rows x NB, in place) = P Linv^T.
 // A workgroup owns 64 full rows, so the in-place update is race free.
-__global__ __launch_bounds__(256) void k_panel(double *P, int64_t ld, const double *Linv)
+__global__ __launch_bounds__(256) void k_panel(Fields F, double *P, int64_t ld, const double *Linv)
 {
     using TL = Tile<1, 4, false>;
     __shared__ double lds[TL::LDS];
-    double *Pb = P + (int64_t)blockIdx.x * 64;
+    const int f = blockIdx.y; // field
+    Linv += f * F.sLinv;
+    double *Pb = P + f * F.sA + (int64_t)blockIdx.x * 64;
     d4 acc[4][4];
     TL::zero(acc);
     TL::run(acc, Pb, ld, Linv, NB, NB, lds);
@@ -864,11 +894,13 @@ __global__ __launch_bounds__(256) void k_panel(double *P, int64_t ld, const doub
                 Pb[TL::row(i, lane, 0) + (int64_t)TL::col(j, r, lane, wave) * ld] = acc[i][j][r];
 }
 
-void launch_panel(hipStream_t s, double *P, int64_t ld, int64_t rows, const double *Linv)
+void launch_panel(hipStream_t s, const Fields &F, double *P, int64_t ld, int64_t rows,
+                  const double *Linv)
 {
     if (rows <= 0)
         return;
-    hipLaunchKernelGGL(k_panel, dim3((unsigned)(rows / 64)), dim3(256), 0, s, P, ld, Linv);
+    hipLaunchKernelGGL(k_panel, dim3((unsigned)(rows / 64), F.count), dim3(256), 0, s, F, P, ld,
+                       Linv);
 }
 
 // Left solve, diagonal block: S[krow:krow+NB, cols] = Linv * S[krow:krow+NB, cols]
@@ -876,12 +908,15 @@ void launch_panel(hipStream_t s, double *P, int64_t ld, int64_t rows, const doub
 // to column 64 c, shifted by col_shift past the first half (two right-hand
 // sides stored side by side; with one right-hand side only the first half is
 // launched).
-__global__ __launch_bounds__(256) void k_diag_apply(double *S, int64_t ld, int64_t krow,
-                                                    const double *Linv, int64_t half_tiles,
-                                                    int64_t col_shift)
+__global__ __launch_bounds__(256) void k_diag_apply(Fields F, int64_t sS, double *S, int64_t ld,
+                                                    int64_t krow, const double *Linv,
+                                                    int64_t half_tiles, int64_t col_shift)
 {
     using TL = Tile<4, 1, true>;
     __shared__ double lds[TL::LDS];
+    const int f = blockIdx.y; // field
+    S += f * sS;
+    Linv += f * F.sLinv;
     const int64_t ct = blockIdx.x;
     const int64_t c0 = (ct < half_tiles) ? 64 * ct : col_shift + 64 * (ct - half_tiles);
     double *Sb = S + krow + c0 * ld;
@@ -898,27 +933,32 @@ __global__ __launch_bounds__(256) void k_diag_apply(double *S, int64_t ld, int64
                 Sb[TL::row(i, lane, wave) + (int64_t)TL::col(j, r, lane, 0) * ld] = acc[i][j][r];
 }
 
-void launch_diag_apply(hipStream_t s, int nmat, double *S, int64_t ld, int64_t krow,
-                       const double *Linv, int64_t ncols, int64_t col_shift)
+void launch_diag_apply(hipStream_t s, const Fields &F, int64_t sS, int nmat, double *S,
+                       int64_t ld, int64_t krow, const double *Linv, int64_t ncols,
+                       int64_t col_shift)
 {
     const int64_t half = ncols / 64;
     if (half <= 0)
         return;
-    hipLaunchKernelGGL(k_diag_apply, dim3((unsigned)(nmat * half)), dim3(256), 0, s, S, ld, krow,
-                       Linv, half, col_shift);
+    hipLaunchKernelGGL(k_diag_apply, dim3((unsigned)(nmat * half), F.count), dim3(256), 0, s, F,
+                       sS, S, ld, krow, Linv, half, col_shift);
 }
 
 // Left solve, update below the diagonal block(s):
 // S[r0 + 128 y, cols] -= L[r0 + 128 y, krow:krow+K] * S[krow:krow+K, cols]
 // (K = NB for one panel, 2 NB for two consecutive panels at once).
 template <bool MIX, int K = NB>
-__global__ __launch_bounds__(256) void k_update_nn(double *S, int64_t ld, const double *L,
-                                                   int64_t lda, int64_t r0, int64_t krow,
-                                                   int64_t half_tiles, int64_t col_shift)
+__global__ __launch_bounds__(256) void k_update_nn(Fields F, int64_t sS, double *S, int64_t ld,
+                                                   const double *L, int64_t lda, int64_t r0,
+                                                   int64_t krow, int64_t half_tiles,
+                                                   int64_t col_shift)
 {
     using TL = Tile<2, 2, true, true>;
     using TF = TileF<2, 2, true>;
     __shared__ double lds[MIX ? (TF::LDS + 1) / 2 : TL::LDS];
+    const int f = blockIdx.z; // field
+    S += f * sS;
+    L += f * F.sA;
     const int64_t ct = blockIdx.x;
     const int64_t c0 = (ct < half_tiles) ? 128 * ct : col_shift + 128 * (ct - half_tiles);
     const int64_t m0 = r0 + 128 * (int64_t)blockIdx.y;
@@ -933,25 +973,25 @@ __global__ __launch_bounds__(256) void k_update_nn(double *S, int64_t ld, const 
     }
 }
 
-void launch_update_nn(hipStream_t s, int nmat, double *S, int64_t ld, const double *L,
-                      int64_t lda, int64_t r0, int64_t krow, int64_t rows, int64_t ncols,
-                      int64_t col_shift, int K, int mixed)
+void launch_update_nn(hipStream_t s, const Fields &F, int64_t sS, int nmat, double *S, int64_t ld,
+                      const double *L, int64_t lda, int64_t r0, int64_t krow, int64_t rows,
+                      int64_t ncols, int64_t col_shift, int K, int mixed)
 {
     const int64_t half = ncols / 128;
     if (rows <= 0 || half <= 0 || (K != NB && K != 2 * NB))
         return;
-    const dim3 g((unsigned)(nmat * half), (unsigned)(rows / 128));
+    const dim3 g((unsigned)(nmat * half), (unsigned)(rows / 128), F.count);
     // The depth K is a template parameter (a known trip count keeps the main
     // loop as fast as the fixed-depth form).  The FP32 form applies two panels
     // as two NB-deep launches: its NB-deep kernel keeps four workgroups per CU.
     if (mixed) {
         for (int p = 0; p < K / NB; ++p)
-            hipLaunchKernelGGL(k_update_nn<true>, g, dim3(256), 0, s, S, ld, L, lda, r0,
+            hipLaunchKernelGGL(k_update_nn<true>, g, dim3(256), 0, s, F, sS, S, ld, L, lda, r0,
                                krow + p * NB, half, col_shift);
         return;
     }
     auto kern = K == 2 * NB ? k_update_nn<false, 2 * NB> : k_update_nn<false, NB>;
-    hipLaunchKernelGGL(kern, g, dim3(256), 0, s, S, ld, L, lda, r0, krow, half, col_shift);
+    hipLaunchKernelGGL(kern, g, dim3(256), 0, s, F, sS, S, ld, L, lda, r0, krow, half, col_shift);
 }
 
 // ---------------------------------------------------------------------------
@@ -973,14 +1013,20 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-__global__ __launch_bounds__(256) void k_panel_reduce(double *Xa, double *Xn, int64_t ld,
-                                                      int64_t r0, int64_t kcol,
-                                                      const double *Linv, int64_t n,
+__global__ __launch_bounds__(256) void k_panel_reduce(Fields F, double *Xa, double *Xn,
+                                                      int64_t ld, int64_t r0, int64_t kcol,
+                                                      const double *Linv, int64_t n1,
                                                       double *partials)
 {
     using TL = Tile<1, 4, false>;
     __shared__ double lds[TL::LDS];
     __shared__ double red[4][8];
+    const int f = blockIdx.y; // field
+    Xa += f * F.sS2;
+    Xn += f * F.sS2;
+    Linv += f * F.sLinv;
+    partials += f * F.sPart;
+    const int64_t n = F.n ? F.n[f] : n1;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t m0 = r0 + (int64_t)blockIdx.x * 64;
     d4 acc[4][4];
@@ -1036,12 +1082,12 @@ __global__ __launch_bounds__(256) void k_panel_reduce(double *Xa, double *Xn, in
     }
 }
 
-void launch_panel_reduce(hipStream_t s, double *Xa, double *Xn, int64_t ld, int64_t r0,
-                         int64_t kcol, int64_t rows, const double *Linv, int64_t n,
+void launch_panel_reduce(hipStream_t s, const Fields &F, double *Xa, double *Xn, int64_t ld,
+                         int64_t r0, int64_t kcol, int64_t rows, const double *Linv, int64_t n,
                          double *partials)
 {
-    hipLaunchKernelGGL(k_panel_reduce, dim3((unsigned)(rows / 64)), dim3(256), 0, s, Xa, Xn, ld, r0,
-                       kcol, Linv, n, partials);
+    hipLaunchKernelGGL(k_panel_reduce, dim3((unsigned)(rows / 64), F.count), dim3(256), 0, s, F,
+                       Xa, Xn, ld, r0, kcol, Linv, n, partials);
 }
 
 // ---------------------------------------------------------------------------
@@ -1061,12 +1107,17 @@ __device__ double block_sum(double v, double *sh)
     return r;
 }
 
-__global__ __launch_bounds__(256) void k_reduce_loglik(const double *A, int64_t lda, int64_t n,
-                                                       int T, const double *logdet_part,
-                                                       double *out)
+__global__ __launch_bounds__(256) void k_reduce_loglik(Fields F, const double *A, int64_t lda,
+                                                       int64_t n1, int T,
+                                                       const double *logdet_part, double *out)
 {
     __shared__ double sh[4];
     const int t = threadIdx.x;
+    const int f = blockIdx.x; // field
+    A += f * F.sA;
+    logdet_part += f * F.sLog;
+    out += 16 * f;
+    const int64_t n = F.n ? F.n[f] : n1;
     double q = 0.0;
     for (int64_t c = t; c < n; c += 256) {
         const double y = A[n + c * lda];
@@ -1083,18 +1134,22 @@ __global__ __launch_bounds__(256) void k_reduce_loglik(const double *A, int64_t 
     }
 }
 
-void launch_reduce_loglik(hipStream_t s, const double *A, int64_t lda, int64_t n, int T,
-                          const double *logdet_part, double *out)
+void launch_reduce_loglik(hipStream_t s, const Fields &F, const double *A, int64_t lda,
+                          int64_t n, int T, const double *logdet_part, double *out)
 {
-    hipLaunchKernelGGL(k_reduce_loglik, dim3(1), dim3(256), 0, s, A, lda, n, T, logdet_part, out);
+    hipLaunchKernelGGL(k_reduce_loglik, dim3((unsigned)F.count), dim3(256), 0, s, F, A, lda, n, T,
+                       logdet_part, out);
 }
 
 // out[2..8] = sums over `count` groups of 8 partials (t_a, t_n, u_a, u_n, F_aa, F_an, F_nn)
-__global__ __launch_bounds__(256) void k_reduce_terms(const double *partials, int64_t count,
-                                                      double *out)
+__global__ __launch_bounds__(256) void k_reduce_terms(Fields F, const double *partials,
+                                                      int64_t count, double *out)
 {
     __shared__ double sh[4];
     const int t = threadIdx.x;
+    const int f = blockIdx.x; // field
+    partials += f * F.sPart;
+    out += 16 * f;
     for (int q = 0; q < 7; ++q) {
         double v = 0.0;
         for (int64_t g = t; g < count; g += 256)
@@ -1105,9 +1160,11 @@ __global__ __launch_bounds__(256) void k_reduce_terms(const double *partials, in
     }
 }
 
-void launch_reduce_terms(hipStream_t s, const double *partials, int64_t count, double *out)
+void launch_reduce_terms(hipStream_t s, const Fields &F, const double *partials, int64_t count,
+                         double *out)
 {
-    hipLaunchKernelGGL(k_reduce_terms, dim3(1), dim3(256), 0, s, partials, count, out);
+    hipLaunchKernelGGL(k_reduce_terms, dim3((unsigned)F.count), dim3(256), 0, s, F, partials,
+                       count, out);
 }
 
 // ---------------------------------------------------------------------------

@@ -86,3 +86,27 @@ def test_paper_mode_eval(ctx, oracle_mod, theta):
     assert np.all(np.abs(fi - want["fisher"]) <= tol * d)
     assert sc[0] == sc_e[0] and sc[1] == sc_e[1]
     say("paper - exact nu score: %.3e (scale %.3e)" % (sc[2] - sc_e[2], scale[2]))
+
+
+@pytest.mark.parametrize("theta_true", [(1.0, 0.1, 1.0), (1.0, 0.1, 0.7)])
+def test_paper_mode_fit_shift(ctx, theta_true):
+    """How far the paper's scheme for Sigma_nu moves the Fisher-BT estimate:
+    the same fit (L9 start within the paper's bounds) in both modes on 2,000
+    uniform points.  Both must converge; the shift of theta-hat is printed and
+    must stay far below the estimate's own standard error (checked at 1e-3
+    relative)."""
+    locs, z, _ = synth.dataset(2000, theta_true, 7)
+    ctx.set_data(locs, z)
+    lo, hi = (0.01, 0.01, 0.01), (5.0, 5.0, 2.0)
+    exact = ctx.fit(lo=lo, hi=hi)
+    ctx.set_sigma_nu_mode(fbt.SIGMA_NU_PAPER)
+    try:
+        paper = ctx.fit(lo=lo, hi=hi)
+    finally:
+        ctx.set_sigma_nu_mode(fbt.SIGMA_NU_EXACT)
+    rel = np.abs(paper["theta"] - exact["theta"]) / np.abs(exact["theta"])
+    say("theta_true %s: exact %s (%d iters, NM %d)  paper %s (%d iters, NM %d)  rel shift %s"
+        % (theta_true, np.round(exact["theta"], 6), exact["n_iter"], exact["used_nelder_mead"],
+           np.round(paper["theta"], 6), paper["n_iter"], paper["used_nelder_mead"], rel))
+    assert exact["converged"] and paper["converged"]
+    assert np.all(rel <= 1e-3)
