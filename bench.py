@@ -139,6 +139,46 @@ def batch_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def fit_bench(args):
+    """Algorithm 1 end to end at the benchmark size: Fisher-BT from the L9
+    start within the paper's simulation bounds, in FP64 and in the mixed form;
+    wall time per fit, call counts and the mixed form's theta-hat error."""
+    import numpy as np
+
+    import paper_2601_11437_amd as fbt
+    from paper_2601_11437_amd import synth
+
+    w = dict(synth.WORKLOADS["n20k"])
+    n = args.n
+    locs, z, _ = synth.dataset(n, w["theta_true"], w["seed"])
+    ctx = fbt.Context(0)
+    ctx.set_data(locs, z)
+    lo, hi = (0.01, 0.01, 0.01), (5.0, 5.0, 2.0)
+    ctx.loglik(w["theta_true"])   # warm-up
+    fits = {}
+    for name, prec in (("fp64", fbt.FP64), ("mixed", fbt.MIXED_FP32)):
+        ctx.set_precision(prec)
+        t0 = time.perf_counter()
+        r = ctx.fit(lo=lo, hi=hi)
+        dt = time.perf_counter() - t0
+        fits[name] = {"seconds": dt, "theta": r["theta"].tolist(), "loglik": r["loglik"],
+                      "n_loglik_calls": r["n_loglik_calls"], "n_grad_calls": r["n_grad_calls"],
+                      "n_iter": r["n_iter"], "used_nelder_mead": bool(r["used_nelder_mead"]),
+                      "converged": bool(r["converged"]), "grad_norm": float(np.linalg.norm(r["score"]))}
+        log("%s fit: %.2f s, theta %s" % (name, dt, np.round(r["theta"], 6)))
+    ctx.close()
+    t64, tm = np.array(fits["fp64"]["theta"]), np.array(fits["mixed"]["theta"])
+    out = {"metric": "Fisher-BT fit wall time at n=%d (L9 start, paper bounds)" % n,
+           "value": fits["fp64"]["seconds"], "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 1,
+           "ms_per_step": 1e3 * fits["fp64"]["seconds"], "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "Matern GRF, n=%d uniform on [0,1]^2, theta_true=%s; one full "
+                                  "Fisher-BT fit" % (n, list(w["theta_true"]))},
+           "fits": fits,
+           "mixed_theta_rel_err_vs_fp64": (np.abs(tm - t64) / np.abs(t64)).tolist()}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,7 +194,12 @@ def main():
     ap.add_argument("--batch", type=int, default=0,
                     help="instead of the n=20k evaluation, time one round over this many fields")
     ap.add_argument("--batch-workers", type=int, default=8)
+    ap.add_argument("--fit", action="store_true",
+                    help="instead of the evaluation rate, time one full Fisher-BT fit (FP64 and mixed)")
     args = ap.parse_args()
+    if args.fit and args.gpus == 1:
+        fit_bench(args)
+        return
     if args.batch and args.gpus == 1:
         batch_bench(args)
         return
