@@ -164,6 +164,7 @@ def fit_bench(args):
         fits[name] = {"seconds": dt, "theta": r["theta"].tolist(), "loglik": r["loglik"],
                       "n_loglik_calls": r["n_loglik_calls"], "n_grad_calls": r["n_grad_calls"],
                       "n_iter": r["n_iter"], "used_nelder_mead": bool(r["used_nelder_mead"]),
+                      "n_fp64_evals": r["n_fp64_evals"], "precision_switch": r["precision_switch"],
                       "converged": bool(r["converged"]), "grad_norm": float(np.linalg.norm(r["score"]))}
         log("%s fit: %.2f s, theta %s" % (name, dt, np.round(r["theta"], 6)))
     ctx.close()

@@ -160,11 +160,28 @@ typedef struct {
     int32_t nm_max_evals;     /* 500 */
     fbt_iter_cb cb;           /* may be NULL */
     void *cb_user;
+    /* 1e-4   fbt_fit on a context in a mixed precision: the score of the mixed
+     * form carries FP32 rounding of the trace terms, so it cannot resolve the
+     * stopping test at large n.  At the first derivative evaluation whose
+     * score satisfies ||grad||_2 <= mixed_switch ||s||_2, with the per-term
+     * scales s = ((q + n) / (2 sigma2), (|t_a| + |u_a|) / 2, (|t_nu| + |u_nu|) / 2)
+     * (t_i = tr(Sigma^-1 Sigma_i), u_i = w^T Sigma_i w, q = Z^T Sigma^-1 Z), the
+     * context switches to FP64 for the rest of the fit and that theta is
+     * evaluated again in FP64 (on the same factor under FBT_MIXED_FP32); the
+     * re-evaluation is not counted as a grad call.  0 never switches.  The
+     * context's precision is restored when fbt_fit returns.  Ignored by
+     * fbt_fit_evaluator and under FBT_FP64. */
+    double mixed_switch;
 } fbt_fit_options;
 
 typedef struct {
     double theta[3], loglik, score[3], fisher[9];
     int32_t n_loglik_calls, n_grad_calls, n_iter, used_nelder_mead, converged, n_nm_evals;
+    /* fbt_fit: the driver's derivative evaluations whose results are FP64
+     * (all of them under FBT_FP64; under a mixed precision those from the
+     * switch on, the one at the switch point included), and the 0-based index
+     * of the derivative evaluation at which the switch happened (-1: none). */
+    int32_t n_fp64_evals, precision_switch;
 } fbt_fit_result;
 
 void fbt_fit_options_default(fbt_fit_options *o);

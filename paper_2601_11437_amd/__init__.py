@@ -40,13 +40,14 @@ class FitOptions(ctypes.Structure):
                 ("armijo_relax", _d), ("backtrack_rho", _d), ("grad_tol", _d),
                 ("max_loglik_calls", _i32), ("max_grad_calls", _i32), ("max_iter", _i32),
                 ("nelder_mead", _i32), ("nm_ftol", _d), ("nm_max_evals", _i32),
-                ("cb", ITER_CB), ("cb_user", _p)]
+                ("cb", ITER_CB), ("cb_user", _p), ("mixed_switch", _d)]
 
 
 class FitResult(ctypes.Structure):
     _fields_ = [("theta", _d * 3), ("loglik", _d), ("score", _d * 3), ("fisher", _d * 9),
                 ("n_loglik_calls", _i32), ("n_grad_calls", _i32), ("n_iter", _i32),
-                ("used_nelder_mead", _i32), ("converged", _i32), ("n_nm_evals", _i32)]
+                ("used_nelder_mead", _i32), ("converged", _i32), ("n_nm_evals", _i32),
+                ("n_fp64_evals", _i32), ("precision_switch", _i32)]
 
 
 class Config(ctypes.Structure):
@@ -181,7 +182,8 @@ def _result(r: FitResult) -> dict:
             "fisher": np.array(r.fisher[:]).reshape(3, 3), "n_loglik_calls": r.n_loglik_calls,
             "n_grad_calls": r.n_grad_calls, "n_iter": r.n_iter,
             "used_nelder_mead": bool(r.used_nelder_mead), "converged": bool(r.converged),
-            "n_nm_evals": r.n_nm_evals}
+            "n_nm_evals": r.n_nm_evals, "n_fp64_evals": r.n_fp64_evals,
+            "precision_switch": r.precision_switch}
 
 
 def fit_with(loglik, evaluate, **opts) -> dict:

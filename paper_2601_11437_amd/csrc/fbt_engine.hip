@@ -884,6 +884,46 @@ fbt_status fbt::group_run(fbt_ctx *c, int G, const int64_t *n, const double *con
     return FBT_OK;
 }
 
+// Derivative evaluation of the Fisher-BT driver (fbt_fit).  Under a mixed
+// precision the trace terms carry FP32 rounding of the block solves, which
+// bounds how small the score can be resolved; once the mixed score is no
+// larger than mixed_switch times the norm of its per-term scales (sigma^2:
+// (q + n) / (2 sigma^2); alpha, nu: (|tr(Sigma^-1 Sigma_i)| + |w^T Sigma_i w|) / 2)
+// the context switches to FP64 for the rest of the fit (*state = 1) and the
+// same theta is evaluated again in FP64, on the same factor when the
+// factorisation was FP64 already (FBT_MIXED_FP32).
+fbt_status fbt::fit_eval(fbt_ctx *c, const double *th, double mixed_switch, int *state,
+                         double *loglik, double *score, double *fisher)
+{
+    fbt_status st = check_call(c, th);
+    if (st != FBT_OK)
+        return st;
+    double t[9];
+    if ((st = derivative_terms(c, th, t)) != FBT_OK)
+        return st;
+    assemble(c->n, th, t, loglik, score, fisher);
+    if (c->precision == FBT_FP64)
+        return FBT_OK;
+    const double s0 = (std::fabs(t[1]) + (double)c->n) / (2.0 * th[0]);
+    const double s1 = 0.5 * (std::fabs(t[2]) + std::fabs(t[4]));
+    const double s2 = 0.5 * (std::fabs(t[3]) + std::fabs(t[5]));
+    const double gn = std::sqrt(score[0] * score[0] + score[1] * score[1] + score[2] * score[2]);
+    if (!(gn <= mixed_switch * std::sqrt(s0 * s0 + s1 * s1 + s2 * s2)))
+        return FBT_OK;
+    *state = 1;
+    // derivative_terms leaves the factor of th in place; it is the FP64 one
+    // unless the Cholesky updates were FP32 as well
+    c->factor_valid = c->precision == FBT_MIXED_FP32;
+    std::memcpy(c->factor_theta, th, sizeof(c->factor_theta));
+    c->precision = FBT_FP64;
+    if ((st = derivative_terms(c, th, t)) != FBT_OK)
+        return st;
+    assemble(c->n, th, t, loglik, score, fisher);
+    return FBT_OK;
+}
+
+int fbt::ctx_precision(const fbt_ctx *c) { return c->precision; }
+
 // =========================================================================
 // C ABI
 // =========================================================================
@@ -1126,7 +1166,9 @@ fbt_status fbt_set_precision(fbt_ctx *ctx, int32_t precision)
 {
     if (!ctx || precision < FBT_FP64 || precision > FBT_MIXED_FP32_ALL)
         return FBT_EINVAL;
-    if (precision != ctx->precision)
+    // the factorisation's arithmetic differs only under FBT_MIXED_FP32_ALL
+    if (precision != ctx->precision &&
+        (precision == FBT_MIXED_FP32_ALL || ctx->precision == FBT_MIXED_FP32_ALL))
         ctx->factor_valid = false;
     ctx->precision = precision;
     return FBT_OK;

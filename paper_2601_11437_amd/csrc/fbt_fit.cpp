@@ -20,6 +20,7 @@
 //    the spread of l over the vertices is below nm_ftol or after nm_max_evals
 //    evaluations.  Its l calls do not count toward the scoring budget.
 #include "fisherbt.h"
+#include "fbt_internal.h"
 
 #include <algorithm>
 #include <cmath>
@@ -225,6 +226,7 @@ void fbt_fit_options_default(fbt_fit_options *o)
     o->nelder_mead = 1;
     o->nm_ftol = 1e-9;
     o->nm_max_evals = 500;
+    o->mixed_switch = 1e-4;
 }
 
 fbt_status fbt_fit_evaluator(const fbt_evaluator *ev, const fbt_fit_options *opt,
@@ -236,6 +238,7 @@ fbt_status fbt_fit_evaluator(const fbt_evaluator *ev, const fbt_fit_options *opt
         opt->max_grad_calls < 1 || !(opt->grad_tol >= 0) || opt->nm_max_evals < 4)
         return FBT_EINVAL;
     std::memset(out, 0, sizeof(*out));
+    out->precision_switch = -1;
     fbt_status err = FBT_OK;
     int n_ll = 0, n_grad = 0, it = 0;
     double theta[3];
@@ -345,23 +348,52 @@ fbt_status fbt_fit_evaluator(const fbt_evaluator *ev, const fbt_fit_options *opt
     return FBT_OK;
 }
 
+// The GPU evaluator of fbt_fit: derivative evaluations go through
+// fbt::fit_eval, which moves a mixed-precision context to FP64 near the
+// optimum; the driver itself is unchanged.
+struct GpuFit {
+    fbt_ctx *ctx;
+    int fp64_ctx;      // the context started in FP64
+    double sw;         // fbt_fit_options.mixed_switch
+    int state;         // 1 once the derivatives run in FP64
+    int calls, n_fp64, switch_at;
+};
+
 static fbt_status gpu_loglik(void *user, const double theta[3], double *ll)
 {
-    return fbt_loglik((fbt_ctx *)user, theta, ll);
+    return fbt_loglik(((GpuFit *)user)->ctx, theta, ll);
 }
 
 static fbt_status gpu_eval(void *user, const double theta[3], double *ll, double score[3],
                            double fisher[9])
 {
-    return fbt_eval((fbt_ctx *)user, theta, ll, score, fisher);
+    GpuFit *g = (GpuFit *)user;
+    const int before = g->state;
+    const fbt_status s = fbt::fit_eval(g->ctx, theta, g->sw, &g->state, ll, score, fisher);
+    if (s == FBT_OK) {
+        if (g->fp64_ctx || g->state)
+            ++g->n_fp64;
+        if (!before && g->state)
+            g->switch_at = g->calls;
+        ++g->calls;
+    }
+    return s;
 }
 
 fbt_status fbt_fit(fbt_ctx *ctx, const fbt_fit_options *opt, fbt_fit_result *out)
 {
-    if (!ctx)
+    if (!ctx || !opt || !(opt->mixed_switch >= 0))
         return FBT_EINVAL;
-    fbt_evaluator ev = {ctx, gpu_loglik, gpu_eval};
-    return fbt_fit_evaluator(&ev, opt, out);
+    const int32_t prec = fbt::ctx_precision(ctx);
+    GpuFit g = {ctx, prec == FBT_FP64, opt->mixed_switch, 0, 0, 0, -1};
+    fbt_evaluator ev = {&g, gpu_loglik, gpu_eval};
+    const fbt_status s = fbt_fit_evaluator(&ev, opt, out);
+    fbt_set_precision(ctx, prec);
+    if (out && (s == FBT_OK || s == FBT_EBUDGET)) {
+        out->n_fp64_evals = g.n_fp64;
+        out->precision_switch = g.switch_at;
+    }
+    return s;
 }
 
 } // extern "C"

@@ -122,4 +122,12 @@ fbt_status group_run(fbt_ctx *c, int G, const int64_t *n, const double *const *l
                      const double *const *z, const double *thetas, int mode, double *loglik,
                      double *score, double *fisher, int32_t *status);
 
+// Derivative evaluation of the Fisher-BT driver with the switch from a mixed
+// precision to FP64 near the optimum (fbt_fit_options.mixed_switch);
+// *state becomes 1 at the switch.  Defined in fbt_engine.hip.
+fbt_status fit_eval(fbt_ctx *c, const double *th, double mixed_switch, int *state,
+                    double *loglik, double *score, double *fisher);
+// the context's fbt_precision
+int ctx_precision(const fbt_ctx *c);
+
 }  // namespace fbt

@@ -156,6 +156,19 @@ def test_driver_matches_oracle_driver_on_matern(oracle_mod):
     assert (got["n_loglik_calls"], got["n_grad_calls"]) == (want["n_loglik_calls"], want["n_grad_calls"])
     np.testing.assert_allclose(got["theta"], want["theta"], rtol=1e-9)
     assert len(seen) == got["n_iter"] + 1
+    # precision switching belongs to the GPU evaluator of fbt_fit only
+    assert got["precision_switch"] == -1 and got["n_fp64_evals"] == 0
+
+
+def test_fit_option_defaults():
+    """fbt_fit_options_default: the paper's constants (Section 2.1, Eq. (4))
+    and the mixed-precision switch point."""
+    o, _ = fbt._options()
+    assert tuple(o.lo) == (0.01, 0.01, 0.01) and tuple(o.hi) == (5.0, 5.0, 2.0)
+    assert (o.armijo_c, o.armijo_relax, o.backtrack_rho, o.grad_tol) == (1e-3, 1e-3, 0.5, 1e-3)
+    assert (o.max_loglik_calls, o.max_grad_calls, o.max_iter, o.nelder_mead) == (60, 20, 0, 1)
+    assert (o.nm_ftol, o.nm_max_evals) == (1e-9, 500)
+    assert o.mixed_switch == 1e-4
 
 
 def test_create_without_gpu_fails_cleanly():

@@ -223,3 +223,36 @@ def test_mixed_precision(ctx, oracle_mod, n, theta):
     d = np.sqrt(np.outer(np.diag(want["fisher"]), np.diag(want["fisher"])))
     assert np.all(np.abs(fisher - want["fisher"]) <= 1e-4 * d)
     assert np.array_equal(score[:1], s64[:1])          # sigma2 score: FP64 quadratic form
+
+
+def test_mixed_fit_switches_to_fp64(ctx):
+    """Fisher-BT on a context in the mixed form: Fisher steps from mixed
+    derivatives while the score is large, FP64 from the switch point on, so
+    the stopping test is always taken on an FP64 score.  The result is a
+    stationary point of the FP64 log-likelihood (||grad||_2 <= 1e-3 in a fresh
+    FP64 evaluation) and agrees with the FP64 fit to 1e-5 relative in theta."""
+    n = 2000
+    say("mixed fit n=%d" % n)
+    locs, z, _ = synth.dataset(n, (1.0, 0.1, 0.5), 2024)
+    ctx.set_data(locs, z)
+    r64 = ctx.fit()
+    assert r64["converged"] and r64["precision_switch"] == -1
+    assert r64["n_fp64_evals"] == r64["n_grad_calls"] + (1 if r64["used_nelder_mead"] else 0)
+    ctx.set_precision(fbt.MIXED_FP32)
+    try:
+        rm = ctx.fit()
+        _, g_after, _ = ctx.eval((1.0, 0.1, 0.5))      # fbt_fit restored the mixed form
+        rnever = ctx.fit(mixed_switch=0.0)
+    finally:
+        ctx.set_precision(fbt.FP64)
+    assert not np.array_equal(g_after[1:], ctx.eval((1.0, 0.1, 0.5))[1][1:])
+    say("fp64", r64["theta"], r64["n_grad_calls"], "mixed", rm["theta"], rm["n_grad_calls"],
+        "switch at", rm["precision_switch"], "fp64 evals", rm["n_fp64_evals"],
+        "never-switch", rnever["theta"], rnever["converged"])
+    assert rm["converged"] and not rm["used_nelder_mead"]
+    assert 0 <= rm["precision_switch"] < rm["n_grad_calls"]
+    assert rm["n_fp64_evals"] == rm["n_grad_calls"] - rm["precision_switch"]
+    assert rnever["precision_switch"] == -1 and rnever["n_fp64_evals"] == 0
+    ll, g, _ = ctx.eval(tuple(rm["theta"]))
+    assert np.linalg.norm(g) <= 1e-3 and ll == rm["loglik"]
+    np.testing.assert_allclose(rm["theta"], r64["theta"], rtol=1e-5)
