@@ -238,30 +238,117 @@ void launch_gen(hipStream_t s, const GenParams &gp, const GenParams *gpa, const 
 
 // ---------------------------------------------------------------------------
 // Diagonal block: Cholesky factor L_kk (in place) and its inverse Linv_k, by
-// one workgroup of 512 threads, right-looking over 32-column panels
-// p = 0..7 (jb = 32 p):
-//  1. thread t < 256 - jb holds row jb + t of the panel in registers and the
-//     panel is factored column by column: the 32 top-block values of column c
-//     go through a double-buffered LDS line, one barrier per column;
-//  2. the panel is written back and kept in LDS (Lp);
-//  3. D_p = inverse of its 32 x 32 top block (threads t < 32, a column each);
-//  4. inverse, block row p, by right-looking forward substitution of
-//     L X = I: X_p = D_p [B_p | I] with B_p the updates of block row p by the
-//     earlier panels;
-//  5. trailing update A[i][j] -= Lp[i] Lp[j]^T (jb + 32 <= j <= i < 256);
-//  6. inverse update of the rows below: B_i -= Lp[i] X_p.
-// MFMA operands of steps 4-6 come from LDS; their C tiles stay in L2 and are
-// loaded in batches of four 16 x 16 tiles per wave.  Linv starts at zero, so
-// its strict upper part is exactly zero.
+// one workgroup of 512 threads over 32-column panels p = 0..7 (jb = 32 p).
+// Per panel:
+//  A. the panel's 32 x 32 top block T = L_t L_t^T is factored by wave 0 and
+//     D_p = L_t^{-1} formed by wave 1 one column behind it, both in registers
+//     with one row per lane (column c of L_t goes through LDS, published to
+//     wave 1 by a counter).  At the same time waves 2..7 finish the previous
+//     panel's updates: trailing tiles outside the next two tile columns, and
+//     the inverse rows below it, B_i -= Lp[i] X_{p-1};
+//  B. L_t and D_p are stored; the rows below the top block L_b = A_b D_p^T
+//     and the inverse block row X_p = D_p [B_p | I] (B_p: block row p of
+//     Linv as updated by the earlier panels) are formed on MFMA;
+//  C. X_p goes to Linv, and the trailing tiles of the next two tile columns
+//     (the next panel, whose top block also lands in LDS) are updated with
+//     L_b on MFMA, so the next panel's top block is ready for step A.
+// MFMA operands come from LDS (Lp, D_p, X_p) or, for L_b, from the block
+// itself; C tiles stay in L2 and are loaded in batches of four 16 x 16 tiles
+// per wave.  Linv starts at zero, so its strict upper part is exactly zero.
 // Pivot rule: rows g >= n (the observation border and the identity padding)
 // take pivot 1; a pivot <= 0 or NaN at g < n records min(g) in *info and
 // continues with pivot 1 so that nothing downstream becomes non-finite.
 // logdet_part[k] = sum of log(pivot) over rows g < n of the block.
 // ---------------------------------------------------------------------------
 constexpr int PW = 32;
-constexpr int LPS = PW + 1; // LDS row stride of the panel and of D_p
+constexpr int LPS = PW + 1; // LDS row stride of the panel, the top block and D_p
 constexpr int XPS = NB + 1; // LDS row stride of X_p (PW x NB)
-constexpr int DT = 256;     // threads of the diagonal kernel
+constexpr int DT = 512;     // threads of the diagonal kernel
+constexpr int NWD = DT / 64;
+
+// value of v in lane l (l wave-uniform) as a scalar
+__device__ __forceinline__ double lane_value(double v, int l)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+// Lanes of one wave exchanging values through LDS: stores before this point
+// are visible to the loads after it in every lane of the wave (and neither
+// moves across it).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// row and column of the u-th tile of a lower triangle of tiles (row-major order)
+__device__ __forceinline__ void tri_tile(int u, int *ti, int *tj)
+{
+    int i = (int)((sqrt(8.0 * u + 1.0) - 1.0) * 0.5);
+    while ((i + 1) * (i + 2) / 2 <= u)
+        ++i;
+    while (i * (i + 1) / 2 > u)
+        --i;
+    *ti = i;
+    *tj = u - i * (i + 1) / 2;
+}
+
+// C -= L_b[ia..] X^T over 16 x 16 tiles, four per wave at a time.  map(u, q)
+// returns the C tile pointer of unit u (nullptr past the end) and sets
+// ia[q] (its first row within the panel), jbk[q] (its first column: a row of
+// Lp, or a column of X_p when inv[q]) and ldc[q]; with tb, the tiles of the
+// next panel's top block are also written to tb.
+template <class Map>
+__device__ __forceinline__ void tile_update(int nu, int wv, int nw, int lane, const double *Lp,
+                                            const double *Xp, double *tb, Map map)
+{
+    for (int u0 = wv * 4; u0 < nu; u0 += nw * 4) {
+        d4 acc[4];
+        double *cp[4];
+        int ia[4], jbk[4];
+        int64_t ldc[4];
+        bool inv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            cp[q] = (u0 + q < nu) ? map(u0 + q, &ia[q], &jbk[q], &ldc[q], &inv[q]) : nullptr;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (cp[q]) {
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr)
+                    acc[q][rr] = cp[q][(lane & 15) + (int64_t)((lane >> 4) + 4 * rr) * ldc[q]];
+            }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (cp[q]) {
+#pragma unroll
+                for (int s4 = 0; s4 < PW / 4; ++s4) {
+                    const int k = 4 * s4 + (lane >> 4);
+                    const double a = -Lp[(ia[q] + (lane & 15)) * LPS + k];
+                    const double b = inv[q] ? Xp[k * XPS + jbk[q] + (lane & 15)]
+                                            : Lp[(jbk[q] + (lane & 15)) * LPS + k];
+                    acc[q] = mfma(b, a, acc[q]);
+                }
+            }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (cp[q]) {
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr)
+                    cp[q][(lane & 15) + (int64_t)((lane >> 4) + 4 * rr) * ldc[q]] = acc[q][rr];
+                // the next panel's top block: trailing rows / columns 0..31
+                if (tb && !inv[q] && ia[q] < 2 * PW && jbk[q] < 2 * PW) {
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr)
+                        tb[(ia[q] - PW + (lane & 15)) * LPS + jbk[q] - PW + (lane >> 4) + 4 * rr] =
+                            acc[q][rr];
+                }
+            }
+    }
+}
 
 __global__ __launch_bounds__(DT) void k_potrf_diag(Fields F, double *__restrict__ A, int64_t lda,
                                                    int kblk, int64_t n1, double *__restrict__ Linv,
@@ -274,168 +361,191 @@ __global__ __launch_bounds__(DT) void k_potrf_diag(Fields F, double *__restrict_
     logdet_part += f * F.sLog;
     info += f;
     const int64_t n = F.n ? F.n[f] : n1;
-    __shared__ double Lp[NB * LPS];
-    __shared__ double Xp[PW * XPS];
-    __shared__ double Dp[PW * LPS];
-    __shared__ double colbuf[2][PW];
+    __shared__ double Lp[NB * LPS];   // the panel: L_t in rows 0..31, L_b below
+    __shared__ double Xp[PW * XPS];   // X_p
+    __shared__ double Tb[PW * LPS];   // top block of the panel -> L_t
+    __shared__ double Db[PW * LPS];   // D_p (strict upper part stays zero)
+    __shared__ double colb[PW * PW];  // column c of L_t at colb[c PW + i]
     __shared__ double piv[NB];
-    __shared__ double sh[DT / 64];
+    __shared__ double sh[NWD];
+    __shared__ int colready;          // columns of L_t published by wave 0
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int64_t o = (int64_t)kblk * NB;
     double *Ab = A + o + o * lda;
 
     for (int idx = t; idx < NB * NB; idx += DT)
         Linv[idx] = 0.0;
+    for (int idx = t; idx < PW * PW; idx += DT) {
+        const int row = idx % PW, col = idx / PW;
+        Tb[row * LPS + col] = Ab[row + (int64_t)col * lda];
+        Db[row * LPS + col] = 0.0;
+    }
+    if (t == 0)
+        colready = 0;
+    __syncthreads();
 
     for (int p = 0; p < NB / PW; ++p) {
         const int jb = p * PW, M = NB - jb;
-        // 1. panel rows into registers, factored column by column
-        double r[PW];
-        double mypiv = 1.0;
-        if (t < M) {
+        const int nt = (M - PW) / 16; // 16-row tiles below the panel's top block
+        // ---- A. top block of panel p ‖ the rest of panel p - 1's updates ----
+        if (wave == 0) {
+            int i = lane & 31;
+            // fresh per panel: keeps the lane masks below from being hoisted
+            // out of the panel loop (they would not fit in scalar registers)
+            asm volatile("" : "+v"(i));
+            double r[PW];
+            // whole rows: entries above the diagonal are never used (rows
+            // above c are cleared at step c before anything reads them)
 #pragma unroll
             for (int c = 0; c < PW; ++c)
-                r[c] = Ab[(jb + t) + (int64_t)(jb + c) * lda];
-        }
-#pragma unroll
-        for (int c = 0; c < PW; ++c) {
-            if (t >= c && t < PW)
-                colbuf[c & 1][t] = r[c];
-            __syncthreads();
-            const double d = colbuf[c & 1][c];
-            const int64_t g = o + jb + c;
-            const bool bad = (g < n) && !(d > 0.0);
-            const double pv = (g >= n || bad) ? 1.0 : sqrt(d);
-            const double ip = 1.0 / pv;
-            if (t == c) {
-                mypiv = pv;
-                piv[jb + c] = pv;
-                if (bad)
-                    atomicMin(info, (int)g);
-            }
-            if (t > c && t < M) {
-                const double l = r[c] * ip;
-                r[c] = l;
-#pragma unroll
-                for (int c2 = c + 1; c2 < PW; ++c2)
-                    r[c2] -= l * (colbuf[c & 1][c2] * ip);
-            }
-        }
-        // 2. write back (top block: lower triangle with the pivots) and keep in LDS
-        if (t < M) {
+                r[c] = Tb[i * LPS + c];
+            int firstbad = 0x7fffffff; // wave-uniform
 #pragma unroll
             for (int c = 0; c < PW; ++c) {
-                const bool keep = (t >= PW) || (c <= t);
-                const double v = (t == c) ? mypiv : r[c];
-                if (keep)
-                    Ab[(jb + t) + (int64_t)(jb + c) * lda] = v;
-                Lp[t * LPS + c] = keep ? v : 0.0;
+                const double d = lane_value(r[c], c);
+                const int g = (int)(o + jb + c);
+                const bool bad = (g < n) && !(d > 0.0); // the same in every lane
+                const double pv = (g >= n || bad) ? 1.0 : sqrt(d);
+                const double ip = 1.0 / pv;
+                firstbad = (bad && firstbad == 0x7fffffff) ? g : firstbad;
+                r[c] = (i > c) ? r[c] * ip : (i == c ? pv : 0.0);
+                if (lane < PW)
+                    colb[c * PW + i] = r[c];
+                wave_sync();
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                if (lane == 0)
+                    __hip_atomic_store(&colready, c + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+                for (int j = c + 1; j < PW; ++j) {
+                    r[j] -= r[c] * colb[c * PW + j];
+                    asm volatile("" : "+v"(r[j])); // update in place
+                }
             }
+            if (lane == 0 && firstbad != 0x7fffffff)
+                atomicMin(info, firstbad);
+            if (lane < PW) {
+#pragma unroll
+                for (int c = 0; c < PW; ++c)
+                    Tb[i * LPS + c] = r[c];
+            }
+        } else if (wave == 1) {
+            // D_p = L_t^{-1} by forward elimination, one column of L_t behind
+            // wave 0: row m is final once divided by its pivot, then it is
+            // removed from the rows below it
+            int i = lane & 31;
+            asm volatile("" : "+v"(i));
+            double x[PW];
+#pragma unroll
+            for (int k = 0; k < PW; ++k)
+                x[k] = (k == i) ? 1.0 : 0.0;
+#pragma unroll
+            for (int m = 0; m < PW; ++m) {
+                while (__hip_atomic_load(&colready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) <= m)
+                    __builtin_amdgcn_s_sleep(1);
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                const double ipm = 1.0 / colb[m * PW + m];
+                const double lim = (i > m) ? colb[m * PW + i] : 0.0;
+                if (lane == m) {
+#pragma unroll
+                    for (int k = 0; k <= m; ++k)
+                        Db[m * LPS + k] = x[k] * ipm;
+                }
+                wave_sync();
+#pragma unroll
+                for (int k = 0; k <= m; ++k) {
+                    x[k] -= lim * Db[m * LPS + k];
+                    asm volatile("" : "+v"(x[k]));
+                }
+            }
+        } else if (p > 0) {
+            // panel p - 1: trailing tiles in tile columns >= 2 of its trailing
+            // block, then the inverse rows below it
+            const int jq = jb - PW, ntq = nt + 2;
+            const int nr = (ntq - 2) * (ntq - 1) / 2, nc6 = jb / 16;
+            tile_update(nr + ntq * nc6, wave - 2, NWD - 2, lane, Lp, Xp, nullptr,
+                        [&](int u, int *ia, int *jbk, int64_t *ldc, bool *inv) -> double * {
+                            if (u < nr) {
+                                int i, j;
+                                tri_tile(u, &i, &j);
+                                *ia = PW + 16 * (i + 2);
+                                *jbk = PW + 16 * (j + 2);
+                                *ldc = lda;
+                                *inv = false;
+                                return Ab + (jq + *ia) + (int64_t)(jq + *jbk) * lda;
+                            }
+                            const int v = u - nr;
+                            *ia = PW + 16 * (v % ntq);
+                            *jbk = 16 * (v / ntq);
+                            *ldc = NB;
+                            *inv = true;
+                            return Linv + (jq + *ia) + (int64_t)*jbk * NB;
+                        });
         }
         __syncthreads();
-        // 3. D_p, column t of the inverse of the top block
-        if (t < PW) {
-            double col[PW];
-#pragma unroll
-            for (int i = 0; i < PW; ++i) {
-                double sacc = (i == t) ? 1.0 : 0.0;
-#pragma unroll
-                for (int m = 0; m < i; ++m)
-                    sacc -= Lp[i * LPS + m] * col[m];
-                col[i] = (i < t) ? 0.0 : sacc / Lp[i * LPS + i];
+        // ---- B. store L_t and D_p; L_b = A_b D_p^T; X_p[:, 0:jb] = D_p B_p ----
+        if (t == 0)
+            colready = 0;
+        for (int idx = t; idx < PW * PW; idx += DT) {
+            const int row = idx % PW, col = idx / PW;
+            const double lv = Tb[row * LPS + col], dv = Db[row * LPS + col];
+            Lp[row * LPS + col] = lv;
+            Xp[row * XPS + jb + col] = dv;
+            if (col <= row) {
+                Ab[(jb + row) + (int64_t)(jb + col) * lda] = lv;
+                Linv[(jb + row) + (int64_t)(jb + col) * NB] = dv;
             }
-#pragma unroll
-            for (int i = 0; i < PW; ++i) {
-                Dp[i * LPS + t] = col[i];
-                Xp[i * XPS + jb + t] = col[i];
-                Linv[(jb + i) + (int64_t)(jb + t) * NB] = col[i];
-            }
+            if (row == col)
+                piv[jb + row] = lv;
         }
-        __syncthreads();
-        // 4. X_p[:, 0:jb] = D_p B_p[:, 0:jb] (into LDS first: B_p is read in place)
-        for (int u = wave; u < 2 * (jb / 16); u += DT / 64) {
-            const int ti = u & 1, tj = u >> 1;
+        const int nlb = 2 * nt; // tiles of L_b
+        for (int u = wave; u < nlb + 2 * (jb / 16); u += NWD) {
             d4 acc = {0, 0, 0, 0};
+            if (u < nlb) {
+                const int ti = u >> 1, tj = u & 1;
+                const double *Arow = Ab + (jb + PW + 16 * ti + (lane & 15)) + (int64_t)jb * lda;
 #pragma unroll
-            for (int s4 = 0; s4 < PW / 4; ++s4) {
-                const int k = 4 * s4 + (lane >> 4);
-                const double a = Dp[(16 * ti + (lane & 15)) * LPS + k];
-                const double b = Linv[(jb + k) + (int64_t)(16 * tj + (lane & 15)) * NB];
-                acc = mfma(b, a, acc);
+                for (int s4 = 0; s4 < PW / 4; ++s4) {
+                    const int k = 4 * s4 + (lane >> 4);
+                    const double a = Arow[(int64_t)k * lda];
+                    const double b = Db[(16 * tj + (lane & 15)) * LPS + k];
+                    acc = mfma(b, a, acc);
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int R = PW + 16 * ti + (lane & 15), C = 16 * tj + (lane >> 4) + 4 * q;
+                    Lp[R * LPS + C] = acc[q];
+                    Ab[(jb + R) + (int64_t)(jb + C) * lda] = acc[q];
+                }
+            } else {
+                const int v = u - nlb, ti = v & 1, tj = v >> 1;
+#pragma unroll
+                for (int s4 = 0; s4 < PW / 4; ++s4) {
+                    const int k = 4 * s4 + (lane >> 4);
+                    const double a = Db[(16 * ti + (lane & 15)) * LPS + k];
+                    const double b = Linv[(jb + k) + (int64_t)(16 * tj + (lane & 15)) * NB];
+                    acc = mfma(b, a, acc);
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    Xp[(16 * ti + (lane & 15)) * XPS + 16 * tj + (lane >> 4) + 4 * q] = acc[q];
             }
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                Xp[(16 * ti + (lane & 15)) * XPS + 16 * tj + (lane >> 4) + 4 * q] = acc[q];
         }
         __syncthreads();
+        // ---- C. X_p to Linv; the next panel's two tile columns ----
         for (int idx = t; idx < PW * jb; idx += DT) {
             const int row = idx % PW, col = idx / PW;
             Linv[(jb + row) + (int64_t)col * NB] = Xp[row * XPS + col];
         }
-        // 5. trailing update of the block and 6. inverse update of the rows below
-        const int nt = (M - PW) / 16;         // 16-row tiles below the panel's top block
-        const int n5 = nt * (nt + 1) / 2;     // lower tiles of the trailing block
-        const int nc6 = (jb + PW) / 16;       // 16-column tiles of X_p
-        const int nunits = n5 + nt * nc6;
-        for (int u0 = wave * 4; u0 < nunits; u0 += (DT / 64) * 4) {
-            d4 acc[4];
-            double *cp[4];
-            int ia[4], jbk[4];
-            bool inv[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int u = u0 + q;
-                cp[q] = nullptr;
-                ia[q] = 0;
-                jbk[q] = 0;
-                inv[q] = false;
-                if (u < n5) {
-                    int i = (int)((sqrt(8.0 * u + 1.0) - 1.0) * 0.5);
-                    while ((i + 1) * (i + 2) / 2 <= u)
-                        ++i;
-                    while (i * (i + 1) / 2 > u)
-                        --i;
-                    const int j = u - i * (i + 1) / 2;
-                    ia[q] = PW + 16 * i;
-                    jbk[q] = PW + 16 * j;
-                    cp[q] = Ab + (jb + ia[q]) + (int64_t)(jb + jbk[q]) * lda;
-                } else if (u < nunits) {
-                    const int v = u - n5, i = v % nt, j = v / nt;
-                    ia[q] = PW + 16 * i;
-                    jbk[q] = 16 * j;
-                    inv[q] = true;
-                    cp[q] = Linv + (jb + ia[q]) + (int64_t)jbk[q] * NB;
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (cp[q]) {
-                    const int64_t ldc = inv[q] ? NB : lda;
-#pragma unroll
-                    for (int rr = 0; rr < 4; ++rr)
-                        acc[q][rr] = cp[q][(lane & 15) + (int64_t)((lane >> 4) + 4 * rr) * ldc];
-                }
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (cp[q]) {
-#pragma unroll
-                    for (int s4 = 0; s4 < PW / 4; ++s4) {
-                        const int k = 4 * s4 + (lane >> 4);
-                        const double a = -Lp[(ia[q] + (lane & 15)) * LPS + k];
-                        const double b = inv[q] ? Xp[k * XPS + jbk[q] + (lane & 15)]
-                                                : Lp[(jbk[q] + (lane & 15)) * LPS + k];
-                        acc[q] = mfma(b, a, acc[q]);
-                    }
-                }
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (cp[q]) {
-                    const int64_t ldc = inv[q] ? NB : lda;
-#pragma unroll
-                    for (int rr = 0; rr < 4; ++rr)
-                        cp[q][(lane & 15) + (int64_t)((lane >> 4) + 4 * rr) * ldc] = acc[q][rr];
-                }
-        }
+        if (nt > 0)
+            tile_update(2 * nt - 1, wave, NWD, lane, Lp, Xp, Tb,
+                        [&](int u, int *ia, int *jbk, int64_t *ldc, bool *inv) -> double * {
+                            const int j = u < nt ? 0 : 1, i = u < nt ? u : u - nt + 1;
+                            *ia = PW + 16 * i;
+                            *jbk = PW + 16 * j;
+                            *ldc = lda;
+                            *inv = false;
+                            return Ab + (jb + *ia) + (int64_t)(jb + *jbk) * lda;
+                        });
         __syncthreads();
     }
     // log-determinant of the block: fixed-order tree over the NB pivots
@@ -448,7 +558,7 @@ __global__ __launch_bounds__(DT) void k_potrf_diag(Fields F, double *__restrict_
     __syncthreads();
     if (t == 0) {
         double s = 0.0;
-        for (int w = 0; w < DT / 64; ++w)
+        for (int w = 0; w < NWD; ++w)
             s += sh[w];
         logdet_part[kblk] = s;
     }
