@@ -296,11 +296,11 @@ __device__ __forceinline__ void tri_tile(int u, int *ti, int *tj)
     *tj = u - i * (i + 1) / 2;
 }
 
-// C -= L_b[ia..] X^T over 16 x 16 tiles, four per wave at a time.  map(u, q)
-// returns the C tile pointer of unit u (nullptr past the end) and sets
-// ia[q] (its first row within the panel), jbk[q] (its first column: a row of
-// Lp, or a column of X_p when inv[q]) and ldc[q]; with tb, the tiles of the
-// next panel's top block are also written to tb.
+// C -= L_b[ia..] X^T over 16 x 16 tiles, four per wave at a time.  map(u,
+// ...) returns the C tile pointer of unit u and sets ia (its first row within
+// the panel), jbk (its first column: a row of Lp, or a column of X_p when
+// inv) and ldc; with tb, the tiles of the next panel's top block are also
+// written to tb.
 template <class Map>
 __device__ __forceinline__ void tile_update(int nu, int wv, int nw, int lane, const double *Lp,
                                             const double *Xp, double *tb, Map map)
@@ -368,6 +368,7 @@ __global__ __launch_bounds__(DT) void k_potrf_diag(Fields F, double *__restrict_
     __shared__ double colb[PW * PW];  // column c of L_t at colb[c PW + i]
     __shared__ double piv[NB];
     __shared__ double sh[NWD];
+    __shared__ double ipv[PW];        // 1 / pivot of each column of L_t
     __shared__ int colready;          // columns of L_t published by wave 0
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int64_t o = (int64_t)kblk * NB;
@@ -405,20 +406,23 @@ __global__ __launch_bounds__(DT) void k_potrf_diag(Fields F, double *__restrict_
                 const double d = lane_value(r[c], c);
                 const int g = (int)(o + jb + c);
                 const bool bad = (g < n) && !(d > 0.0); // the same in every lane
-                const double pv = (g >= n || bad) ? 1.0 : sqrt(d);
-                const double ip = 1.0 / pv;
+                const bool one = g >= n || bad;
+                const double ip = one ? 1.0 : rsqrt(d);
+                const double pv = one ? 1.0 : d * ip;
                 firstbad = (bad && firstbad == 0x7fffffff) ? g : firstbad;
                 r[c] = (i > c) ? r[c] * ip : (i == c ? pv : 0.0);
+                // column c and 1 / pivot to wave 1
                 if (lane < PW)
                     colb[c * PW + i] = r[c];
-                wave_sync();
+                if (lane == 0)
+                    ipv[c] = ip;
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                 if (lane == 0)
                     __hip_atomic_store(&colready, c + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 #pragma unroll
                 for (int j = c + 1; j < PW; ++j) {
-                    r[j] -= r[c] * colb[c * PW + j];
-                    asm volatile("" : "+v"(r[j])); // update in place
+                    r[j] -= r[c] * lane_value(r[c], j);
+                    asm volatile("" : "+v"(r[j])); // update in place: no broadcast outlives its use
                 }
             }
             if (lane == 0 && firstbad != 0x7fffffff)
@@ -431,10 +435,10 @@ __global__ __launch_bounds__(DT) void k_potrf_diag(Fields F, double *__restrict_
         } else if (wave == 1) {
             // D_p = L_t^{-1} by forward elimination, one column of L_t behind
             // wave 0: row m is final once divided by its pivot, then it is
-            // removed from the rows below it
+            // removed from the rows below it (broadcast by readlane)
             int i = lane & 31;
             asm volatile("" : "+v"(i));
-            double x[PW];
+            double x[PW], myip = 1.0;
 #pragma unroll
             for (int k = 0; k < PW; ++k)
                 x[k] = (k == i) ? 1.0 : 0.0;
@@ -443,19 +447,22 @@ __global__ __launch_bounds__(DT) void k_potrf_diag(Fields F, double *__restrict_
                 while (__hip_atomic_load(&colready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) <= m)
                     __builtin_amdgcn_s_sleep(1);
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-                const double ipm = 1.0 / colb[m * PW + m];
+                const double ipm = ipv[m];
                 const double lim = (i > m) ? colb[m * PW + i] : 0.0;
-                if (lane == m) {
-#pragma unroll
-                    for (int k = 0; k <= m; ++k)
-                        Db[m * LPS + k] = x[k] * ipm;
-                }
-                wave_sync();
+                myip = (i == m) ? ipm : myip;
 #pragma unroll
                 for (int k = 0; k <= m; ++k) {
-                    x[k] -= lim * Db[m * LPS + k];
+                    x[k] -= lim * (lane_value(x[k], m) * ipm);
                     asm volatile("" : "+v"(x[k]));
                 }
+            }
+            // row i of D_p: the eliminated row divided by its pivot
+            asm volatile("" : "+v"(i));
+            if (lane < PW) {
+#pragma unroll
+                for (int k = 0; k < PW; ++k)
+                    if (k <= i)
+                        Db[i * LPS + k] = x[k] * myip;
             }
         } else if (p > 0) {
             // panel p - 1: trailing tiles in tile columns >= 2 of its trailing
@@ -497,27 +504,30 @@ __global__ __launch_bounds__(DT) void k_potrf_diag(Fields F, double *__restrict_
             if (row == col)
                 piv[jb + row] = lv;
         }
-        const int nlb = 2 * nt; // tiles of L_b
-        for (int u = wave; u < nlb + 2 * (jb / 16); u += NWD) {
+        // one unit per 16-row tile of L_b (both column halves: the unit
+        // overwrites the A_b rows it reads), then the tiles of X_p
+        for (int u = wave; u < nt + 2 * (jb / 16); u += NWD) {
             d4 acc = {0, 0, 0, 0};
-            if (u < nlb) {
-                const int ti = u >> 1, tj = u & 1;
-                const double *Arow = Ab + (jb + PW + 16 * ti + (lane & 15)) + (int64_t)jb * lda;
+            if (u < nt) {
+                d4 acc1 = {0, 0, 0, 0};
+                const double *Arow = Ab + (jb + PW + 16 * u + (lane & 15)) + (int64_t)jb * lda;
 #pragma unroll
                 for (int s4 = 0; s4 < PW / 4; ++s4) {
                     const int k = 4 * s4 + (lane >> 4);
                     const double a = Arow[(int64_t)k * lda];
-                    const double b = Db[(16 * tj + (lane & 15)) * LPS + k];
-                    acc = mfma(b, a, acc);
+                    acc = mfma(Db[(lane & 15) * LPS + k], a, acc);
+                    acc1 = mfma(Db[(16 + (lane & 15)) * LPS + k], a, acc1);
                 }
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const int R = PW + 16 * ti + (lane & 15), C = 16 * tj + (lane >> 4) + 4 * q;
+                    const int R = PW + 16 * u + (lane & 15), C = (lane >> 4) + 4 * q;
                     Lp[R * LPS + C] = acc[q];
+                    Lp[R * LPS + C + 16] = acc1[q];
                     Ab[(jb + R) + (int64_t)(jb + C) * lda] = acc[q];
+                    Ab[(jb + R) + (int64_t)(jb + C + 16) * lda] = acc1[q];
                 }
             } else {
-                const int v = u - nlb, ti = v & 1, tj = v >> 1;
+                const int v = u - nt, ti = v & 1, tj = v >> 1;
 #pragma unroll
                 for (int s4 = 0; s4 < PW / 4; ++s4) {
                     const int k = 4 * s4 + (lane >> 4);

@@ -134,6 +134,22 @@ def test_determinism(ctx):
     np.testing.assert_array_equal(a, c)
 
 
+def test_factorisation_repeats_bitwise(ctx):
+    """Sixty factorisations of one covariance give the bitwise same
+    log-likelihood and factor: every reduction has a fixed order and no
+    workgroup reads a value another one may still be writing (a regression
+    test for an in-place race in the diagonal-block kernel, seen in about one
+    launch in fifty)."""
+    say("factorisation repeats")
+    locs, z, _ = synth.dataset(1000, (1.0, 0.1, 0.5), 6)
+    ctx.set_data(locs, z)
+    theta = (0.9, 0.07, 1.3)
+    ref = ctx.factor(theta)
+    lls = {ctx.loglik(theta) for _ in range(60)}
+    assert len(lls) == 1
+    np.testing.assert_array_equal(ctx.factor(theta), ref)
+
+
 def test_not_positive_definite(ctx, oracle_mod):
     """A covariance that is numerically indefinite (range 50 and smoothness 4
     on 300 points of the unit square: condition number far beyond 1/eps) fails
