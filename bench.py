@@ -180,6 +180,107 @@ def fit_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def grid_bench(args):
+    """The 3 x 3 simulation grid at n = 10,000 (100 x 100 jittered grid):
+    one FP64 Fisher-BT fit (L9 start, paper bounds) per true theta."""
+    import numpy as np
+
+    import paper_2601_11437_amd as fbt
+    from paper_2601_11437_amd import synth
+
+    ctx = fbt.Context(0)
+    fits, total = [], 0.0
+    for ib in range(3):
+        for inu in range(3):
+            w = synth.grid_workload(ib, inu)
+            t0 = time.perf_counter()
+            locs, z, info = synth.dataset(w["n"], w["theta_true"], w["seed"], design=w["design"])
+            tg = time.perf_counter() - t0
+            ctx.set_data(locs, z)
+            t0 = time.perf_counter()
+            r = ctx.fit()
+            dt = time.perf_counter() - t0
+            total += dt
+            fits.append({"theta_true": list(w["theta_true"]), "seed": w["seed"],
+                         "redraws": info["redraws"], "seconds": dt, "theta_hat": r["theta"].tolist(),
+                         "loglik": r["loglik"], "grad_norm": float(np.linalg.norm(r["score"])),
+                         "n_loglik_calls": r["n_loglik_calls"], "n_grad_calls": r["n_grad_calls"],
+                         "n_iter": r["n_iter"], "used_nelder_mead": r["used_nelder_mead"],
+                         "converged": r["converged"]})
+            log("grid theta_true %s: data %.1f s, fit %.2f s, theta_hat %s, %d l / %d grad calls%s"
+                % (w["theta_true"], tg, dt, np.round(r["theta"], 5), r["n_loglik_calls"],
+                   r["n_grad_calls"], ", Nelder-Mead" if r["used_nelder_mead"] else ""))
+    ctx.close()
+    out = {"metric": "Fisher-BT fits/s, 3x3 grid at n=10,000 (jittered 100x100 grid)",
+           "value": len(fits) / total, "unit": "fits/s", "n_gpus": 1, "steps": len(fits),
+           "warmup": 0, "ms_per_step": 1e3 * total / len(fits), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "100x100 grid on [0,1]^2 with +-0.4 cell jitter; sigma2 = 1, "
+                                  "beta in {0.03, 0.1, 0.3}, nu in {0.5, 1.0, 2.5}; one "
+                                  "realisation and one FP64 Fisher-BT fit per setting"},
+           "fits": fits}
+    print(json.dumps(out), flush=True)
+
+
+def precision_bench(args):
+    """FP64 against the mixed forms at n = 50,000 (theta = (1, 0.05, 0.8)):
+    one evaluation each, errors of l, score and Fisher against FP64."""
+    import numpy as np
+
+    import paper_2601_11437_amd as fbt
+    from paper_2601_11437_amd import synth
+
+    w = synth.WORKLOADS["n50k"]
+    n, theta = args.n if args.n != 20000 else w["n"], w["theta_true"]
+    gen = synth.rng(w["seed"])
+    locs = synth.uniform_locations(n, gen)
+    z = synth.rff_field(locs, theta, gen)
+    ctx = fbt.Context(0)
+    ctx.set_data(locs, z)
+    res = {}
+    for name, prec in (("fp64", fbt.FP64), ("mixed_fp32", fbt.MIXED_FP32),
+                       ("mixed_fp32_all", fbt.MIXED_FP32_ALL)):
+        ctx.set_precision(prec)
+        try:
+            t0 = time.perf_counter()
+            ll_only = ctx.loglik(theta)
+            t1 = time.perf_counter()
+            terms = ctx.eval_terms(theta)        # reuses the factor of the loglik call
+            t2 = time.perf_counter()
+            ll, sc, fi = ctx.eval(theta)          # factors afresh
+            t3 = time.perf_counter()
+        except fbt.FisherBTError as e:
+            res[name] = {"status": str(e)}
+            log("%s: %s" % (name, e))
+            continue
+        res[name] = {"loglik": ll, "score": sc.tolist(), "fisher": fi.tolist(), "terms": terms.tolist(),
+                     "loglik_s": t1 - t0, "eval_s": t3 - t2, "w_phase_s": t2 - t1}
+        log("%s: loglik %.3f s, eval %.3f s" % (name, t1 - t0, t3 - t2))
+    ctx.close()
+    ref = res["fp64"]
+    t = np.array(ref["terms"])
+    scale = np.array([(t[1] + n) / (2 * theta[0]), 0.5 * (abs(t[2]) + abs(t[4])),
+                      0.5 * (abs(t[3]) + abs(t[5]))])
+    fd = np.diag(np.array(ref["fisher"]))
+    for name in ("mixed_fp32", "mixed_fp32_all"):
+        r = res[name]
+        if "loglik" not in r:
+            continue
+        r["loglik_rel_err_vs_fp64"] = abs(r["loglik"] - ref["loglik"]) / abs(ref["loglik"])
+        r["score_err_per_term_vs_fp64"] = (np.abs(np.array(r["score"]) - ref["score"]) / scale).tolist()
+        r["fisher_rel_err_vs_fp64"] = float(np.max(np.abs(np.array(r["fisher"]) - ref["fisher"])
+                                                   / np.sqrt(np.outer(fd, fd))))
+        r["eval_speedup_vs_fp64"] = ref["eval_s"] / r["eval_s"]
+    out = {"metric": "loglik+score+Fisher evals/s at n=%d, FP64 vs mixed" % n,
+           "value": 1.0 / ref["eval_s"], "unit": "evals/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+           "ms_per_step": 1e3 * ref["eval_s"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "n=%d uniform on [0,1]^2, theta=%s; data by %d random Fourier "
+                                  "features of the Matern field" % (n, list(theta), 4096)},
+           "forms": res}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -197,7 +298,17 @@ def main():
     ap.add_argument("--batch-workers", type=int, default=8)
     ap.add_argument("--fit", action="store_true",
                     help="instead of the evaluation rate, time one full Fisher-BT fit (FP64 and mixed)")
+    ap.add_argument("--grid", action="store_true",
+                    help="instead of the evaluation rate, the 3x3 grid of FP64 fits at n=10,000")
+    ap.add_argument("--precision", action="store_true",
+                    help="instead of the evaluation rate, FP64 vs the mixed forms at n=50,000")
     args = ap.parse_args()
+    if args.grid and args.gpus == 1:
+        grid_bench(args)
+        return
+    if args.precision and args.gpus == 1:
+        precision_bench(args)
+        return
     if args.fit and args.gpus == 1:
         fit_bench(args)
         return

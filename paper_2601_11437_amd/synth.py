@@ -68,6 +68,26 @@ def grf(locs: np.ndarray, theta, gen: np.random.Generator) -> np.ndarray:
     return L @ w
 
 
+def rff_field(locs: np.ndarray, theta, gen: np.random.Generator, features: int = 4096) -> np.ndarray:
+    """An approximate realisation of the Matern field by random Fourier
+    features, for sizes where the exact draw (a dense host Cholesky) is out of
+    reach: Z(s) = sqrt(2 sigma2 / M) sum_m cos(w_m . s + b_m) with b_m ~ U(0, 2 pi)
+    and w_m from the Matern spectral density, proportional to
+    (1 / alpha^2 + |w|^2)^-(nu + 1) in two dimensions, i.e. w = g / (alpha sqrt(V))
+    with g ~ N(0, I_2) and V ~ chi^2 with 2 nu degrees of freedom.  Its
+    covariance tends to the Matern one as M grows."""
+    s2, a, nu = (float(t) for t in theta)
+    g = gen.standard_normal((features, 2))
+    v = gen.chisquare(2.0 * nu, features)
+    w = g / (a * np.sqrt(v))[:, None]
+    b = gen.uniform(0.0, 2.0 * np.pi, features)
+    z = np.zeros(locs.shape[0])
+    for r0 in range(0, locs.shape[0], 8192):      # bounded temporaries
+        ph = locs[r0:r0 + 8192] @ w.T + b
+        z[r0:r0 + 8192] = np.cos(ph).sum(axis=1)
+    return np.sqrt(2.0 * s2 / features) * z
+
+
 def dataset(n: int, theta_true, seed: int, design: str = "uniform", max_redraws: int = 20):
     """(locs, z, info) for a uniform or jittered-grid design."""
     for redraw in range(max_redraws + 1):
@@ -105,6 +125,9 @@ WORKLOADS = {
     "n20k": dict(n=20000, theta_true=(1.0, 0.1, 0.5), design="uniform", seed=20000),
     # Differentiation check: 10,000 uniform points, theta = (1, 0.1, 1.5).
     "n10k_diff": dict(n=10000, theta_true=(1.0, 0.1, 1.5), design="uniform", seed=3000),
+    # Precision comparison: 50,000 uniform points, theta = (1, 0.05, 0.8); data by
+    # random Fourier features (rff_field).
+    "n50k": dict(n=50000, theta_true=(1.0, 0.05, 0.8), design="uniform", seed=4000),
 }
 
 
