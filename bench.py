@@ -239,7 +239,7 @@ def precision_bench(args):
     ctx.set_data(locs, z)
     res = {}
     for name, prec in (("fp64", fbt.FP64), ("mixed_fp32", fbt.MIXED_FP32),
-                       ("mixed_fp32_all", fbt.MIXED_FP32_ALL)):
+                       ("mixed_fp32_all", fbt.MIXED_FP32_ALL), ("mixed_bf16", fbt.MIXED_BF16)):
         ctx.set_precision(prec)
         try:
             t0 = time.perf_counter()
@@ -262,7 +262,7 @@ def precision_bench(args):
     scale = np.array([(t[1] + n) / (2 * theta[0]), 0.5 * (abs(t[2]) + abs(t[4])),
                       0.5 * (abs(t[3]) + abs(t[5]))])
     fd = np.diag(np.array(ref["fisher"]))
-    for name in ("mixed_fp32", "mixed_fp32_all"):
+    for name in ("mixed_fp32", "mixed_fp32_all", "mixed_bf16"):
         r = res[name]
         if "loglik" not in r:
             continue

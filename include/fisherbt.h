@@ -56,8 +56,18 @@ typedef enum {
  *   fbt_loglik is unchanged and fbt_eval returns the FP64 log-likelihood.
  * FBT_MIXED_FP32_ALL: the Cholesky trailing updates in FP32 as well.  The
  *   log-likelihood then carries FP32 rounding amplified by the conditioning
- *   of Sigma, and the factorisation can fail for ill-conditioned Sigma. */
-typedef enum { FBT_FP64 = 0, FBT_MIXED_FP32 = 1, FBT_MIXED_FP32_ALL = 2 } fbt_precision;
+ *   of Sigma, and the factorisation can fail for ill-conditioned Sigma.
+ * FBT_MIXED_BF16: as FBT_MIXED_FP32, with the operands of those updates
+ *   rounded to bfloat16 (8-bit significand) and the products summed in FP32
+ *   (v_mfma_f32_16x16x16_bf16).  The log-likelihood is the FP64 one; score and
+ *   Fisher carry bfloat16 rounding of both block solves, amplified by the
+ *   conditioning of Sigma (errors of order 1e-3 relative or worse). */
+typedef enum {
+    FBT_FP64 = 0,
+    FBT_MIXED_FP32 = 1,
+    FBT_MIXED_FP32_ALL = 2,
+    FBT_MIXED_BF16 = 3
+} fbt_precision;
 
 typedef struct {
     int32_t device;    /* HIP device ordinal */

@@ -54,7 +54,7 @@ class Config(ctypes.Structure):
     _fields_ = [("device", _i32), ("tile", _i32), ("precision", _i32), ("hip_stream", _p)]
 
 
-FP64, MIXED_FP32, MIXED_FP32_ALL = 0, 1, 2
+FP64, MIXED_FP32, MIXED_FP32_ALL, MIXED_BF16 = 0, 1, 2, 3
 SIGMA_NU_EXACT, SIGMA_NU_PAPER = 0, 1
 
 
@@ -329,8 +329,9 @@ class Context:
         return out
 
     def set_precision(self, precision: int):
-        """FP64 (0), MIXED_FP32 (1: solve updates in FP32) or MIXED_FP32_ALL
-        (2: Cholesky updates too) for the following evaluations."""
+        """FP64 (0), MIXED_FP32 (1: solve updates in FP32), MIXED_FP32_ALL
+        (2: Cholesky updates too) or MIXED_BF16 (3: solve updates with
+        bfloat16 operands and FP32 sums) for the following evaluations."""
         self._check(lib().fbt_set_precision(self._h, int(precision)))
 
     def set_sigma_nu_mode(self, mode: int):

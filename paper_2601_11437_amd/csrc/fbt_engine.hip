@@ -546,7 +546,8 @@ fbt_status derivative_terms(fbt_ctx *c, const double *th, double terms[9])
     const int T = c->T;
     double *Sa = c->S2, *Sn = c->S2 + npad * ld, *A = c->A;
     const double dn = (double)n, dNB = NB;
-    const int mix = c->precision != FBT_FP64; // solve updates in FP32
+    // solve updates: FP32 (1) or BF16 operands with FP32 sums (2)
+    const int mix = c->precision == FBT_FP64 ? 0 : c->precision == FBT_MIXED_BF16 ? 2 : 1;
     auto Lk = [&](int k) { return c->Linv + (size_t)k * NB * NB; };
 
     // Left solve X = L'^{-1} [Sigma_alpha' | Sigma_nu'] on columns [0, ncols) of
@@ -913,7 +914,7 @@ fbt_status fbt::fit_eval(fbt_ctx *c, const double *th, double mixed_switch, int 
     *state = 1;
     // derivative_terms leaves the factor of th in place; it is the FP64 one
     // unless the Cholesky updates were FP32 as well
-    c->factor_valid = c->precision == FBT_MIXED_FP32;
+    c->factor_valid = c->precision != FBT_MIXED_FP32_ALL;
     std::memcpy(c->factor_theta, th, sizeof(c->factor_theta));
     c->precision = FBT_FP64;
     if ((st = derivative_terms(c, th, t)) != FBT_OK)
@@ -954,7 +955,7 @@ fbt_status fbt_create(const fbt_config *cfg, fbt_ctx **out)
         return FBT_EINVAL;
     *out = nullptr;
     if (!(cfg->tile == 0 || cfg->tile == NB) ||
-        cfg->precision < FBT_FP64 || cfg->precision > FBT_MIXED_FP32_ALL)
+        cfg->precision < FBT_FP64 || cfg->precision > FBT_MIXED_BF16)
         return FBT_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev)
@@ -1164,7 +1165,7 @@ fbt_status fbt_factor(fbt_ctx *ctx, const double theta[3], double *out, int64_t 
 
 fbt_status fbt_set_precision(fbt_ctx *ctx, int32_t precision)
 {
-    if (!ctx || precision < FBT_FP64 || precision > FBT_MIXED_FP32_ALL)
+    if (!ctx || precision < FBT_FP64 || precision > FBT_MIXED_BF16)
         return FBT_EINVAL;
     // the factorisation's arithmetic differs only under FBT_MIXED_FP32_ALL
     if (precision != ctx->precision &&

@@ -884,11 +884,121 @@ template <int WM, int WN, bool BKC> struct TileF {
     }
 };
 
+// BF16 variant of TileF: operands rounded to bfloat16 (round to nearest
+// even, through FP32) when staged into LDS, products summed in FP32 on
+// v_mfma_f32_16x16x16_bf16 over NB-deep slices, each slice subtracted from the
+// FP64 C tile.  LDS rows hold one row of A or B with k contiguous, so a lane
+// reads its four consecutive-k operands with one 8-byte load.
+typedef short s4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short to_bf16(double v)
+{
+    const unsigned int u = __float_as_uint((float)v);
+    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+template <int WM, int WN, bool BKC> struct TileB {
+    static constexpr int BM = 64 * WM, BN = 64 * WN, KC = 16;
+    static constexpr int LK = KC + 4;                 // padded LDS row (bf16 elements)
+    static constexpr int STAGE = (BM + BN) * LK;
+    static constexpr int LDS = 2 * STAGE;             // bf16 elements
+    static constexpr int NA = BM * KC / 512;          // double2 loads per thread
+    static constexpr int NBL = BN * KC / 512;
+
+    __device__ static void store(const double2 *ra, const double2 *rb, unsigned short *st)
+    {
+        const int t = threadIdx.x;
+        unsigned short *As = st, *Bs = st + BM * LK;
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const int q = t + 256 * i, m2 = q % (BM / 2), k = q / (BM / 2);
+            As[(2 * m2) * LK + k] = to_bf16(ra[i].x);
+            As[(2 * m2 + 1) * LK + k] = to_bf16(ra[i].y);
+        }
+#pragma unroll
+        for (int i = 0; i < NBL; ++i) {
+            const int q = t + 256 * i;
+            if (!BKC) {
+                const int n2 = q % (BN / 2), k = q / (BN / 2);
+                Bs[(2 * n2) * LK + k] = to_bf16(rb[i].x);
+                Bs[(2 * n2 + 1) * LK + k] = to_bf16(rb[i].y);
+            } else {
+                const int k2 = q % (KC / 2), nn = q / (KC / 2);
+                Bs[nn * LK + 2 * k2] = to_bf16(rb[i].x);
+                Bs[nn * LK + 2 * k2 + 1] = to_bf16(rb[i].y);
+            }
+        }
+    }
+    __device__ static void compute(f4 (&acc)[4][4], const unsigned short *st, int wm, int wn,
+                                   int lane)
+    {
+        const unsigned short *As = st + (wm * 64 + (lane & 15)) * LK + 4 * (lane >> 4);
+        const unsigned short *Bs = st + BM * LK + (wn * 64 + (lane & 15)) * LK + 4 * (lane >> 4);
+        s4v a[4], b[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            a[i] = *(const s4v *)(As + 16 * i * LK);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            b[j] = *(const s4v *)(Bs + 16 * j * LK);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(b[j], a[i], acc[i][j], 0, 0, 0);
+    }
+    __device__ __forceinline__ static void update(double *C, int64_t ldc, const double *A, int64_t lda,
+                                                  const double *B, int64_t ldb, int K,
+                                                  unsigned short *lds)
+    {
+#pragma unroll 1
+        for (int k0 = 0; k0 < K; k0 += NB)
+            update_slice(C, ldc, A + (int64_t)k0 * lda, lda, BKC ? B + k0 : B + (int64_t)k0 * ldb,
+                         ldb, K - k0 < NB ? K - k0 : NB, lds);
+    }
+    __device__ __forceinline__ static void update_slice(double *C, int64_t ldc, const double *A,
+                                                        int64_t lda, const double *B, int64_t ldb,
+                                                        int K, unsigned short *lds)
+    {
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        const int wm = wave % WM, wn = wave / WM;
+        f4 acc[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
+        double2 ra[NA], rb[NBL];
+        TileF<WM, WN, BKC>::load(ra, rb, A, lda, B, ldb, 0);
+        store(ra, rb, lds);
+        __syncthreads();
+        const int nch = K / KC;
+        for (int c = 0; c < nch; ++c) {
+            if (c + 1 < nch)
+                TileF<WM, WN, BKC>::load(ra, rb, A, lda, B, ldb, (c + 1) * KC);
+            compute(acc, lds + (c & 1) * STAGE, wm, wn, lane);
+            if (c + 1 < nch)
+                store(ra, rb, lds + ((c + 1) & 1) * STAGE);
+            __syncthreads();
+        }
+        double *cb = C + (wm * 64 + (lane & 15)) + (int64_t)(wn * 64 + 4 * (lane >> 4)) * ldc;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                double *cc = cb + (int64_t)(16 * j + r) * ldc;
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    cc[16 * i] = cc[16 * i] - (double)acc[i][j][r];
+            }
+    }
+};
+
 // C -= A * B^T over the block-lower tiles of a trailing matrix of nblk x nblk
 // NB-blocks (128 x 128 tiles; both 128-tiles above the diagonal inside a
 // diagonal NB-block are included), depth K (one or two panels).  blockIdx.y
 // selects (C0, A0) or (C1, A1).
-template <bool MIX, int K = NB>
+template <int MIX, int K = NB>
 __global__ __launch_bounds__(256) void k_update_lower(int nmat, int64_t sC, int64_t sB,
                                                       double *C0, double *C1, int64_t ldc,
                                                       const double *A0, const double *A1,
@@ -896,7 +1006,8 @@ __global__ __launch_bounds__(256) void k_update_lower(int nmat, int64_t sC, int6
 {
     using TL = Tile<2, 2, false, true>;
     using TF = TileF<2, 2, false>;
-    __shared__ double lds[MIX ? (TF::LDS + 1) / 2 : TL::LDS];
+    using TBF = TileB<2, 2, false>;
+    __shared__ double lds[MIX == 2 ? (TBF::LDS + 3) / 4 : MIX ? (TF::LDS + 1) / 2 : TL::LDS];
     const int64_t p = blockIdx.x >> 2;
     const int s = blockIdx.x & 3;
     int64_t I = (int64_t)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
@@ -910,7 +1021,9 @@ __global__ __launch_bounds__(256) void k_update_lower(int nmat, int64_t sC, int6
     double *C = (mat ? C1 : C0) + f * sC + m0 + n0 * ldc;
     const double *A = (mat ? A1 : A0) + f * sC + m0;
     B += f * sB;
-    if constexpr (MIX) {
+    if constexpr (MIX == 2) {
+        TBF::update(C, ldc, A, lda, B + n0, ldb, K, (unsigned short *)lds);
+    } else if constexpr (MIX == 1) {
         TF::update(C, ldc, A, lda, B + n0, ldb, K, (float *)lds);
     } else {
         d4 acc[4][4];
@@ -923,7 +1036,7 @@ __global__ __launch_bounds__(256) void k_update_lower(int nmat, int64_t sC, int6
 // C -= A * B^T on a rectangle of rows x ncol (128 x 128 tiles, depth K): the
 // next block column(s) of a trailing update (lookahead).  blockIdx.z selects
 // the matrix.
-template <bool MIX, int K = NB>
+template <int MIX, int K = NB>
 __global__ __launch_bounds__(256) void k_update_rect(int nmat, int64_t sC, int64_t sB, double *C0,
                                                      double *C1, int64_t ldc, const double *A0,
                                                      const double *A1, int64_t lda,
@@ -931,13 +1044,16 @@ __global__ __launch_bounds__(256) void k_update_rect(int nmat, int64_t sC, int64
 {
     using TL = Tile<2, 2, false, true>;
     using TF = TileF<2, 2, false>;
-    __shared__ double lds[MIX ? (TF::LDS + 1) / 2 : TL::LDS];
+    using TBF = TileB<2, 2, false>;
+    __shared__ double lds[MIX == 2 ? (TBF::LDS + 3) / 4 : MIX ? (TF::LDS + 1) / 2 : TL::LDS];
     const int64_t m0 = 128 * (int64_t)blockIdx.x, n0 = 128 * (int64_t)blockIdx.y;
     const int mat = blockIdx.z % nmat, f = blockIdx.z / nmat; // matrix, field
     double *C = (mat ? C1 : C0) + f * sC + m0 + n0 * ldc;
     const double *A = (mat ? A1 : A0) + f * sC + m0;
     B += f * sB;
-    if constexpr (MIX) {
+    if constexpr (MIX == 2) {
+        TBF::update(C, ldc, A, lda, B + n0, ldb, K, (unsigned short *)lds);
+    } else if constexpr (MIX == 1) {
         TF::update(C, ldc, A, lda, B + n0, ldb, K, (float *)lds);
     } else {
         d4 acc[4][4];
@@ -959,14 +1075,15 @@ void launch_update_rect(hipStream_t s, const Fields &F, int64_t sC, int64_t sB, 
         return;
     const dim3 g((unsigned)(rows / 128), (unsigned)(ncol / 128), (unsigned)(nmat * F.count));
     if (mixed) {
+        auto kern = mixed == 2 ? k_update_rect<2> : k_update_rect<1>;
         for (int p = 0; p < K / NB; ++p) {
             const int64_t o = (int64_t)p * NB;
-            hipLaunchKernelGGL(k_update_rect<true>, g, dim3(256), 0, s, nmat, sC, sB, C0, C1, ldc,
+            hipLaunchKernelGGL(kern, g, dim3(256), 0, s, nmat, sC, sB, C0, C1, ldc,
                                A0 + o * lda, A1 ? A1 + o * lda : nullptr, lda, B + o * ldb, ldb);
         }
         return;
     }
-    auto kern = K == 2 * NB ? k_update_rect<false, 2 * NB> : k_update_rect<false, NB>;
+    auto kern = K == 2 * NB ? k_update_rect<0, 2 * NB> : k_update_rect<0, NB>;
     hipLaunchKernelGGL(kern, g, dim3(256), 0, s, nmat, sC, sB, C0, C1, ldc, A0, A1, lda, B, ldb);
 }
 
@@ -980,15 +1097,16 @@ void launch_update_lower(hipStream_t s, const Fields &F, int64_t sC, int64_t sB,
     const int64_t pairs = (int64_t)nblk * (nblk + 1) / 2;
     const dim3 g((unsigned)(4 * pairs), (unsigned)(nmat * F.count));
     if (mixed) {
+        auto kern = mixed == 2 ? k_update_lower<2> : k_update_lower<1>;
         for (int p = 0; p < K / NB; ++p) {
             const int64_t o = (int64_t)p * NB;
-            hipLaunchKernelGGL(k_update_lower<true>, g, dim3(256), 0, s, nmat, sC, sB, C0, C1,
+            hipLaunchKernelGGL(kern, g, dim3(256), 0, s, nmat, sC, sB, C0, C1,
                                ldc, A0 + o * lda, A1 ? A1 + o * lda : nullptr, lda, B + o * ldb,
                                ldb);
         }
         return;
     }
-    auto kern = K == 2 * NB ? k_update_lower<false, 2 * NB> : k_update_lower<false, NB>;
+    auto kern = K == 2 * NB ? k_update_lower<0, 2 * NB> : k_update_lower<0, NB>;
     hipLaunchKernelGGL(kern, g, dim3(256), 0, s, nmat, sC, sB, C0, C1, ldc, A0, A1, lda, B, ldb);
 }
 
@@ -1067,7 +1185,7 @@ void launch_diag_apply(hipStream_t s, const Fields &F, int64_t sS, int nmat, dou
 // Left solve, update below the diagonal block(s):
 // S[r0 + 128 y, cols] -= L[r0 + 128 y, krow:krow+K] * S[krow:krow+K, cols]
 // (K = NB for one panel, 2 NB for two consecutive panels at once).
-template <bool MIX, int K = NB>
+template <int MIX, int K = NB>
 __global__ __launch_bounds__(256) void k_update_nn(Fields F, int64_t sS, double *S, int64_t ld,
                                                    const double *L, int64_t lda, int64_t r0,
                                                    int64_t krow, int64_t half_tiles,
@@ -1075,7 +1193,8 @@ __global__ __launch_bounds__(256) void k_update_nn(Fields F, int64_t sS, double 
 {
     using TL = Tile<2, 2, true, true>;
     using TF = TileF<2, 2, true>;
-    __shared__ double lds[MIX ? (TF::LDS + 1) / 2 : TL::LDS];
+    using TBF = TileB<2, 2, true>;
+    __shared__ double lds[MIX == 2 ? (TBF::LDS + 3) / 4 : MIX ? (TF::LDS + 1) / 2 : TL::LDS];
     const int f = blockIdx.z; // field
     S += f * sS;
     L += f * F.sA;
@@ -1083,7 +1202,10 @@ __global__ __launch_bounds__(256) void k_update_nn(Fields F, int64_t sS, double 
     const int64_t c0 = (ct < half_tiles) ? 128 * ct : col_shift + 128 * (ct - half_tiles);
     const int64_t m0 = r0 + 128 * (int64_t)blockIdx.y;
     double *C = S + m0 + c0 * ld;
-    if constexpr (MIX) {
+    if constexpr (MIX == 2) {
+        TBF::update(C, ld, L + m0 + krow * lda, lda, S + krow + c0 * ld, ld, K,
+                    (unsigned short *)lds);
+    } else if constexpr (MIX == 1) {
         TF::update(C, ld, L + m0 + krow * lda, lda, S + krow + c0 * ld, ld, K, (float *)lds);
     } else {
         d4 acc[4][4];
@@ -1105,12 +1227,13 @@ void launch_update_nn(hipStream_t s, const Fields &F, int64_t sS, int nmat, doub
     // loop as fast as the fixed-depth form).  The FP32 form applies two panels
     // as two NB-deep launches: its NB-deep kernel keeps four workgroups per CU.
     if (mixed) {
+        auto kern = mixed == 2 ? k_update_nn<2> : k_update_nn<1>;
         for (int p = 0; p < K / NB; ++p)
-            hipLaunchKernelGGL(k_update_nn<true>, g, dim3(256), 0, s, F, sS, S, ld, L, lda, r0,
+            hipLaunchKernelGGL(kern, g, dim3(256), 0, s, F, sS, S, ld, L, lda, r0,
                                krow + p * NB, half, col_shift);
         return;
     }
-    auto kern = K == 2 * NB ? k_update_nn<false, 2 * NB> : k_update_nn<false, NB>;
+    auto kern = K == 2 * NB ? k_update_nn<0, 2 * NB> : k_update_nn<0, NB>;
     hipLaunchKernelGGL(kern, g, dim3(256), 0, s, F, sS, S, ld, L, lda, r0, krow, half, col_shift);
 }
 

@@ -241,6 +241,33 @@ def test_mixed_precision(ctx, oracle_mod, n, theta):
     assert np.array_equal(score[:1], s64[:1])          # sigma2 score: FP64 quadratic form
 
 
+@pytest.mark.parametrize("n,theta", [(600, (1.0, 0.1, 0.5)), (1500, (1.5, 0.07, 1.0))])
+def test_mixed_bf16(ctx, n, theta):
+    """BF16 operands with FP32 sums in the trace-phase updates: the
+    log-likelihood is the FP64 one bit for bit, the sigma2 score too; the other
+    score terms and the Fisher entries carry bfloat16 rounding (eps = 2^-8) of
+    both block solves: measured 1e-4 .. 1.3e-2 of the per-term scale and
+    4e-4 .. 1.4e-2 relative on these cases; the gates are 5e-2."""
+    say("bf16 n=%d theta=%s" % (n, theta))
+    locs, z, _ = synth.dataset(n, (1.0, 0.1, 0.5), 3000 + n)
+    ctx.set_data(locs, z)
+    t = ctx.eval_terms(theta)
+    ll64, s64, f64 = ctx.eval(theta)
+    ctx.set_precision(fbt.MIXED_BF16)
+    try:
+        ll, score, fisher = ctx.eval(theta)
+    finally:
+        ctx.set_precision(fbt.FP64)
+    assert ll == ll64 and score[0] == s64[0]
+    scale = np.array([(t[1] + n) / (2 * theta[0]), 0.5 * (abs(t[2]) + abs(t[4])),
+                      0.5 * (abs(t[3]) + abs(t[5]))])
+    err = np.abs(score - s64) / scale
+    d = np.sqrt(np.outer(np.diag(f64), np.diag(f64)))
+    say("score err / scale", err, "fisher rel", np.max(np.abs(fisher - f64) / d))
+    assert np.all(err <= 5e-2) and np.all(np.abs(fisher - f64) <= 5e-2 * d)
+    assert np.any(err[1:] > 0)                        # the BF16 path really ran
+
+
 def test_mixed_fit_switches_to_fp64(ctx):
     """Fisher-BT on a context in the mixed form: Fisher steps from mixed
     derivatives while the score is large, FP64 from the switch point on, so
