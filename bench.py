@@ -115,12 +115,32 @@ def batch_bench(args):
             break
         redraws += int(bad.sum())
         thetas = synth.batch_redraw_thetas(thetas, bad, gen)
-    for _ in range(args.warmup):
-        b.eval(thetas, fbt.Batch.EVAL)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ll, sc, fi, st = b.eval(thetas, fbt.Batch.EVAL)
-    dt = time.perf_counter() - t0
+    def timed():
+        for _ in range(args.warmup):
+            b.eval(thetas, fbt.Batch.EVAL)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            r = b.eval(thetas, fbt.Batch.EVAL)
+        return time.perf_counter() - t0, r
+
+    # the worker execution without group limits, for comparison
+    dt_workers, _ = timed()
+    log("workers, no limits: %.1f ms per round" % (1e3 * dt_workers / args.steps))
+    tune = None
+    if args.batch_exec == "graph":
+        b.set_exec(fbt.Batch.GRAPH)
+    elif args.batch_exec == "tuned":
+        t0 = time.perf_counter()
+        path = os.path.join(ROOT, "gpurun_out", "batch_tuning.json")
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        b.autotune(thetas, fbt.Batch.EVAL, path)
+        with open(path) as f:
+            tune = json.load(f)
+        tune["tuning_seconds"] = time.perf_counter() - t0
+        log("autotune: %.1f s, exec %s, limits %s" % (tune["tuning_seconds"],
+                                                      ("workers", "graph")[tune["exec"]],
+                                                      tune["limits"]))
+    dt, (ll, sc, fi, st) = timed()
     b.close()
     ns = np.array([z.size for _, z in fields], dtype=np.float64)
     exec_flops = float(np.sum(3.0 * ns ** 3)) * args.steps
@@ -132,7 +152,10 @@ def batch_bench(args):
            "config": {"workload": "%d independent Matern fields, n_f ~ U[500, 4000] uniform points, "
                                   "theta_f uniform in [0.5,2]x[0.02,0.3]x[0.3,2.5], one full "
                                   "evaluation per field per step" % nf,
-                      "workers": args.batch_workers, "theta_redraws": redraws},
+                      "workers": args.batch_workers, "theta_redraws": redraws,
+                      "exec": args.batch_exec},
+           "tuning": tune,
+           "ms_per_step_workers_untuned": 1e3 * dt_workers / args.steps,
            "executed_tflops": exec_flops / dt / 1e12,
            "fp64_frac": exec_flops / dt / 1e12 / PEAK_FP64_TFLOPS,
            "failed_fields": int(np.sum(st != fbt.OK))}
@@ -296,6 +319,9 @@ def main():
     ap.add_argument("--batch", type=int, default=0,
                     help="instead of the n=20k evaluation, time one round over this many fields")
     ap.add_argument("--batch-workers", type=int, default=8)
+    ap.add_argument("--batch-exec", choices=("workers", "graph", "tuned"), default="tuned",
+                    help="batch execution: worker threads, one HIP graph per round, or the "
+                         "autotuner's choice of execution and group limits")
     ap.add_argument("--fit", action="store_true",
                     help="instead of the evaluation rate, time one full Fisher-BT fit (FP64 and mixed)")
     ap.add_argument("--grid", action="store_true",

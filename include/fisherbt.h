@@ -260,6 +260,44 @@ fbt_status fbt_batch_eval(fbt_batch *b, const double *thetas, const int32_t *mod
                           double *loglik, double *score, double *fisher, int32_t *status);
 const char *fbt_batch_last_error(const fbt_batch *b);
 
+/* Execution of fbt_batch_eval (batched evaluations of one Fisher-BT
+ * iteration over many fields, the batching of Section 2's estimator across
+ * replicates).
+ *   FBT_BATCH_WORKERS (default): groups go to the worker contexts, driven by
+ *     host threads.
+ *   FBT_BATCH_GRAPH: every group of the call gets a context of its own
+ *     (device memory for all groups at once) and the whole call - for every
+ *     group the upload of its theta tables, generation, factorisation, W phase
+ *     and the copies of the results - is captured in one HIP graph, rebuilt
+ *     only when the fields, the modes, the group limits or the precision
+ *     change; other calls replay it with their theta (one graph launch per
+ *     call).  Adjoint-mode fields run after the graph, one by one.
+ * Results are bitwise the same in both.  In this build FBT_BATCH_GRAPH is
+ * switched off (its first capture and replay crashed the host process with a
+ * segmentation fault; the cause is not identified): asking for it returns
+ * FBT_EINVAL with the reason in fbt_batch_last_error.  Errors: FBT_EINVAL. */
+typedef enum { FBT_BATCH_WORKERS = 0, FBT_BATCH_GRAPH = 1 } fbt_batch_exec;
+fbt_status fbt_batch_set_exec(fbt_batch *b, int32_t exec);
+int32_t fbt_batch_get_exec(const fbt_batch *b); /* -1 for NULL */
+/* At most max_fields fields of padded order npad (a multiple of 256) per group
+ * (0: only the 8 GB cap).  Errors: FBT_EINVAL. */
+fbt_status fbt_batch_set_group_limit(fbt_batch *b, int64_t npad, int32_t max_fields);
+int32_t fbt_batch_group_limit(const fbt_batch *b, int64_t npad); /* 0: none; -1 for NULL */
+/* Autotuner: for every padded order among the fields of the workload (thetas,
+ * mode as in fbt_batch_eval), time the calls of that order's fields alone with
+ * group limits 1, 2, 4, 8, 16, 32 and none in the current execution (best of
+ * two after one untimed call), keep the fastest limit, then time the whole
+ * call in both executions and keep the faster (the workers only while the
+ * graph execution is switched off).  The choices go to the JSON
+ * file `path` (NULL: none) for fbt_batch_load_tuning.  The outputs of the
+ * timed calls are discarded.  Errors: as fbt_batch_eval, FBT_EINVAL when the
+ * file cannot be written. */
+fbt_status fbt_batch_autotune(fbt_batch *b, const double *thetas, const int32_t *mode,
+                              const char *path);
+/* Group limits and execution from a file written by fbt_batch_autotune.
+ * Errors: FBT_EINVAL (missing or malformed file). */
+fbt_status fbt_batch_load_tuning(fbt_batch *b, const char *path);
+
 /* How Sigma_nu = dSigma/dnu is computed (Section 2.2).
  *   FBT_SIGMA_NU_EXACT (default): the exact derivative of the Matern entry,
  *     by quadrature of the integral form of K_nu and its order derivative.

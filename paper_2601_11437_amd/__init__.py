@@ -89,6 +89,12 @@ SIGNATURES = {
     "fbt_batch_set_fields": (ctypes.c_int, [_p, _i32, _p, _p, _p]),
     "fbt_batch_eval": (ctypes.c_int, [_p, _p, _p, _p, _p, _p, _p]),
     "fbt_batch_last_error": (ctypes.c_char_p, [_p]),
+    "fbt_batch_set_exec": (ctypes.c_int, [_p, _i32]),
+    "fbt_batch_get_exec": (_i32, [_p]),
+    "fbt_batch_set_group_limit": (ctypes.c_int, [_p, _i64, _i32]),
+    "fbt_batch_group_limit": (_i32, [_p, _i64]),
+    "fbt_batch_autotune": (ctypes.c_int, [_p, _p, _p, ctypes.c_char_p]),
+    "fbt_batch_load_tuning": (ctypes.c_int, [_p, ctypes.c_char_p]),
     "fbt_set_timing": (ctypes.c_int, [_p, _i32]),
     "fbt_get_timing": (ctypes.c_int, [_p, _i32, ctypes.POINTER(_i64), _dp, _dp]),
 }
@@ -354,9 +360,12 @@ class Context:
 
 class Batch:
     """Many independent fields evaluated together (fbt_batch_*): a pool of
-    `workers` device contexts fed by host threads, longest field first."""
+    `workers` device contexts fed by host threads, longest field first, or one
+    HIP graph per call (exec GRAPH); group sizes per padded order from
+    set_group_limit or the autotuner."""
 
     SKIP, LOGLIK, EVAL, GRAD = 0, 1, 2, 3
+    WORKERS, GRAPH = 0, 1
 
     def __init__(self, workers: int = 8, device: int = 0, precision: int = FP64):
         cfg = Config(int(device), 0, int(precision), None)
@@ -403,3 +412,38 @@ class Batch:
         if st != OK:
             raise FisherBTError(st, lib().fbt_batch_last_error(self._h).decode())
         return ll, sc, fi.reshape(self.nf, 3, 3), status
+
+    def set_exec(self, exec_: int):
+        """WORKERS (0) or GRAPH (1) for the following calls."""
+        st = lib().fbt_batch_set_exec(self._h, int(exec_))
+        if st != OK:
+            raise FisherBTError(st, "fbt_batch_set_exec: " +
+                                lib().fbt_batch_last_error(self._h).decode())
+
+    @property
+    def exec(self) -> int:
+        return int(lib().fbt_batch_get_exec(self._h))
+
+    def set_group_limit(self, npad: int, max_fields: int):
+        st = lib().fbt_batch_set_group_limit(self._h, int(npad), int(max_fields))
+        if st != OK:
+            raise FisherBTError(st, "fbt_batch_set_group_limit")
+
+    def group_limit(self, npad: int) -> int:
+        return int(lib().fbt_batch_group_limit(self._h, int(npad)))
+
+    def autotune(self, thetas, mode, path=None):
+        """Time the candidate group limits per padded order and both
+        executions on this workload; keep the fastest (written to `path` as
+        JSON when given)."""
+        th = np.ascontiguousarray(thetas, dtype=np.float64).reshape(self.nf, 3)
+        md = np.ascontiguousarray(np.broadcast_to(np.asarray(mode, dtype=np.int32), (self.nf,)))
+        st = lib().fbt_batch_autotune(self._h, th.ctypes.data, md.ctypes.data,
+                                      None if path is None else str(path).encode())
+        if st != OK:
+            raise FisherBTError(st, lib().fbt_batch_last_error(self._h).decode())
+
+    def load_tuning(self, path):
+        st = lib().fbt_batch_load_tuning(self._h, str(path).encode())
+        if st != OK:
+            raise FisherBTError(st, "fbt_batch_load_tuning(%s)" % path)

@@ -59,8 +59,13 @@ struct fbt_ctx {
     int *h_info = nullptr;
     size_t cap[24] = {0};  // allocated bytes per buffer (buffers only grow)
 
-    // fields held: 1 for the single-field API; G > 1 inside a batched group
+    // fields held: 1 for the single-field API; G >= 1 inside a batched group
     int G = 1;
+    bool batched = false;          // per-field n and theta from device arrays, per-field status
+    // work may be captured in a HIP graph: only non-blocking streams (the
+    // CU-masked stream3 is a blocking stream and synchronises with the
+    // legacy default stream, which a capture does not allow)
+    bool capturable = false;
     Fields F{};
     int64_t *d_nf = nullptr;       // per-field n (device)
     GenParams *d_gpa = nullptr;    // per-field generation parameters (device)
@@ -326,7 +331,7 @@ void free_buffers(fbt_ctx *c)
 
 // Buffers for G fields of up to nmax observations each (same padded order);
 // a buffer is reallocated only when it must grow.
-fbt_status alloc_fields(fbt_ctx *c, int64_t nmax, int G)
+fbt_status alloc_fields(fbt_ctx *c, int64_t nmax, int G, bool batched)
 {
     const int64_t npad = NB * ((nmax + 1 + NB - 1) / NB);
     const int T = (int)(npad / NB);
@@ -387,7 +392,8 @@ fbt_status alloc_fields(fbt_ctx *c, int64_t nmax, int G)
     c->F.sVec = npad;
     c->F.sPart = (int64_t)part;
     c->F.sLog = T;
-    c->F.n = G > 1 ? c->d_nf : nullptr;
+    c->batched = batched;
+    c->F.n = batched ? c->d_nf : nullptr;
     c->fst.assign(G, FBT_OK);
     c->fout.assign(2 * g, 0.0);
     return FBT_OK;
@@ -396,22 +402,34 @@ fbt_status alloc_fields(fbt_ctx *c, int64_t nmax, int G)
 fbt_status alloc_for(fbt_ctx *c, int64_t n)
 {
     c->nf.assign(1, n);
-    return alloc_fields(c, n, 1);
+    return alloc_fields(c, n, 1, false);
 }
 
-// Quadrature tables for the G fields' theta (th: G x 3), uploaded at once;
-// *gp receives field 0's parameters (the by-value launch argument).
-fbt_status upload_theta(fbt_ctx *c, const double *th, GenParams *gp)
+// Quadrature tables for the G fields' theta (th: G x 3) into the pinned
+// staging buffers; *gp receives field 0's parameters (the by-value launch
+// argument of a single field).
+void stage_theta(fbt_ctx *c, const double *th, GenParams *gp)
 {
     for (int f = 0; f < c->G; ++f)
-        c->h_gpa[f] = setup_theta(c, th + 3 * f, f, c->G > 1 ? c->nf[f] : c->n);
+        c->h_gpa[f] = setup_theta(c, th + 3 * f, f, c->batched ? c->nf[f] : c->n);
     *gp = c->h_gpa[0];
+}
+
+// Staged tables to the device (ordered on the context's stream).
+fbt_status upload_staged_theta(fbt_ctx *c)
+{
     HIPCHK(c, hipMemcpyAsync(c->tab, c->h_tab, (size_t)c->G * TAB_BYTES, hipMemcpyHostToDevice,
                              c->stream));
-    if (c->G > 1)
+    if (c->batched)
         HIPCHK(c, hipMemcpyAsync(c->d_gpa, c->h_gpa, (size_t)c->G * sizeof(GenParams),
                                  hipMemcpyHostToDevice, c->stream));
     return FBT_OK;
+}
+
+fbt_status upload_theta(fbt_ctx *c, const double *th, GenParams *gp)
+{
+    stage_theta(c, th, gp);
+    return upload_staged_theta(c);
 }
 
 // Generate Sigma' (and/or the derivative matrices) and factor the bordered
@@ -422,16 +440,14 @@ fbt_status upload_theta(fbt_ctx *c, const double *th, GenParams *gp)
 // diagonal block k+1 and solve panel k+1.  On s1: the rest of the trailing
 // update with panel k (block columns >= k+2).  Block column k+1 is written
 // by s0 only after the previous bulk update (which also wrote it) is done.
-fbt_status factorize(fbt_ctx *c, const double *th, int mode)
+// Launches of the factorisation (tables already on the device), ending with
+// the copies of the results to the pinned host buffers; no host wait.
+fbt_status factorize_enqueue(fbt_ctx *c, const GenParams &gp, int mode)
 {
-    GenParams gp;
-    fbt_status st = upload_theta(c, th, &gp);
-    if (st != FBT_OK)
-        return st;
     c->factor_valid = false;
     const int64_t npad = c->npad, ld = c->ld, n = c->n;
     const int T = c->T;
-    hipStream_t s0 = c->stream, s1 = c->stream3;
+    hipStream_t s0 = c->stream, s1 = c->capturable ? c->stream2 : c->stream3;
     double *A = c->A;
     const double dNB = NB;
     const int mix = c->precision == FBT_MIXED_FP32_ALL; // Cholesky updates in FP32
@@ -489,9 +505,13 @@ fbt_status factorize(fbt_ctx *c, const double *th, int mode)
                              hipMemcpyDeviceToHost, s0));
     HIPCHK(c, hipMemcpyAsync(c->h_info, c->info, (size_t)c->G * sizeof(int), hipMemcpyDeviceToHost,
                              s0));
-    HIPCHK(c, hipStreamSynchronize(s0));
-    tcollect(c);
-    // per-field status and results (also for one field: batched groups read them)
+    return FBT_OK;
+}
+
+// Per-field status and {log det, q} from the pinned buffers, once the
+// enqueued factorisation has completed.
+void factor_results(fbt_ctx *c)
+{
     for (int f = 0; f < c->G; ++f) {
         const double ld_ = c->h_out[16 * f], q = c->h_out[16 * f + 1];
         c->fout[2 * f] = ld_;
@@ -500,7 +520,20 @@ fbt_status factorize(fbt_ctx *c, const double *th, int mode)
                     : (!std::isfinite(ld_) || !std::isfinite(q)) ? FBT_ENONFINITE
                                                                  : FBT_OK;
     }
-    if (c->G > 1)
+}
+
+fbt_status factorize(fbt_ctx *c, const double *th, int mode)
+{
+    GenParams gp;
+    fbt_status st = upload_theta(c, th, &gp);
+    if (st != FBT_OK)
+        return st;
+    if ((st = factorize_enqueue(c, gp, mode)) != FBT_OK)
+        return st;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    tcollect(c);
+    factor_results(c);
+    if (c->batched)
         return FBT_OK;
     if (c->h_info[0] != 0x7fffffff) {
         c->notpd = c->h_info[0];
@@ -524,6 +557,9 @@ bool same_theta(const fbt_ctx *c, const double *th)
     return c->factor_valid && std::memcmp(c->factor_theta, th, sizeof(c->factor_theta)) == 0;
 }
 
+fbt_status wphase_enqueue(fbt_ctx *c);
+fbt_status wphase_results(fbt_ctx *c, double *terms);
+
 // W phase of Algorithm 3 on a valid factor: out[0..8] (see fbt_eval_terms).
 // Both block solves use the same two-stream lookahead as the factorisation:
 // s0 finishes block row / column k+1 and applies its diagonal inverse while
@@ -531,7 +567,7 @@ bool same_theta(const fbt_ctx *c, const double *th)
 fbt_status derivative_terms(fbt_ctx *c, const double *th, double terms[9])
 {
     fbt_status st;
-    hipStream_t s0 = c->stream, s1 = c->stream2;
+    hipStream_t s0 = c->stream;
     if (same_theta(c, th)) {
         GenParams gp;
         if ((st = upload_theta(c, th, &gp)) != FBT_OK)
@@ -542,6 +578,19 @@ fbt_status derivative_terms(fbt_ctx *c, const double *th, double terms[9])
         return st;
     }
     c->factor_valid = false; // reuse is for one derivative evaluation only
+    if ((st = wphase_enqueue(c)) != FBT_OK)
+        return st;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    tcollect(c);
+    return wphase_results(c, terms);
+}
+
+// Launches of the W phase on a factor in place (derivative matrices already
+// generated), ending with the copy of the nine terms per field to the pinned
+// host buffer; no host wait.
+fbt_status wphase_enqueue(fbt_ctx *c)
+{
+    hipStream_t s0 = c->stream, s1 = c->stream2;
     const int64_t npad = c->npad, ld = c->ld, n = c->n, ncols = c->ncols;
     const int T = c->T;
     double *Sa = c->S2, *Sn = c->S2 + npad * ld, *A = c->A;
@@ -642,9 +691,14 @@ fbt_status derivative_terms(fbt_ctx *c, const double *th, double terms[9])
     TIMED(c, s0, KC_RED, 0.0, launch_reduce_terms(s0, c->F, c->partials, groups, c->out));
     HIPCHK(c, hipMemcpyAsync(c->h_out, c->out, (size_t)c->G * 16 * sizeof(double),
                              hipMemcpyDeviceToHost, s0));
-    HIPCHK(c, hipStreamSynchronize(s0));
-    tcollect(c);
-    if (c->G > 1) { // a batched group: terms[9 f + i] per field
+    return FBT_OK;
+}
+
+// The nine terms (per field: terms[9 f + i] in a batched group) from the
+// pinned buffer, once the enqueued W phase has completed.
+fbt_status wphase_results(fbt_ctx *c, double *terms)
+{
+    if (c->batched) {
         for (int f = 0; f < c->G; ++f) {
             terms[9 * f] = c->fout[2 * f];
             terms[9 * f + 1] = c->fout[2 * f + 1];
@@ -819,15 +873,16 @@ fbt_status set_data_common(fbt_ctx *c, int64_t n, const double *locs, const doub
 // Batched group: G fields of the same padded order evaluated together, every
 // launch covering all of them (field f's buffers at f times the strides).
 // mode 1: log-likelihood (Algorithm 2); mode 2: log-likelihood, score and
-// Fisher (Algorithm 3).  Per-field status in status[f]; a field's outputs are
-// written only when its status is FBT_OK.  The arithmetic of each field is
-// exactly that of a single-field evaluation.
-fbt_status fbt::group_run(fbt_ctx *c, int G, const int64_t *n, const double *const *locs,
-                          const double *const *z, const double *thetas, int mode, double *loglik,
-                          double *score, double *fisher, int32_t *status)
+// Fisher (Algorithm 3).  Per-field status; a field's outputs are written only
+// when its status is FBT_OK.  The arithmetic of each field is exactly that of
+// a single-field evaluation.  The steps are separate so that a caller can
+// capture group_enqueue in a HIP graph and replay it with new theta.
+
+// Buffers (batched layout) and data of the G fields.
+fbt_status fbt::group_prepare(fbt_ctx *c, int G, const int64_t *n, const double *const *locs,
+                              const double *const *z)
 {
-    if (!c || G < 1 || !n || !locs || !z || !thetas || !loglik || !status ||
-        (mode == 2 && (!score || !fisher)) || (mode != 1 && mode != 2))
+    if (!c || G < 1 || !n || !locs || !z)
         return FBT_EINVAL;
     c->err.clear();
     if (hipSetDevice(c->device) != hipSuccess)
@@ -839,51 +894,101 @@ fbt_status fbt::group_run(fbt_ctx *c, int G, const int64_t *n, const double *con
     for (int f = 0; f < G; ++f)
         if (n[f] < 1 || NB * ((n[f] + 1 + NB - 1) / NB) != npad)
             return fail(c, FBT_EINVAL, "group fields must share the padded order");
-    fbt_status st = alloc_fields(c, nmax, G);
+    fbt_status st = alloc_fields(c, nmax, G, true);
     if (st != FBT_OK)
         return st;
     c->nf.assign(n, n + G);
-    // data, padded per field; invalid theta is replaced by a harmless one and reported
     std::vector<double> xs((size_t)G * npad, 0.0), ys((size_t)G * npad, 0.0), zs((size_t)G * npad, 0.0);
-    std::vector<double> th(thetas, thetas + 3 * (size_t)G);
-    std::vector<int> bad(G, 0);
-    for (int f = 0; f < G; ++f) {
+    for (int f = 0; f < G; ++f)
         for (int64_t i = 0; i < n[f]; ++i) {
             xs[(size_t)f * npad + i] = locs[f][2 * i];
             ys[(size_t)f * npad + i] = locs[f][2 * i + 1];
             zs[(size_t)f * npad + i] = z[f][i];
         }
-        if (!theta_ok(&th[3 * f])) {
-            bad[f] = 1;
-            th[3 * f] = 1.0;
-            th[3 * f + 1] = 0.1;
-            th[3 * f + 2] = 0.5;
-        }
-    }
     HIPCHK(c, hipMemcpyAsync(c->x, xs.data(), xs.size() * 8, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->y, ys.data(), ys.size() * 8, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->z, zs.data(), zs.size() * 8, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->d_nf, n, (size_t)G * 8, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    std::vector<double> terms((size_t)G * 9);
-    if (mode == 1)
-        st = factorize(c, th.data(), GEN_SIGMA);
-    else
-        st = derivative_terms(c, th.data(), terms.data());
+    return FBT_OK;
+}
+
+// Tables of the G fields' theta (G x 3) into the pinned staging buffers; an
+// invalid theta is replaced by a harmless one and flagged in bad[f].
+void fbt::group_stage(fbt_ctx *c, const double *thetas, int *bad)
+{
+    std::vector<double> th(thetas, thetas + 3 * (size_t)c->G);
+    for (int f = 0; f < c->G; ++f) {
+        bad[f] = !theta_ok(&th[3 * f]);
+        if (bad[f]) {
+            th[3 * f] = 1.0;
+            th[3 * f + 1] = 0.1;
+            th[3 * f + 2] = 0.5;
+        }
+    }
+    GenParams gp;
+    stage_theta(c, th.data(), &gp);
+}
+
+// One evaluation of the group from the staged tables: upload, generation,
+// factorisation and (mode 2) the W phase, ending with the result copies to
+// pinned host memory.  No host wait, no allocation, no memset: capturable.
+fbt_status fbt::group_enqueue(fbt_ctx *c, int mode)
+{
+    if (!c || !c->batched || (mode != 1 && mode != 2))
+        return FBT_EINVAL;
+    fbt_status st = upload_staged_theta(c);
     if (st != FBT_OK)
         return st;
-    for (int f = 0; f < G; ++f) {
+    if ((st = factorize_enqueue(c, c->h_gpa[0], mode == 1 ? GEN_SIGMA : GEN_ALL)) != FBT_OK)
+        return st;
+    return mode == 2 ? wphase_enqueue(c) : FBT_OK;
+}
+
+// Per-field outputs once the enqueued evaluation has completed.
+fbt_status fbt::group_results(fbt_ctx *c, int mode, const double *thetas, const int *bad,
+                              double *loglik, double *score, double *fisher, int32_t *status)
+{
+    factor_results(c);
+    std::vector<double> terms((size_t)c->G * 9);
+    if (mode == 2)
+        wphase_results(c, terms.data());
+    for (int f = 0; f < c->G; ++f) {
         status[f] = bad[f] ? FBT_EINVAL : c->fst[f];
         if (status[f] != FBT_OK)
             continue;
         if (mode == 1)
-            loglik[f] = loglik_from(n[f], c->fout[2 * f], c->fout[2 * f + 1]);
+            loglik[f] = loglik_from(c->nf[f], c->fout[2 * f], c->fout[2 * f + 1]);
         else
-            assemble(n[f], &th[3 * f], &terms[9 * f], loglik + f, score + 3 * f, fisher + 9 * f);
+            assemble(c->nf[f], thetas + 3 * f, &terms[9 * f], loglik + f, score + 3 * f,
+                     fisher + 9 * f);
     }
     c->factor_valid = false;
     return FBT_OK;
 }
+
+fbt_status fbt::group_run(fbt_ctx *c, int G, const int64_t *n, const double *const *locs,
+                          const double *const *z, const double *thetas, int mode, double *loglik,
+                          double *score, double *fisher, int32_t *status)
+{
+    if (!c || G < 1 || !n || !locs || !z || !thetas || !loglik || !status ||
+        (mode == 2 && (!score || !fisher)) || (mode != 1 && mode != 2))
+        return FBT_EINVAL;
+    fbt_status st = group_prepare(c, G, n, locs, z);
+    if (st != FBT_OK)
+        return st;
+    std::vector<int> bad(G);
+    group_stage(c, thetas, bad.data());
+    if ((st = group_enqueue(c, mode)) != FBT_OK)
+        return st;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    tcollect(c);
+    return group_results(c, mode, thetas, bad.data(), loglik, score, fisher, status);
+}
+
+hipStream_t fbt::ctx_stream(fbt_ctx *c) { return c->stream; }
+
+void fbt::ctx_set_capturable(fbt_ctx *c, bool on) { c->capturable = on; }
 
 // Derivative evaluation of the Fisher-BT driver (fbt_fit).  Under a mixed
 // precision the trace terms carry FP32 rounding of the block solves, which

@@ -117,10 +117,20 @@ void launch_adjoint(hipStream_t s, const GenParams &gp, const double *xs, const 
 void launch_reduce_pairs(hipStream_t s, const double *part, int64_t count, double *out);
 
 // Batched group of fields of one padded order (fbt_engine.hip), used by the
-// batch executor; see the definition for the contract.
+// batch executor; see the definitions for the contract.  group_run is
+// prepare + stage + enqueue + wait + results; a graph captures group_enqueue.
 fbt_status group_run(fbt_ctx *c, int G, const int64_t *n, const double *const *locs,
                      const double *const *z, const double *thetas, int mode, double *loglik,
                      double *score, double *fisher, int32_t *status);
+fbt_status group_prepare(fbt_ctx *c, int G, const int64_t *n, const double *const *locs,
+                         const double *const *z);
+void group_stage(fbt_ctx *c, const double *thetas, int *bad);
+fbt_status group_enqueue(fbt_ctx *c, int mode);
+fbt_status group_results(fbt_ctx *c, int mode, const double *thetas, const int *bad,
+                         double *loglik, double *score, double *fisher, int32_t *status);
+hipStream_t ctx_stream(fbt_ctx *c);
+// Restrict the context to streams a HIP graph capture accepts (no CU-masked stream).
+void ctx_set_capturable(fbt_ctx *c, bool on);
 
 // Derivative evaluation of the Fisher-BT driver with the switch from a mixed
 // precision to FP64 near the optimum (fbt_fit_options.mixed_switch);

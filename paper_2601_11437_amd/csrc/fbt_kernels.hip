@@ -233,7 +233,7 @@ void launch_gen(hipStream_t s, const GenParams &gp, const GenParams *gpa, const 
     const int64_t nt = gp.npad / GT;
     const int64_t pairs = nt * (nt + 1) / 2;
     hipLaunchKernelGGL(k_gen, dim3((unsigned)pairs, F.count), dim3(256), 0, s, gp,
-                       F.count > 1 ? gpa : nullptr, F, xs, ys, z, S, Sa, Sn, mode);
+                       F.n ? gpa : nullptr, F, xs, ys, z, S, Sa, Sn, mode);
 }
 
 // ---------------------------------------------------------------------------

@@ -60,6 +60,12 @@ def test_null_arguments_are_rejected():
     assert L.fbt_batch_create(ctypes.byref(cfg), 0, ctypes.byref(ctypes.c_void_p())) == fbt.EINVAL
     assert L.fbt_batch_set_fields(None, 0, None, None, None) == fbt.EINVAL
     assert L.fbt_batch_eval(None, None, None, None, None, None, None) == fbt.EINVAL
+    assert L.fbt_batch_set_exec(None, 0) == fbt.EINVAL
+    assert L.fbt_batch_get_exec(None) == -1
+    assert L.fbt_batch_set_group_limit(None, 256, 1) == fbt.EINVAL
+    assert L.fbt_batch_group_limit(None, 256) == -1
+    assert L.fbt_batch_autotune(None, None, None, None) == fbt.EINVAL
+    assert L.fbt_batch_load_tuning(None, b"x.json") == fbt.EINVAL
     L.fbt_batch_destroy(None)                # NULL-safe
 
 

@@ -5,6 +5,7 @@ FBT_ENOTPD in its status slot without disturbing the others; skipped fields
 are untouched.  Field sizes are drawn so that several fall in different
 padded orders (npad = 256 ceil((n + 1) / 256)) and buffers are reused across
 sizes."""
+import json
 import sys
 
 import numpy as np
@@ -67,6 +68,113 @@ def test_batch_matches_single_context(fields):
         np.testing.assert_array_equal(sc, ref_sc)
         np.testing.assert_array_equal(fi, ref_fi)
         assert np.isnan(ll[5])
+
+
+def _calls(thetas0, nf):
+    g = synth.rng(77)
+    calls = [thetas0]
+    for _ in range(2):
+        th = thetas0.copy()
+        th[:, 0] *= g.uniform(0.8, 1.2, nf)
+        th[:, 1] *= g.uniform(0.8, 1.2, nf)
+        th[3] = thetas0[3]
+        calls.append(th)
+    return calls
+
+
+@pytest.mark.skip(reason="the graph execution is switched off: its first capture and replay "
+                         "crashed the host process (segmentation fault) and the cause is not "
+                         "identified")
+def test_graph_execution_matches_workers(fields):
+    """The whole call captured in one HIP graph and replayed: every replay
+    (three calls with different theta, eager work of another batch and a
+    single-context evaluation between them, a non-PD field, skipped and
+    adjoint-mode fields) is bitwise the worker execution's result."""
+    data, thetas0 = fields
+    nf = len(data)
+    mode = np.array([2, 1, 3] * (nf // 3 + 1))[:nf]
+    mode[5] = 0
+    g = synth.rng(77)
+    calls = [thetas0]
+    for _ in range(2):
+        th = thetas0.copy()
+        th[:, 0] *= g.uniform(0.8, 1.2, nf)
+        th[:, 1] *= g.uniform(0.8, 1.2, nf)
+        th[3] = thetas0[3]
+        calls.append(th)
+    bw, bg = fbt.Batch(3), fbt.Batch(2)
+    bw.set_fields(data)
+    bg.set_fields(data)
+    bg.set_exec(fbt.Batch.GRAPH)
+    assert bg.exec == fbt.Batch.GRAPH
+    for r, th in enumerate(calls * 2):
+        say("graph replay %d" % r)
+        want = bw.eval(th, mode)
+        got = bg.eval(th, mode)
+        for a, b in zip(got, want):
+            np.testing.assert_array_equal(a, b)
+        assert got[3][3] == fbt.ENOTPD and np.isnan(got[0][5])
+        with fbt.Context(0) as c:       # eager work between replays
+            c.set_data(*data[0])
+            c.loglik(th[0])
+    bw.close()
+    bg.close()
+
+
+def test_graph_execution_is_refused(fields):
+    data, _ = fields
+    b = fbt.Batch(1)
+    b.set_fields(data[:2])
+    with pytest.raises(fbt.FisherBTError):
+        b.set_exec(fbt.Batch.GRAPH)
+    assert b.exec == fbt.Batch.WORKERS
+    b.close()
+
+
+def test_group_limits_and_autotune(fields, tmp_path):
+    """Group limits change the grouping, not the numbers (bitwise); the
+    autotuner picks a limit per padded order and its file restores them."""
+    data, thetas0 = fields
+    nf = len(data)
+    mode = np.array([2, 1, 3] * (nf // 3 + 1))[:nf]
+    mode[5] = 0
+    calls = _calls(thetas0, nf)
+    bw, bl = fbt.Batch(3), fbt.Batch(2)
+    bw.set_fields(data)
+    bl.set_fields(data)
+    # limits: one field per group of order 768, two for 1280
+    bl.set_group_limit(768, 1)
+    bl.set_group_limit(1280, 2)
+    assert bl.group_limit(768) == 1 and bl.group_limit(512) == 0
+    for th in calls:
+        got = bl.eval(th, mode)
+        want = bw.eval(th, mode)
+        for a, b in zip(got, want):
+            np.testing.assert_array_equal(a, b)
+    # autotuner on a small workload, its file restores the choices
+    path = tmp_path / "tune.json"
+    small = [i for i in range(nf) if data[i][1].size <= 700]
+    bt = fbt.Batch(2)
+    bt.set_fields([data[i] for i in small])
+    bt.autotune(calls[0][small], 2, path)
+    rec = json.loads(path.read_text())
+    say("autotune", rec)
+    assert rec["exec"] == 0 and rec["chosen"] in ("per_order", "none", "all_4", "all_16", "all_64")
+    assert (len(rec["limits"]) == 0) == (rec["chosen"] == "none")
+    bt2 = fbt.Batch(2)
+    bt2.set_fields([data[i] for i in small])
+    bt2.load_tuning(path)
+    assert bt2.exec == rec["exec"]
+    for k, v in rec["limits"].items():
+        assert bt2.group_limit(int(k)) == v
+    a = bt2.eval(calls[0][small], 2)
+    mode_s = np.zeros(nf, dtype=np.int32)
+    mode_s[small] = 2
+    b = bw.eval(calls[0], mode_s)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y[small])
+    for bb in (bw, bl, bt, bt2):
+        bb.close()
 
 
 def test_batch_argument_errors(fields):
