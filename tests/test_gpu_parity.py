@@ -214,6 +214,23 @@ def test_fit_n400_matches_oracle(ctx, oracle_mod):
     assert len(it_gpu) == got["n_iter"] + 1
 
 
+def test_fit_l9_n1500_matches_oracle(ctx, oracle_mod):
+    """Fisher-BT from the L9 start (Table 1, the paper's bounds) on 1,500
+    uniform points: the same path as the oracle's driver on the oracle's
+    evaluations (call counts, convergence) and theta-hat to 1e-6 relative."""
+    say("fit n1500 L9")
+    locs, z, _ = synth.dataset(1500, (1.0, 0.1, 0.5), 2025)
+    ctx.set_data(locs, z)
+    got = ctx.fit()
+    want = oracle_mod.fisher_bt(oracle_mod.OracleEvaluator(locs, z))
+    say("gpu", got["theta"], got["n_loglik_calls"], got["n_grad_calls"], "oracle", want["theta"],
+        want["n_loglik_calls"], want["n_grad_calls"])
+    assert got["converged"] and want["converged"]
+    assert got["used_nelder_mead"] == want["used_nelder_mead"]
+    assert (got["n_loglik_calls"], got["n_grad_calls"]) == (want["n_loglik_calls"], want["n_grad_calls"])
+    np.testing.assert_allclose(got["theta"], want["theta"], rtol=1e-6)
+
+
 @pytest.mark.parametrize("n,theta", [(600, (1.0, 0.1, 0.5)), (1500, (1.5, 0.07, 1.0))])
 def test_mixed_precision(ctx, oracle_mod, n, theta):
     """Mixed form: the trace-phase updates on FP32 MFMA.  The log-likelihood is
