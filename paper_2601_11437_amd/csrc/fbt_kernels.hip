@@ -274,16 +274,6 @@ __device__ __forceinline__ double lane_value(double v, int l)
     return __hiloint2double(hi, lo);
 }
 
-// Lanes of one wave exchanging values through LDS: stores before this point
-// are visible to the loads after it in every lane of the wave (and neither
-// moves across it).
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // row and column of the u-th tile of a lower triangle of tiles (row-major order)
 __device__ __forceinline__ void tri_tile(int u, int *ti, int *tj)
 {
