@@ -279,6 +279,27 @@ def precision_bench(args):
         res[name] = {"loglik": ll, "score": sc.tolist(), "fisher": fi.tolist(), "terms": terms.tolist(),
                      "loglik_s": t1 - t0, "eval_s": t3 - t2, "w_phase_s": t2 - t1}
         log("%s: loglik %.3f s, eval %.3f s" % (name, t1 - t0, t3 - t2))
+    if args.precision_fits:
+        # Fisher-BT from the L9 start in FP64 and in the FP32 mixed form
+        lo, hi = (0.01, 0.01, 0.01), (5.0, 5.0, 2.0)
+        for name, prec in (("fp64", fbt.FP64), ("mixed_fp32", fbt.MIXED_FP32)):
+            ctx.set_precision(prec)
+            t0 = time.perf_counter()
+            r = ctx.fit(lo=lo, hi=hi, callback=lambda it, th, ll, g, fi: log(
+                "  %s fit iterate %d: theta %s, |grad| %.3g" % (name, it, np.round(th, 6),
+                                                               np.linalg.norm(g))))
+            dt = time.perf_counter() - t0
+            res[name]["fit"] = {"seconds": dt, "theta": r["theta"].tolist(), "loglik": r["loglik"],
+                                "n_loglik_calls": r["n_loglik_calls"],
+                                "n_grad_calls": r["n_grad_calls"], "converged": r["converged"],
+                                "used_nelder_mead": r["used_nelder_mead"],
+                                "precision_switch": r["precision_switch"],
+                                "grad_norm": float(np.linalg.norm(r["score"]))}
+            log("%s fit: %.1f s, theta %s" % (name, dt, np.round(r["theta"], 7)))
+        ctx.set_precision(fbt.FP64)
+        t64 = np.array(res["fp64"]["fit"]["theta"])
+        tm = np.array(res["mixed_fp32"]["fit"]["theta"])
+        res["mixed_fp32"]["fit"]["theta_rel_err_vs_fp64"] = (np.abs(tm - t64) / np.abs(t64)).tolist()
     ctx.close()
     ref = res["fp64"]
     t = np.array(ref["terms"])
@@ -328,6 +349,8 @@ def main():
                     help="instead of the evaluation rate, the 3x3 grid of FP64 fits at n=10,000")
     ap.add_argument("--precision", action="store_true",
                     help="instead of the evaluation rate, FP64 vs the mixed forms at n=50,000")
+    ap.add_argument("--precision-fits", action="store_true",
+                    help="with --precision, also one FP64 and one mixed Fisher-BT fit (minutes)")
     args = ap.parse_args()
     if args.grid and args.gpus == 1:
         grid_bench(args)

@@ -355,8 +355,6 @@ fbt_status fbt_batch_autotune(fbt_batch *b, const double *thetas, const int32_t 
         *secs = best;
         return FBT_OK;
     };
-    std::string js = "{\n  \"limits\": {";
-    bool first = true;
     for (const auto &kv : count) {
         const int64_t npad = kv.first;
         std::vector<int32_t> sub(nf, 0);
@@ -383,11 +381,6 @@ fbt_status fbt_batch_autotune(fbt_batch *b, const double *thetas, const int32_t 
                 break;
         }
         fbt_batch_set_group_limit(b, npad, best_lim);
-        char buf[96];
-        std::snprintf(buf, sizeof(buf), "%s\n    \"%lld\": %d", first ? "" : ",", (long long)npad,
-                      best_lim);
-        js += buf;
-        first = false;
     }
     // The buckets were timed alone; in the whole call their groups share the
     // workers, so the per-order choices compete with no limits and with one
@@ -428,8 +421,8 @@ fbt_status fbt_batch_autotune(fbt_batch *b, const double *thetas, const int32_t 
         }
     }
     set_all(best_map);
-    js = "{\n  \"limits\": {";
-    first = true;
+    std::string js = "{\n  \"limits\": {";
+    bool first = true;
     for (const auto &kv : b->limit) {
         char lb[96];
         std::snprintf(lb, sizeof(lb), "%s\n    \"%lld\": %d", first ? "" : ",", (long long)kv.first,
