@@ -241,9 +241,9 @@ void launch_gen(hipStream_t s, const GenParams &gp, const GenParams *gpa, const 
 // one workgroup of 512 threads over 32-column panels p = 0..7 (jb = 32 p).
 // Per panel:
 //  A. the panel's 32 x 32 top block T = L_t L_t^T is factored by wave 0 and
-//     D_p = L_t^{-1} formed by wave 1 one column behind it, both in registers
-//     with one row per lane (column c of L_t goes through LDS, published to
-//     wave 1 by a counter).  At the same time waves 2..7 finish the previous
+//     D_p = L_t^{-1} formed by wave 1 a column or two behind it, both in
+//     registers with one row per lane (columns of L_t go through LDS,
+//     published to wave 1 in pairs by a counter).  At the same time waves 2..7 finish the previous
 //     panel's updates: trailing tiles outside the next two tile columns, and
 //     the inverse rows below it, B_i -= Lp[i] X_{p-1};
 //  B. L_t and D_p are stored; the rows below the top block L_b = A_b D_p^T
@@ -406,13 +406,18 @@ __global__ __launch_bounds__(DT) void k_potrf_diag(Fields F, double *__restrict_
                     colb[c * PW + i] = r[c];
                 if (lane == 0)
                     ipv[c] = ip;
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                if (lane == 0)
-                    __hip_atomic_store(&colready, c + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 #pragma unroll
                 for (int j = c + 1; j < PW; ++j) {
                     r[j] -= r[c] * lane_value(r[c], j);
                     asm volatile("" : "+v"(r[j])); // update in place: no broadcast outlives its use
+                }
+                // columns are published in pairs, after the row updates: the
+                // stores above complete behind the updates instead of stalling
+                // the column chain at the fence
+                if ((c & 1) || c == PW - 1) {
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                    if (lane == 0)
+                        __hip_atomic_store(&colready, c + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
             }
             if (lane == 0 && firstbad != 0x7fffffff)

@@ -7,8 +7,12 @@ configuration bench.py times) on outputs the oracle can afford:
   * properties that hold at any size: the Fisher matrix is symmetric positive
     definite with I_11 = n / (2 sigma2^2); the sigma2 score equals
     (Z' Sigma^-1 Z - n) / (2 sigma2); the score matches central differences
-    of the GPU log-likelihood; repeated evaluations are bitwise identical.
+    of the GPU log-likelihood; repeated evaluations are bitwise identical;
+  * a whole Fisher-BT fit (Algorithm 1 from the L9 start) against the
+    oracle's fit of the same field, stored by tests/golden/make_fit_n20k.py.
 """
+import json
+import os
 import sys
 
 import numpy as np
@@ -101,3 +105,29 @@ def test_score_and_fisher_properties(big):
         scale = (t[1] + n) / (2 * theta[0]) if k == 0 else 0.5 * (abs(t[1 + k]) + abs(t[3 + k]))
         say("fullsize: score %d gpu %.6f fd %.6f scale %.3e" % (k, score[k], fd, scale))
         assert abs(fd - score[k]) <= 1e-6 * scale
+
+
+GOLDEN_FIT = os.path.join(os.path.dirname(__file__), "golden", "fit_n20k_oracle.json")
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN_FIT),
+                    reason="the oracle's fit at n = 20,000 has not been stored "
+                           "(tests/golden/make_fit_n20k.py takes hours of host time)")
+def test_fit_matches_oracle_fit(big):
+    """Algorithm 1 at n = 20,000 from the L9 start of Table 1 within the
+    paper's simulation bounds: the same path as the oracle's driver on the
+    oracle's evaluations (call counts, convergence, no Nelder-Mead) and
+    theta-hat within 1e-6 relative of the oracle's."""
+    ctx, locs, z, w = big
+    g = json.load(open(GOLDEN_FIT))
+    assert g["workload"]["n"] == w["n"] and g["workload"]["seed"] == w["seed"]
+    say("fullsize: fit")
+    got = ctx.fit(lo=g["bounds"]["lower"], hi=g["bounds"]["upper"])
+    say("fullsize: fit gpu %s (%d ll, %d grad) oracle %s (%d ll, %d grad)" % (
+        np.array2string(got["theta"], precision=10), got["n_loglik_calls"], got["n_grad_calls"],
+        g["theta"], g["n_loglik_calls"], g["n_grad_calls"]))
+    assert got["converged"] and g["converged"]
+    assert bool(got["used_nelder_mead"]) == g["used_nelder_mead"]
+    assert (got["n_loglik_calls"], got["n_grad_calls"]) == (g["n_loglik_calls"], g["n_grad_calls"])
+    np.testing.assert_allclose(got["theta"], g["theta"], rtol=1e-6)
+    assert abs(got["loglik"] - g["loglik"]) <= 1e-10 * abs(g["loglik"])
