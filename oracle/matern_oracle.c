@@ -77,24 +77,37 @@ static double scaled_integral(double mu, double x, int kind)
 double oracle_bessel_k_scaled(double mu, double x) { return scaled_integral(mu, x, 0); }
 double oracle_bessel_dk_scaled(double mu, double x) { return scaled_integral(mu, x, 1); }
 
-/* C, C_alpha, C_nu at distance h >= 0 for theta = (sigma2, alpha, nu). */
-void oracle_matern_entry(double h, double sigma2, double alpha, double nu, double out[3])
+/* The entries selected by `want` (bit 0: C, bit 1: C_alpha, bit 2: C_nu) at
+ * distance h >= 0; only the integrals those entries need are evaluated, and
+ * the others are left as 0. */
+static void matern_entry_sel(double h, double sigma2, double alpha, double nu, int want,
+                             double out[3])
 {
+    out[0] = out[1] = out[2] = 0.0;
     if (h == 0.0) {
         out[0] = sigma2;
-        out[1] = 0.0;
-        out[2] = 0.0;
         return;
     }
     double x = h / alpha;
     double cnu = exp((1.0 - nu) * log(2.0) - lgamma(nu));
     double xnu_emx = exp(nu * log(x) - x); /* x^nu e^{-x}; the K sums carry e^{+x} */
-    double k_nu = oracle_bessel_k_scaled(nu, x);
-    double k_num1 = oracle_bessel_k_scaled(nu - 1.0, x);
-    double dk_nu = oracle_bessel_dk_scaled(nu, x);
-    out[0] = sigma2 * cnu * xnu_emx * k_nu;
-    out[1] = (sigma2 / alpha) * cnu * x * xnu_emx * k_num1;
-    out[2] = sigma2 * cnu * xnu_emx * ((log(0.5 * x) - oracle_digamma(nu)) * k_nu + dk_nu);
+    double k_nu = (want & 5) ? oracle_bessel_k_scaled(nu, x) : 0.0;
+    if (want & 1)
+        out[0] = sigma2 * cnu * xnu_emx * k_nu;
+    if (want & 2) {
+        double k_num1 = oracle_bessel_k_scaled(nu - 1.0, x);
+        out[1] = (sigma2 / alpha) * cnu * x * xnu_emx * k_num1;
+    }
+    if (want & 4) {
+        double dk_nu = oracle_bessel_dk_scaled(nu, x);
+        out[2] = sigma2 * cnu * xnu_emx * ((log(0.5 * x) - oracle_digamma(nu)) * k_nu + dk_nu);
+    }
+}
+
+/* C, C_alpha, C_nu at distance h >= 0 for theta = (sigma2, alpha, nu). */
+void oracle_matern_entry(double h, double sigma2, double alpha, double nu, double out[3])
+{
+    matern_entry_sel(h, sigma2, alpha, nu, 7, out);
 }
 
 /* Entry-wise over a list of distances (used by the pins). */
@@ -117,13 +130,14 @@ void oracle_matern_entries(int64_t m, const double *h, double sigma2, double alp
 void oracle_cov_matrices(int64_t n, const double *locs, double sigma2, double alpha, double nu,
                          double *S, double *Sa, double *Sn)
 {
+    const int want = (S ? 1 : 0) | (Sa ? 2 : 0) | (Sn ? 4 : 0);
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t i = 0; i < n; ++i) {
         for (int64_t j = 0; j <= i; ++j) {
             double dx = locs[2 * i] - locs[2 * j];
             double dy = locs[2 * i + 1] - locs[2 * j + 1];
             double o[3];
-            oracle_matern_entry(sqrt(dx * dx + dy * dy), sigma2, alpha, nu, o);
+            matern_entry_sel(sqrt(dx * dx + dy * dy), sigma2, alpha, nu, want, o);
             if (S) {
                 S[i * n + j] = o[0];
                 S[j * n + i] = o[0];
