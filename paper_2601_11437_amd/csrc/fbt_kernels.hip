@@ -691,9 +691,12 @@ template <int WM, int WN, bool BKC, bool NEG = false, bool AKC = false> struct T
                     acc[i][j] = mfma(b[j], a[i], acc[i][j]);
         }
     }
-    // acc += (NEG ? -A : A)(BM x K) * B(BN x K)^T for the workgroup tile; K % 16 == 0
+    // acc += (NEG ? -A : A)(BM x K) * B(BN x K)^T for the workgroup tile; K % 16 == 0.
+    // A wave multiplies only the first `cmax` chunks of 16: callers whose operand is a
+    // lower-triangular NB x NB block pass the chunks that can hold nonzeros for the wave's
+    // rows (every chunk is still staged by the whole workgroup).
     __device__ static void run(d4 (&acc)[4][4], const double *A, int64_t lda, const double *B,
-                               int64_t ldb, int K, double *lds)
+                               int64_t ldb, int K, double *lds, int cmax = 1 << 30)
     {
         const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
         const int wm = wave % WM, wn = wave / WM;
@@ -705,7 +708,8 @@ template <int WM, int WN, bool BKC, bool NEG = false, bool AKC = false> struct T
         for (int c = 0; c < nch; ++c) {
             if (c + 1 < nch)
                 load(ra, rb, A, lda, B, ldb, (c + 1) * KC);
-            compute(acc, lds + (c & 1) * STAGE, wm, wn, lane);
+            if (c < cmax)
+                compute(acc, lds + (c & 1) * STAGE, wm, wn, lane);
             if (c + 1 < nch)
                 store(ra, rb, lds + ((c + 1) & 1) * STAGE);
             __syncthreads();
@@ -1114,10 +1118,11 @@ __global__ __launch_bounds__(256) void k_panel(Fields F, double *P, int64_t ld, 
     const int f = blockIdx.y; // field
     Linv += f * F.sLinv;
     double *Pb = P + f * F.sA + (int64_t)blockIdx.x * 64;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     d4 acc[4][4];
     TL::zero(acc);
-    TL::run(acc, Pb, ld, Linv, NB, NB, lds);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // output columns 64 wave.. of P Linv^T: Linv rows there vanish past column 64 wave + 63
+    TL::run(acc, Pb, ld, Linv, NB, NB, lds, 4 * (wave + 1));
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -1153,10 +1158,11 @@ __global__ __launch_bounds__(256) void k_diag_apply(Fields F, int64_t sS, double
     const int64_t ct = blockIdx.x;
     const int64_t c0 = (ct < half_tiles) ? 64 * ct : col_shift + 64 * (ct - half_tiles);
     double *Sb = S + krow + c0 * ld;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     d4 acc[4][4];
     TL::zero(acc);
-    TL::run(acc, Linv, NB, Sb, ld, NB, lds);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // rows 64 wave.. of Linv vanish past column 64 wave + 63
+    TL::run(acc, Linv, NB, Sb, ld, NB, lds, 4 * (wave + 1));
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -1270,7 +1276,8 @@ __global__ __launch_bounds__(256) void k_panel_reduce(Fields F, double *Xa, doub
     d4 acc[4][4];
     double s[7] = {0, 0, 0, 0, 0, 0, 0}; // t_a, t_n, u_a, u_n, F_aa, F_an, F_nn
     TL::zero(acc);
-    TL::run(acc, Xa + m0 + kcol * ld, ld, Linv, NB, NB, lds);
+    // output columns 64 wave.. of X Linv^T: Linv rows there vanish past column 64 wave + 63
+    TL::run(acc, Xa + m0 + kcol * ld, ld, Linv, NB, NB, lds, 4 * (wave + 1));
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -1279,7 +1286,7 @@ __global__ __launch_bounds__(256) void k_panel_reduce(Fields F, double *Xa, doub
             for (int r = 0; r < 4; ++r)
                 Xa[m0 + TL::row(i, lane, 0) + (kcol + TL::col(j, r, lane, wave)) * ld] = acc[i][j][r];
     TL::zero(acc);
-    TL::run(acc, Xn + m0 + kcol * ld, ld, Linv, NB, NB, lds);
+    TL::run(acc, Xn + m0 + kcol * ld, ld, Linv, NB, NB, lds, 4 * (wave + 1));
     // W_alpha is read back by the lane that stored it (program order makes its
     // own stores visible), which keeps the workgroup small enough to share a
     // CU with a trailing-update workgroup.
