@@ -280,16 +280,21 @@ def precision_bench(args):
                      "loglik_s": t1 - t0, "eval_s": t3 - t2, "w_phase_s": t2 - t1}
         log("%s: loglik %.3f s, eval %.3f s" % (name, t1 - t0, t3 - t2))
     if args.precision_fits:
-        # Fisher-BT from the L9 start in FP64 and in the FP32 mixed form
+        # Fisher-BT from the L9 start in FP64 and in the FP32 and BF16 mixed forms
+        # (both switch to FP64 near the optimum).  No Nelder-Mead fallback: a
+        # fit that exhausts its derivative budget reports so (the fallback's
+        # hundreds of log-likelihood calls would take minutes at this size).
         lo, hi = (0.01, 0.01, 0.01), (5.0, 5.0, 2.0)
-        for name, prec in (("fp64", fbt.FP64), ("mixed_fp32", fbt.MIXED_FP32)):
+        for name, prec in (("fp64", fbt.FP64), ("mixed_fp32", fbt.MIXED_FP32),
+                           ("mixed_bf16", fbt.MIXED_BF16)):
             ctx.set_precision(prec)
             t0 = time.perf_counter()
-            r = ctx.fit(lo=lo, hi=hi, callback=lambda it, th, ll, g, fi: log(
+            r = ctx.fit(lo=lo, hi=hi, nelder_mead=0, callback=lambda it, th, ll, g, fi: log(
                 "  %s fit iterate %d: theta %s, |grad| %.3g" % (name, it, np.round(th, 6),
                                                                np.linalg.norm(g))))
             dt = time.perf_counter() - t0
             res[name]["fit"] = {"seconds": dt, "theta": r["theta"].tolist(), "loglik": r["loglik"],
+                                "status": int(r["status"]),
                                 "n_loglik_calls": r["n_loglik_calls"],
                                 "n_grad_calls": r["n_grad_calls"], "converged": r["converged"],
                                 "used_nelder_mead": r["used_nelder_mead"],
@@ -298,8 +303,9 @@ def precision_bench(args):
             log("%s fit: %.1f s, theta %s" % (name, dt, np.round(r["theta"], 7)))
         ctx.set_precision(fbt.FP64)
         t64 = np.array(res["fp64"]["fit"]["theta"])
-        tm = np.array(res["mixed_fp32"]["fit"]["theta"])
-        res["mixed_fp32"]["fit"]["theta_rel_err_vs_fp64"] = (np.abs(tm - t64) / np.abs(t64)).tolist()
+        for name in ("mixed_fp32", "mixed_bf16"):
+            tm = np.array(res[name]["fit"]["theta"])
+            res[name]["fit"]["theta_rel_err_vs_fp64"] = (np.abs(tm - t64) / np.abs(t64)).tolist()
     ctx.close()
     ref = res["fp64"]
     t = np.array(ref["terms"])
@@ -350,7 +356,7 @@ def main():
     ap.add_argument("--precision", action="store_true",
                     help="instead of the evaluation rate, FP64 vs the mixed forms at n=50,000")
     ap.add_argument("--precision-fits", action="store_true",
-                    help="with --precision, also one FP64 and one mixed Fisher-BT fit (minutes)")
+                    help="with --precision, also one FP64 and two mixed Fisher-BT fits (minutes)")
     args = ap.parse_args()
     if args.grid and args.gpus == 1:
         grid_bench(args)
