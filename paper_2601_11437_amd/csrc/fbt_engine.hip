@@ -58,6 +58,13 @@ struct fbt_ctx {
     double *h_out = nullptr;
     int *h_info = nullptr;
     size_t cap[24] = {0};  // allocated bytes per buffer (buffers only grow)
+    // FBT_MIXED_FP32: FP32 copies of the factor's block-lower part (same layout
+    // as A) and of the left solve's current pair of solved block rows (two
+    // slots of 2 NB x 2 npad floats, by pair parity); allocated on the first
+    // evaluation in that form, and optional (without them the solve converts
+    // the FP64 operands when staging, with bitwise the same results)
+    float *Lf = nullptr, *Xf = nullptr;
+    size_t cap_lf = 0, cap_xf = 0;
 
     // fields held: 1 for the single-field API; G >= 1 inside a batched group
     int G = 1;
@@ -327,6 +334,40 @@ void free_buffers(fbt_ctx *c)
         *p = nullptr;
     }
     std::memset(c->cap, 0, sizeof(c->cap));
+    (void)hipFree(c->Lf);
+    (void)hipFree(c->Xf);
+    c->Lf = nullptr;
+    c->Xf = nullptr;
+    c->cap_lf = c->cap_xf = 0;
+}
+
+// The FP32 copies for the current fields (FBT_MIXED_FP32 only).  A failed
+// allocation is not an error: the left solve then converts when staging.
+void ensure_f32(fbt_ctx *c)
+{
+    if (c->precision != FBT_MIXED_FP32)
+        return;
+    const size_t lf = (size_t)c->G * c->npad * c->ld * sizeof(float);
+    const size_t xf = (size_t)c->G * (size_t)c->F.sXf * sizeof(float);
+    if (lf > c->cap_lf) {
+        (void)hipFree(c->Lf);
+        c->Lf = nullptr;
+        c->cap_lf = 0;
+        if (hipMalloc(&c->Lf, lf) == hipSuccess)
+            c->cap_lf = lf;
+        else
+            c->Lf = nullptr;
+    }
+    if (xf > c->cap_xf) {
+        (void)hipFree(c->Xf);
+        c->Xf = nullptr;
+        c->cap_xf = 0;
+        if (hipMalloc(&c->Xf, xf) == hipSuccess)
+            c->cap_xf = xf;
+        else
+            c->Xf = nullptr;
+    }
+    (void)hipGetLastError(); // a failed allocation leaves no sticky error behind
 }
 
 // Buffers for G fields of up to nmax observations each (same padded order);
@@ -392,6 +433,7 @@ fbt_status alloc_fields(fbt_ctx *c, int64_t nmax, int G, bool batched)
     c->F.sVec = npad;
     c->F.sPart = (int64_t)part;
     c->F.sLog = T;
+    c->F.sXf = 2 * (2 * NB) * (2 * npad);
     c->batched = batched;
     c->F.n = batched ? c->d_nf : nullptr;
     c->fst.assign(G, FBT_OK);
@@ -578,6 +620,7 @@ fbt_status derivative_terms(fbt_ctx *c, const double *th, double terms[9])
         return st;
     }
     c->factor_valid = false; // reuse is for one derivative evaluation only
+    ensure_f32(c);
     if ((st = wphase_enqueue(c)) != FBT_OK)
         return st;
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -598,6 +641,24 @@ fbt_status wphase_enqueue(fbt_ctx *c)
     // solve updates: FP32 (1) or BF16 operands with FP32 sums (2)
     const int mix = c->precision == FBT_FP64 ? 0 : c->precision == FBT_MIXED_BF16 ? 2 : 1;
     auto Lk = [&](int k) { return c->Linv + (size_t)k * NB * NB; };
+    // FP32 form with its operand copies: the factor once, each solved pair of
+    // block rows as the diagonal apply writes it (slot by pair parity, so the
+    // next pair's rows never overwrite rows a running update still reads)
+    const bool f32 = mix == 1 && c->Lf && c->Xf;
+    auto xslot = [&](int b) { return c->Xf + (size_t)((b / 2) & 1) * (2 * NB) * (2 * npad); };
+    if (f32)
+        launch_to_f32_lower(s0, c->F, A, ld, npad, c->Lf);
+    // left update of `rows` rows from r by the `kp` panels of pair b (K = kp NB)
+    auto left_update = [&](hipStream_t st, int64_t r, int64_t rows, int b, int kp, int K) {
+        if (!f32) {
+            launch_update_nn(st, c->F, c->F.sS2, 2, c->S2, ld, A, ld, r, (int64_t)b * NB, rows, ncols,
+                             npad, K, mix);
+            return;
+        }
+        for (int p = 0; p < kp; ++p)
+            launch_update_nn_f32(st, c->F, c->F.sS2, 2, c->S2, ld, c->Lf, r, (int64_t)(b + p) * NB,
+                                 xslot(b), p * NB, rows, ncols, npad);
+    };
 
     // Left solve X = L'^{-1} [Sigma_alpha' | Sigma_nu'] on columns [0, ncols) of
     // each half.  Block rows are taken in pairs (b, b + 1).  Inside a pair the
@@ -616,12 +677,14 @@ fbt_status wphase_enqueue(fbt_ctx *c)
         const int64_t r0 = (int64_t)b * NB, rn = r0 + (int64_t)nb * NB;
         const int K = nb * NB;
         TIMED(c, s0, KC_LAPPLY, 2.0 * dn * dNB * dNB,
-              launch_diag_apply(s0, c->F, c->F.sS2, 2, c->S2, ld, r0, Lk(b), ncols, npad));
+              launch_diag_apply(s0, c->F, c->F.sS2, 2, c->S2, ld, r0, Lk(b), ncols, npad,
+                                f32 ? xslot(b) : nullptr, 0));
         if (nb == 2) {
             TIMED(c, s0, KC_LUPD, 2.0 * real_rows(r0 + NB, NB) * dNB * 2.0 * dn,
-                  launch_update_nn(s0, c->F, c->F.sS2, 2, c->S2, ld, A, ld, r0 + NB, r0, NB, ncols, npad, NB, mix));
+                  left_update(s0, r0 + NB, NB, b, 1, NB));
             TIMED(c, s0, KC_LAPPLY, 2.0 * dn * dNB * dNB,
-                  launch_diag_apply(s0, c->F, c->F.sS2, 2, c->S2, ld, r0 + NB, Lk(b + 1), ncols, npad));
+                  launch_diag_apply(s0, c->F, c->F.sS2, 2, c->S2, ld, r0 + NB, Lk(b + 1), ncols, npad,
+                                    f32 ? xslot(b) : nullptr, NB));
         }
         HIPCHK(c, hipEventRecord(c->evP, s0));
         if (rn >= npad)
@@ -629,12 +692,11 @@ fbt_status wphase_enqueue(fbt_ctx *c)
         const int64_t la = std::min<int64_t>(2 * NB, npad - rn); // rows of the next pair
         HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
         TIMED(c, s0, KC_LUPD, 2.0 * real_rows(rn, la) * K * 2.0 * dn,
-              launch_update_nn(s0, c->F, c->F.sS2, 2, c->S2, ld, A, ld, rn, r0, la, ncols, npad, K, mix));
+              left_update(s0, rn, la, b, nb, K));
         HIPCHK(c, hipStreamWaitEvent(s1, c->evP, 0));
         if (rn + la < npad)
             TIMED(c, s1, KC_LUPD, 2.0 * real_rows(rn + la, npad) * K * 2.0 * dn,
-                  launch_update_nn(s1, c->F, c->F.sS2, 2, c->S2, ld, A, ld, rn + la, r0, npad - rn - la, ncols,
-                                   npad, K, mix));
+                  left_update(s1, rn + la, npad - rn - la, b, nb, K));
         HIPCHK(c, hipEventRecord(c->evB, s1));
     }
     HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
@@ -897,6 +959,7 @@ fbt_status fbt::group_prepare(fbt_ctx *c, int G, const int64_t *n, const double 
     fbt_status st = alloc_fields(c, nmax, G, true);
     if (st != FBT_OK)
         return st;
+    ensure_f32(c);
     c->nf.assign(n, n + G);
     std::vector<double> xs((size_t)G * npad, 0.0), ys((size_t)G * npad, 0.0), zs((size_t)G * npad, 0.0);
     for (int f = 0; f < G; ++f)

@@ -71,6 +71,7 @@ struct Fields {
     int64_t sPart; // partial sums
     int64_t sLog;  // log-det partials (T)
     const int64_t *n; // per-field n (device; nullptr: the launch's n for every field)
+    int64_t sXf;   // FP32 copies of a pair of solved block rows (2 x 2 NB x 2 npad floats)
 };
 
 // kernel launchers (fbt_kernels.hip); all asynchronous on `s`.  Launchers
@@ -94,9 +95,20 @@ void launch_update_rect(hipStream_t s, const Fields &F, int64_t sC, int64_t sB, 
                         int64_t lda, const double *B, int64_t ldb, int64_t rows, int64_t ncol,
                         int K, int mixed);
 // sS: stride of S (F.sS2, or F.sA for the adjoint's inverse)
+// With Xf (FP32 form of the left solve), the solved rows are also stored as
+// floats at Xf[(kofs + row) + col * 2 NB] (per field offset F.sXf).
 void launch_diag_apply(hipStream_t s, const Fields &F, int64_t sS, int nmat, double *S,
                        int64_t ld, int64_t krow, const double *Linv, int64_t ncols,
-                       int64_t col_shift);
+                       int64_t col_shift, float *Xf = nullptr, int kofs = 0);
+// FP32 form of the left-solve update from FP32 operand copies: S[r0.., cols] -=
+// Lf[r0.., krow:krow+NB] * Xf[kofs:kofs+NB, cols] (one NB-deep slice; Lf per field
+// offset F.sA, Xf as written by launch_diag_apply)
+void launch_update_nn_f32(hipStream_t s, const Fields &F, int64_t sS, int nmat, double *S,
+                          int64_t ld, const float *Lf, int64_t r0, int64_t krow, const float *Xf,
+                          int kofs, int64_t rows, int64_t ncols, int64_t col_shift);
+// Lf = (float) A on the block-lower part (NB blocks at or below the diagonal)
+void launch_to_f32_lower(hipStream_t s, const Fields &F, const double *A, int64_t ld, int64_t npad,
+                         float *Lf);
 void launch_update_nn(hipStream_t s, const Fields &F, int64_t sS, int nmat, double *S, int64_t ld,
                       const double *L, int64_t lda, int64_t r0, int64_t krow, int64_t rows,
                       int64_t ncols, int64_t col_shift, int K, int mixed);

@@ -883,6 +883,89 @@ template <int WM, int WN, bool BKC> struct TileF {
     }
 };
 
+// TileF with the operands already in FP32 in memory (the FP32 copies of the
+// factor and of the solved block rows): A M-contiguous (element (m, k) at
+// A[m + k lda]), B K-contiguous (element (n, k) at B[k + n ldb]); 16-byte
+// loads, no conversion when staging.  Same LDS layout, MFMA sequence and C
+// update as TileF, so the results are bitwise those of TileF on the FP64
+// operands.
+template <int WM, int WN> struct TileG {
+    using T = TileF<WM, WN, true>;
+    static constexpr int BM = T::BM, BN = T::BN, KC = T::KC, LSA = T::LSA, LSB = T::LSB;
+    static constexpr int STAGE = T::STAGE, LDS = T::LDS;
+    static constexpr int NA = BM * KC / 1024, NBL = BN * KC / 1024; // float4 loads per thread
+
+    __device__ static void load(float4 *ra, float4 *rb, const float *A, int64_t lda,
+                                const float *B, int64_t ldb, int k0)
+    {
+        const int t = threadIdx.x;
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const int q = t + 256 * i, m4 = q % (BM / 4), k = q / (BM / 4);
+            ra[i] = *(const float4 *)(A + 4 * m4 + (int64_t)(k0 + k) * lda);
+        }
+#pragma unroll
+        for (int i = 0; i < NBL; ++i) {
+            const int q = t + 256 * i, k4 = q % (KC / 4), nn = q / (KC / 4);
+            rb[i] = *(const float4 *)(B + (k0 + 4 * k4) + (int64_t)nn * ldb);
+        }
+    }
+    __device__ static void store(const float4 *ra, const float4 *rb, float *st)
+    {
+        const int t = threadIdx.x;
+        float *As = st, *Bs = st + KC * LSA;
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const int q = t + 256 * i, m4 = q % (BM / 4), k = q / (BM / 4);
+            *(float4 *)(As + k * LSA + 4 * m4) = ra[i];
+        }
+#pragma unroll
+        for (int i = 0; i < NBL; ++i) {
+            const int q = t + 256 * i, k4 = q % (KC / 4), nn = q / (KC / 4);
+            Bs[(4 * k4) * LSB + nn] = rb[i].x;
+            Bs[(4 * k4 + 1) * LSB + nn] = rb[i].y;
+            Bs[(4 * k4 + 2) * LSB + nn] = rb[i].z;
+            Bs[(4 * k4 + 3) * LSB + nn] = rb[i].w;
+        }
+    }
+    // C(BM x BN, FP64) -= A(BM x NB) * B(BN x NB)^T, one NB-deep FP32 slice
+    __device__ static void update_slice(double *C, int64_t ldc, const float *A, int64_t lda,
+                                        const float *B, int64_t ldb, float *lds)
+    {
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        const int wm = wave % WM, wn = wave / WM;
+        f4 acc[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
+        float4 ra[NA], rb[NBL];
+        load(ra, rb, A, lda, B, ldb, 0);
+        store(ra, rb, lds);
+        __syncthreads();
+        constexpr int nch = NB / KC;
+        for (int c = 0; c < nch; ++c) {
+            if (c + 1 < nch)
+                load(ra, rb, A, lda, B, ldb, (c + 1) * KC);
+            T::compute(acc, lds + (c & 1) * STAGE, wm, wn, lane);
+            if (c + 1 < nch)
+                store(ra, rb, lds + ((c + 1) & 1) * STAGE);
+            __syncthreads();
+        }
+        double *cb = C + (wm * 64 + (lane & 15)) + (int64_t)(wn * 64 + 4 * (lane >> 4)) * ldc;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                double *cc = cb + (int64_t)(16 * j + r) * ldc;
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    cc[16 * i] = cc[16 * i] - (double)acc[i][j][r];
+            }
+    }
+};
+
 // BF16 variant of TileF: operands rounded to bfloat16 (round to nearest
 // even, through FP32) when staged into LDS, products summed in FP32 on
 // v_mfma_f32_16x16x16_bf16 over NB-deep slices, each slice subtracted from the
@@ -1148,7 +1231,8 @@ void launch_panel(hipStream_t s, const Fields &F, double *P, int64_t ld, int64_t
 // launched).
 __global__ __launch_bounds__(256) void k_diag_apply(Fields F, int64_t sS, double *S, int64_t ld,
                                                     int64_t krow, const double *Linv,
-                                                    int64_t half_tiles, int64_t col_shift)
+                                                    int64_t half_tiles, int64_t col_shift,
+                                                    float *Xf, int kofs)
 {
     using TL = Tile<4, 1, true>;
     __shared__ double lds[TL::LDS];
@@ -1170,17 +1254,28 @@ __global__ __launch_bounds__(256) void k_diag_apply(Fields F, int64_t sS, double
 #pragma unroll
             for (int r = 0; r < 4; ++r)
                 Sb[TL::row(i, lane, wave) + (int64_t)TL::col(j, r, lane, 0) * ld] = acc[i][j][r];
+    if (Xf) {
+        float *xb = Xf + f * F.sXf + kofs + c0 * (2 * NB);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    xb[TL::row(i, lane, wave) + (int64_t)TL::col(j, r, lane, 0) * (2 * NB)] =
+                        (float)acc[i][j][r];
+    }
 }
 
 void launch_diag_apply(hipStream_t s, const Fields &F, int64_t sS, int nmat, double *S,
                        int64_t ld, int64_t krow, const double *Linv, int64_t ncols,
-                       int64_t col_shift)
+                       int64_t col_shift, float *Xf, int kofs)
 {
     const int64_t half = ncols / 64;
     if (half <= 0)
         return;
     hipLaunchKernelGGL(k_diag_apply, dim3((unsigned)(nmat * half), F.count), dim3(256), 0, s, F,
-                       sS, S, ld, krow, Linv, half, col_shift);
+                       sS, S, ld, krow, Linv, half, col_shift, Xf, kofs);
 }
 
 // Left solve, update below the diagonal block(s):
@@ -1236,6 +1331,63 @@ void launch_update_nn(hipStream_t s, const Fields &F, int64_t sS, int nmat, doub
     }
     auto kern = K == 2 * NB ? k_update_nn<0, 2 * NB> : k_update_nn<0, NB>;
     hipLaunchKernelGGL(kern, g, dim3(256), 0, s, F, sS, S, ld, L, lda, r0, krow, half, col_shift);
+}
+
+// FP32 form of the left-solve update from the FP32 copies (one NB-deep slice):
+// C = S[m0.., c0..] -= Lf[m0.., krow:krow+NB] * Xf[kofs.., c0..]^T, 128 x 128 tiles.
+// Bitwise the same as k_update_nn<1, NB> on the FP64 operands.
+__global__ __launch_bounds__(256) void k_update_nn_f32(Fields F, int64_t sS, double *S, int64_t ld,
+                                                       const float *Lf, int64_t r0, int64_t krow,
+                                                       const float *Xf, int kofs,
+                                                       int64_t half_tiles, int64_t col_shift)
+{
+    using TG = TileG<2, 2>;
+    __shared__ float lds[TG::LDS];
+    const int f = blockIdx.z; // field
+    S += f * sS;
+    Lf += f * F.sA;
+    Xf += f * F.sXf;
+    const int64_t ct = blockIdx.x;
+    const int64_t c0 = (ct < half_tiles) ? 128 * ct : col_shift + 128 * (ct - half_tiles);
+    const int64_t m0 = r0 + 128 * (int64_t)blockIdx.y;
+    TG::update_slice(S + m0 + c0 * ld, ld, Lf + m0 + krow * ld, ld, Xf + kofs + c0 * (2 * NB),
+                     2 * NB, lds);
+}
+
+void launch_update_nn_f32(hipStream_t s, const Fields &F, int64_t sS, int nmat, double *S,
+                          int64_t ld, const float *Lf, int64_t r0, int64_t krow, const float *Xf,
+                          int kofs, int64_t rows, int64_t ncols, int64_t col_shift)
+{
+    const int64_t half = ncols / 128;
+    if (rows <= 0 || half <= 0)
+        return;
+    const dim3 g((unsigned)(nmat * half), (unsigned)(rows / 128), F.count);
+    hipLaunchKernelGGL(k_update_nn_f32, g, dim3(256), 0, s, F, sS, S, ld, Lf, r0, krow, Xf, kofs,
+                       half, col_shift);
+}
+
+// Lf = (float) A on the NB blocks at or below the diagonal; blockIdx.x walks
+// the columns of a block column (y = block column, z = field), 64 threads per
+// 64 rows.
+__global__ __launch_bounds__(256) void k_to_f32_lower(Fields F, const double *A, int64_t ld,
+                                                      int64_t npad, float *Lf)
+{
+    const int f = blockIdx.z;
+    A += f * F.sA;
+    Lf += f * F.sA;
+    const int64_t col = (int64_t)blockIdx.y * NB + blockIdx.x;  // one column per workgroup
+    const int64_t r0 = (int64_t)blockIdx.y * NB;                // rows from its block's diagonal
+    for (int64_t r = r0 + 2 * (int64_t)threadIdx.x; r < npad; r += 512) {
+        const double2 v = *(const double2 *)(A + r + col * ld);
+        *(float2 *)(Lf + r + col * ld) = make_float2((float)v.x, (float)v.y);
+    }
+}
+
+void launch_to_f32_lower(hipStream_t s, const Fields &F, const double *A, int64_t ld, int64_t npad,
+                         float *Lf)
+{
+    hipLaunchKernelGGL(k_to_f32_lower, dim3(NB, (unsigned)(npad / NB), F.count), dim3(256), 0, s, F,
+                       A, ld, npad, Lf);
 }
 
 // ---------------------------------------------------------------------------
