@@ -58,7 +58,7 @@ struct fbt_ctx {
     double *h_out = nullptr;
     int *h_info = nullptr;
     size_t cap[24] = {0};  // allocated bytes per buffer (buffers only grow)
-    // FBT_MIXED_FP32: FP32 copies of the factor's block-lower part (same layout
+    // FBT_MIXED_FP32 and _BF16: FP32 copies of the factor's block-lower part (same layout
     // as A) and of the left solve's current pair of solved block rows (two
     // slots of 2 NB x 2 npad floats, by pair parity); allocated on the first
     // evaluation in that form, and optional (without them the solve converts
@@ -341,11 +341,11 @@ void free_buffers(fbt_ctx *c)
     c->cap_lf = c->cap_xf = 0;
 }
 
-// The FP32 copies for the current fields (FBT_MIXED_FP32 only).  A failed
+// The FP32 copies for the current fields (FBT_MIXED_FP32 and FBT_MIXED_BF16).  A failed
 // allocation is not an error: the left solve then converts when staging.
 void ensure_f32(fbt_ctx *c)
 {
-    if (c->precision != FBT_MIXED_FP32)
+    if (c->precision != FBT_MIXED_FP32 && c->precision != FBT_MIXED_BF16)
         return;
     const size_t lf = (size_t)c->G * c->npad * c->ld * sizeof(float);
     const size_t xf = (size_t)c->G * (size_t)c->F.sXf * sizeof(float);
@@ -641,10 +641,10 @@ fbt_status wphase_enqueue(fbt_ctx *c)
     // solve updates: FP32 (1) or BF16 operands with FP32 sums (2)
     const int mix = c->precision == FBT_FP64 ? 0 : c->precision == FBT_MIXED_BF16 ? 2 : 1;
     auto Lk = [&](int k) { return c->Linv + (size_t)k * NB * NB; };
-    // FP32 form with its operand copies: the factor once, each solved pair of
+    // mixed forms with their operand copies: the factor once, each solved pair of
     // block rows as the diagonal apply writes it (slot by pair parity, so the
     // next pair's rows never overwrite rows a running update still reads)
-    const bool f32 = mix == 1 && c->Lf && c->Xf;
+    const bool f32 = mix != 0 && c->Lf && c->Xf;
     auto xslot = [&](int b) { return c->Xf + (size_t)((b / 2) & 1) * (2 * NB) * (2 * npad); };
     if (f32)
         launch_to_f32_lower(s0, c->F, A, ld, npad, c->Lf);
@@ -657,7 +657,7 @@ fbt_status wphase_enqueue(fbt_ctx *c)
         }
         for (int p = 0; p < kp; ++p)
             launch_update_nn_f32(st, c->F, c->F.sS2, 2, c->S2, ld, c->Lf, r, (int64_t)(b + p) * NB,
-                                 xslot(b), p * NB, rows, ncols, npad);
+                                 xslot(b), p * NB, rows, ncols, npad, mix == 2);
     };
 
     // Left solve X = L'^{-1} [Sigma_alpha' | Sigma_nu'] on columns [0, ncols) of

@@ -100,12 +100,12 @@ void launch_update_rect(hipStream_t s, const Fields &F, int64_t sC, int64_t sB, 
 void launch_diag_apply(hipStream_t s, const Fields &F, int64_t sS, int nmat, double *S,
                        int64_t ld, int64_t krow, const double *Linv, int64_t ncols,
                        int64_t col_shift, float *Xf = nullptr, int kofs = 0);
-// FP32 form of the left-solve update from FP32 operand copies: S[r0.., cols] -=
-// Lf[r0.., krow:krow+NB] * Xf[kofs:kofs+NB, cols] (one NB-deep slice; Lf per field
-// offset F.sA, Xf as written by launch_diag_apply)
+// FP32 (or, with bf16, BF16) form of the left-solve update from FP32 operand
+// copies: S[r0.., cols] -= Lf[r0.., krow:krow+NB] * Xf[kofs:kofs+NB, cols] (one
+// NB-deep slice; Lf per field offset F.sA, Xf as written by launch_diag_apply)
 void launch_update_nn_f32(hipStream_t s, const Fields &F, int64_t sS, int nmat, double *S,
                           int64_t ld, const float *Lf, int64_t r0, int64_t krow, const float *Xf,
-                          int kofs, int64_t rows, int64_t ncols, int64_t col_shift);
+                          int kofs, int64_t rows, int64_t ncols, int64_t col_shift, bool bf16);
 // Lf = (float) A on the block-lower part (NB blocks at or below the diagonal)
 void launch_to_f32_lower(hipStream_t s, const Fields &F, const double *A, int64_t ld, int64_t npad,
                          float *Lf);

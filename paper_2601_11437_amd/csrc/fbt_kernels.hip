@@ -12,6 +12,7 @@
 #include "fbt_internal.h"
 
 #include <math.h>
+#include <type_traits>
 
 namespace fbt {
 
@@ -1076,6 +1077,81 @@ template <int WM, int WN, bool BKC> struct TileB {
     }
 };
 
+// TileB from the FP32 operand copies (A M-contiguous, B K-contiguous, as in
+// TileG): the floats are rounded to bfloat16 when staged, which gives the same
+// operands as TileB's rounding of the FP64 values through FP32, so the results
+// are bitwise TileB's.
+__device__ __forceinline__ unsigned short to_bf16f(float v)
+{
+    const unsigned int u = __float_as_uint(v);
+    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+template <int WM, int WN> struct TileBG {
+    using T = TileB<WM, WN, true>;
+    static constexpr int BM = T::BM, BN = T::BN, KC = T::KC, LK = T::LK, STAGE = T::STAGE;
+    static constexpr int LDS = T::LDS;
+    static constexpr int NA = BM * KC / 1024, NBL = BN * KC / 1024; // float4 loads per thread
+
+    __device__ static void store(const float4 *ra, const float4 *rb, unsigned short *st)
+    {
+        const int t = threadIdx.x;
+        unsigned short *As = st, *Bs = st + BM * LK;
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const int q = t + 256 * i, m4 = q % (BM / 4), k = q / (BM / 4);
+            As[(4 * m4) * LK + k] = to_bf16f(ra[i].x);
+            As[(4 * m4 + 1) * LK + k] = to_bf16f(ra[i].y);
+            As[(4 * m4 + 2) * LK + k] = to_bf16f(ra[i].z);
+            As[(4 * m4 + 3) * LK + k] = to_bf16f(ra[i].w);
+        }
+#pragma unroll
+        for (int i = 0; i < NBL; ++i) {
+            const int q = t + 256 * i, k4 = q % (KC / 4), nn = q / (KC / 4);
+            Bs[nn * LK + 4 * k4] = to_bf16f(rb[i].x);
+            Bs[nn * LK + 4 * k4 + 1] = to_bf16f(rb[i].y);
+            Bs[nn * LK + 4 * k4 + 2] = to_bf16f(rb[i].z);
+            Bs[nn * LK + 4 * k4 + 3] = to_bf16f(rb[i].w);
+        }
+    }
+    // C(BM x BN, FP64) -= A(BM x NB) * B(BN x NB)^T, one NB-deep slice
+    __device__ static void update_slice(double *C, int64_t ldc, const float *A, int64_t lda,
+                                        const float *B, int64_t ldb, unsigned short *lds)
+    {
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        const int wm = wave % WM, wn = wave / WM;
+        f4 acc[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
+        float4 ra[NA], rb[NBL];
+        TileG<WM, WN>::load(ra, rb, A, lda, B, ldb, 0);
+        store(ra, rb, lds);
+        __syncthreads();
+        constexpr int nch = NB / KC;
+        for (int c = 0; c < nch; ++c) {
+            if (c + 1 < nch)
+                TileG<WM, WN>::load(ra, rb, A, lda, B, ldb, (c + 1) * KC);
+            T::compute(acc, lds + (c & 1) * STAGE, wm, wn, lane);
+            if (c + 1 < nch)
+                store(ra, rb, lds + ((c + 1) & 1) * STAGE);
+            __syncthreads();
+        }
+        double *cb = C + (wm * 64 + (lane & 15)) + (int64_t)(wn * 64 + 4 * (lane >> 4)) * ldc;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                double *cc = cb + (int64_t)(16 * j + r) * ldc;
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    cc[16 * i] = cc[16 * i] - (double)acc[i][j][r];
+            }
+    }
+};
+
 // C -= A * B^T over the block-lower tiles of a trailing matrix of nblk x nblk
 // NB-blocks (128 x 128 tiles; both 128-tiles above the diagonal inside a
 // diagonal NB-block are included), depth K (one or two panels).  blockIdx.y
@@ -1336,13 +1412,16 @@ void launch_update_nn(hipStream_t s, const Fields &F, int64_t sS, int nmat, doub
 // FP32 form of the left-solve update from the FP32 copies (one NB-deep slice):
 // C = S[m0.., c0..] -= Lf[m0.., krow:krow+NB] * Xf[kofs.., c0..]^T, 128 x 128 tiles.
 // Bitwise the same as k_update_nn<1, NB> on the FP64 operands.
+template <bool BF>
 __global__ __launch_bounds__(256) void k_update_nn_f32(Fields F, int64_t sS, double *S, int64_t ld,
                                                        const float *Lf, int64_t r0, int64_t krow,
                                                        const float *Xf, int kofs,
                                                        int64_t half_tiles, int64_t col_shift)
 {
-    using TG = TileG<2, 2>;
-    __shared__ float lds[TG::LDS];
+    // BF: bfloat16 operands (TileB's rounding) instead of FP32
+    using TG = typename std::conditional<BF, TileBG<2, 2>, TileG<2, 2>>::type;
+    using E = typename std::conditional<BF, unsigned short, float>::type;
+    __shared__ E lds[TG::LDS];
     const int f = blockIdx.z; // field
     S += f * sS;
     Lf += f * F.sA;
@@ -1356,14 +1435,14 @@ __global__ __launch_bounds__(256) void k_update_nn_f32(Fields F, int64_t sS, dou
 
 void launch_update_nn_f32(hipStream_t s, const Fields &F, int64_t sS, int nmat, double *S,
                           int64_t ld, const float *Lf, int64_t r0, int64_t krow, const float *Xf,
-                          int kofs, int64_t rows, int64_t ncols, int64_t col_shift)
+                          int kofs, int64_t rows, int64_t ncols, int64_t col_shift, bool bf16)
 {
     const int64_t half = ncols / 128;
     if (rows <= 0 || half <= 0)
         return;
     const dim3 g((unsigned)(nmat * half), (unsigned)(rows / 128), F.count);
-    hipLaunchKernelGGL(k_update_nn_f32, g, dim3(256), 0, s, F, sS, S, ld, Lf, r0, krow, Xf, kofs,
-                       half, col_shift);
+    hipLaunchKernelGGL(bf16 ? k_update_nn_f32<true> : k_update_nn_f32<false>, g, dim3(256), 0, s, F,
+                       sS, S, ld, Lf, r0, krow, Xf, kofs, half, col_shift);
 }
 
 // Lf = (float) A on the NB blocks at or below the diagonal; blockIdx.x walks
