@@ -409,30 +409,38 @@ def main():
         ctx.loglik(theta)
     dt_ll = (time.perf_counter() - t1) / max(1, args.steps)
 
-    mixed = adjoint = None
+    mixed = mixed_bf16 = adjoint = None
     if not args.no_mixed:
-        # the mixed form (trace-phase updates on FP32 MFMA), same workload and steps
-        ctx.set_precision(fbt.MIXED_FP32)
-        for i in range(args.warmup):
-            ctx.eval(theta)
-        t2 = time.perf_counter()
-        for i in range(args.steps):
-            llm, scm, fim = ctx.eval(theta)
-        dt_mix = time.perf_counter() - t2
-        ctx.set_precision(fbt.FP64)
         tscale = ctx.eval_terms(theta)
         sscale = np.array([(tscale[1] + n) / (2 * theta[0]),
                            0.5 * (abs(tscale[2]) + abs(tscale[4])),
                            0.5 * (abs(tscale[3]) + abs(tscale[5]))])
         dd = np.sqrt(np.outer(np.diag(fisher), np.diag(fisher)))
-        mixed = {"precision": "trace-phase updates FP32 MFMA (FP32 accumulation); factorisation, "
-                              "log-det, solves of the diagonal blocks, Bessel terms and reductions FP64",
-                 "value": args.steps / dt_mix, "unit": "evals/s",
-                 "ms_per_step": 1e3 * dt_mix / args.steps, "speedup_vs_fp64": dt / dt_mix,
-                 "loglik_rel_err_vs_fp64": abs(llm - ll) / abs(ll),
-                 "score_err_per_term_vs_fp64": (np.abs(scm - score) / sscale).tolist(),
-                 "fisher_rel_err_vs_fp64": float(np.max(np.abs(fim - fisher) / dd))}
-        log("mixed: %.1f ms per step" % (1e3 * dt_mix / args.steps))
+
+        def mixed_form(prec, what):
+            # a mixed form, same workload and steps, with its errors against FP64
+            ctx.set_precision(prec)
+            for i in range(args.warmup):
+                ctx.eval(theta)
+            t2 = time.perf_counter()
+            for i in range(args.steps):
+                llm, scm, fim = ctx.eval(theta)
+            dt_mix = time.perf_counter() - t2
+            ctx.set_precision(fbt.FP64)
+            return {"precision": what, "value": args.steps / dt_mix, "unit": "evals/s",
+                    "ms_per_step": 1e3 * dt_mix / args.steps, "speedup_vs_fp64": dt / dt_mix,
+                    "loglik_rel_err_vs_fp64": abs(llm - ll) / abs(ll),
+                    "score_err_per_term_vs_fp64": (np.abs(scm - score) / sscale).tolist(),
+                    "fisher_rel_err_vs_fp64": float(np.max(np.abs(fim - fisher) / dd))}
+
+        mixed = mixed_form(fbt.MIXED_FP32,
+                           "trace-phase updates FP32 MFMA (FP32 accumulation); factorisation, log-det, "
+                           "solves of the diagonal blocks, Bessel terms and reductions FP64")
+        log("mixed: %.1f ms per step" % mixed["ms_per_step"])
+        mixed_bf16 = mixed_form(fbt.MIXED_BF16,
+                                "trace-phase updates with bfloat16 operands on MFMA (FP32 sums per "
+                                "256-deep slice); the rest as in the FP32 form; not a fitting form")
+        log("mixed bf16: %.1f ms per step" % mixed_bf16["ms_per_step"])
         # adjoint gradient (log-likelihood + score, no Fisher), FP64
         ctx.grad(theta)
         t3 = time.perf_counter()
@@ -487,6 +495,7 @@ def main():
         "loglik_only_evals_per_s": 1.0 / dt_ll,
         "phases": phases,
         "mixed": mixed,
+        "mixed_bf16": mixed_bf16,
         "adjoint_grad": adjoint,
         "result": {"loglik": ll, "score": score.tolist(), "fisher_diag": np.diag(fisher).tolist()},
     }
