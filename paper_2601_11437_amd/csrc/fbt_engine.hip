@@ -644,13 +644,13 @@ fbt_status wphase_enqueue(fbt_ctx *c)
     // mixed forms with their operand copies: the factor once, each solved pair of
     // block rows as the diagonal apply writes it (slot by pair parity, so the
     // next pair's rows never overwrite rows a running update still reads)
-    const bool f32 = mix != 0 && c->Lf && c->Xf;
+    const bool copies = mix != 0 && c->Lf && c->Xf;
     auto xslot = [&](int b) { return c->Xf + (size_t)((b / 2) & 1) * (2 * NB) * (2 * npad); };
-    if (f32)
+    if (copies)
         launch_to_f32_lower(s0, c->F, A, ld, npad, c->Lf);
     // left update of `rows` rows from r by the `kp` panels of pair b (K = kp NB)
     auto left_update = [&](hipStream_t st, int64_t r, int64_t rows, int b, int kp, int K) {
-        if (!f32) {
+        if (!copies) {
             launch_update_nn(st, c->F, c->F.sS2, 2, c->S2, ld, A, ld, r, (int64_t)b * NB, rows, ncols,
                              npad, K, mix);
             return;
@@ -678,13 +678,13 @@ fbt_status wphase_enqueue(fbt_ctx *c)
         const int K = nb * NB;
         TIMED(c, s0, KC_LAPPLY, 2.0 * dn * dNB * dNB,
               launch_diag_apply(s0, c->F, c->F.sS2, 2, c->S2, ld, r0, Lk(b), ncols, npad,
-                                f32 ? xslot(b) : nullptr, 0));
+                                copies ? xslot(b) : nullptr, 0));
         if (nb == 2) {
             TIMED(c, s0, KC_LUPD, 2.0 * real_rows(r0 + NB, NB) * dNB * 2.0 * dn,
                   left_update(s0, r0 + NB, NB, b, 1, NB));
             TIMED(c, s0, KC_LAPPLY, 2.0 * dn * dNB * dNB,
                   launch_diag_apply(s0, c->F, c->F.sS2, 2, c->S2, ld, r0 + NB, Lk(b + 1), ncols, npad,
-                                    f32 ? xslot(b) : nullptr, NB));
+                                    copies ? xslot(b) : nullptr, NB));
         }
         HIPCHK(c, hipEventRecord(c->evP, s0));
         if (rn >= npad)
