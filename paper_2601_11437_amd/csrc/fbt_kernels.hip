@@ -1304,7 +1304,8 @@ void launch_panel(hipStream_t s, const Fields &F, double *P, int64_t ld, int64_t
 // (in place; a workgroup owns all NB rows of 64 columns).  Column tile c maps
 // to column 64 c, shifted by col_shift past the first half (two right-hand
 // sides stored side by side; with one right-hand side only the first half is
-// launched).
+// launched).  With Xf (the mixed forms), the solved rows are also stored as
+// floats at Xf[(kofs + row) + col * 2 NB], the operand copy of the updates.
 __global__ __launch_bounds__(256) void k_diag_apply(Fields F, int64_t sS, double *S, int64_t ld,
                                                     int64_t krow, const double *Linv,
                                                     int64_t half_tiles, int64_t col_shift,
