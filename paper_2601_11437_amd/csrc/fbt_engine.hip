@@ -97,6 +97,11 @@ namespace {
 
 // CUs kept free of the factorisation's bulk stream: one per XCD of MI355X
 constexpr int FACT_CU_RESERVE = 8;
+// The factorisation steps one block column at a time over its last
+// FACT_SINGLE_TAIL blocks (two elsewhere): there the critical chain, not the
+// trailing update, bounds each step, and a 2 NB-deep lookahead update would
+// lengthen the chain (its time is per-workgroup latency, not throughput).
+constexpr int FACT_SINGLE_TAIL = 40;
 
 // node table followed by the paper-mode coefficient table (one upload)
 constexpr size_t TAB_BYTES = TAB_MAX * sizeof(Node) + PC_SIZE * sizeof(double);
@@ -497,15 +502,19 @@ fbt_status factorize_enqueue(fbt_ctx *c, const GenParams &gp, int mode)
     launch_init_info(s0, c->info, c->G);
     TIMED(c, s0, KC_GEN, 0.0, launch_gen(s0, gp, c->d_gpa, c->F, c->x, c->y, c->z, A, c->S2,
                                            c->S2 + npad * ld, mode));
-    // Block columns are taken in pairs (b, b + 1).  On s0: diagonal block b,
-    // panel b, update of block column b + 1 by panel b, diagonal block b + 1,
-    // panel b + 1.  The trailing matrix is then updated by both panels at once
-    // (K = 2 NB): s0 updates the next pair of block columns (lookahead) once
-    // s1 has finished the previous bulk update; s1 updates the rest.
+    // Block columns are taken in pairs (b, b + 1), and singly in the last
+    // FACT_SINGLE_TAIL blocks.  On s0: diagonal block b, panel b, update of
+    // block column b + 1 by panel b, diagonal block b + 1, panel b + 1.  The
+    // trailing matrix is then updated by the step's panels at once (K = nb NB):
+    // s0 updates the next step's block columns (lookahead) once s1 has finished
+    // the previous bulk update; s1 updates the rest.  A K = 2 NB update is the
+    // FMA sequence of two NB-deep ones (C lives in the accumulators), so the
+    // step widths do not change the results.
     auto rows_from = [&](int64_t r) { return (double)std::max<int64_t>(0, n - r); };
+    auto width = [&](int b) { return T - b <= FACT_SINGLE_TAIL ? 1 : std::min(2, T - b); };
     HIPCHK(c, hipEventRecord(c->evB, s0));
-    for (int b = 0; b < T; b += 2) {
-        const int nb = std::min(2, T - b);
+    for (int b = 0, nb = 1; b < T; b += nb) {
+        nb = width(b);
         const int64_t r0 = (int64_t)b * NB, rn = r0 + (int64_t)nb * NB;
         const int K = nb * NB;
         TIMED(c, s0, KC_DIAG, 2.0 * dNB * dNB * dNB / 3.0,
@@ -527,7 +536,8 @@ fbt_status factorize_enqueue(fbt_ctx *c, const GenParams &gp, int mode)
         HIPCHK(c, hipEventRecord(c->evP, s0));
         if (rn >= npad)
             break;
-        const int64_t la = std::min<int64_t>(2 * NB, npad - rn); // columns of the next pair
+        // columns of the next step
+        const int64_t la = std::min<int64_t>((int64_t)width(b + nb) * NB, npad - rn);
         HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
         TIMED(c, s0, KC_SYRK, 2.0 * rows_from(rn) * (double)la * K,
               launch_update_rect(s0, c->F, c->F.sA, c->F.sA, 1, A + rn + rn * ld, nullptr, ld, A + rn + r0 * ld, nullptr,
