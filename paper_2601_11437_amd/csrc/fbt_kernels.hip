@@ -38,9 +38,9 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c)
 //   C_nu    = sigma2 c_nu E ((log x - log 2 - psi(nu)) SK + SD)
 // The integrals use the trapezoid rule with step h_L = 0.2 / 2^L, where the
 // level L is the smallest with x <= 9 * 4^L (so h_L <= 0.6 / sqrt(x)), and
-// stop at the t where x (cosh t - 1) - (|nu| + 1) t reaches 45: beyond it the
-// integrands are below e^-45 of their value at t = 0.  At x = 0 the entry is
-// (sigma2, 0, 0).
+// stop past the t where x (cosh t - 1) - (|nu| + 1) t reaches 45 (an upper
+// bound of it): beyond it the integrands are below e^-45 of their value at
+// t = 0.  At x = 0 the entry is (sigma2, 0, 0).
 // ---------------------------------------------------------------------------
 constexpr int GT = 64; // generation tile (rows x cols)
 
@@ -114,12 +114,15 @@ __device__ __forceinline__ void matern3(const GenParams &gp, const Node *tab, do
     for (int l = 0; l < NLEV - 1; ++l)
         L += (x > gp.xtop[l]);
     const double h = gp.h[L];
-    // truncation point
+    // truncation point: the root t* of F(t) = x (cosh t - 1) - g t - 45.  The
+    // iterates t1 = acosh(1 + 45 / x), t2 = acosh(1 + (45 + g t1) / x) rise
+    // towards it with F(t2) = -g (t2 - t1), and beyond t2 the slope of F is at
+    // least x (cosh t2 - 1) - g = 45 + g t1 - g, so t2 + g (t2 - t1) / (45 - g)
+    // bounds t* from above (for g < 45; larger g falls back to the table's end)
     const double g = gp.abs_nu + 1.0;
-    double t = acosh_ge1(1.0 + 45.0 / x);
-#pragma unroll
-    for (int it = 0; it < 3; ++it)
-        t = acosh_ge1(1.0 + (45.0 + g * t) / x);
+    const double t1 = acosh_ge1(1.0 + 45.0 / x);
+    const double t2 = acosh_ge1(1.0 + (45.0 + g * t1) / x);
+    double t = g < 44.0 ? t2 + g * (t2 - t1) / (45.0 - g) : 1.0e4;
     t = fmin(t, 1.0e4); // x below ~1e-300: every node of the level
     int J = (int)(t / h) + 2;
     J = J < gp.len[L] ? J : gp.len[L];
