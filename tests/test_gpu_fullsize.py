@@ -91,6 +91,10 @@ def test_score_and_fisher_properties(big):
     ll2, score2, fisher2 = ctx.eval(theta)
     assert ll == ll2 and np.array_equal(score, score2) and np.array_equal(fisher, fisher2)
     assert ll == ctx.loglik(theta)
+    # right after that log-likelihood call the evaluation reuses its factor
+    # (only the derivative matrices are generated): bitwise the same numbers
+    ll3, score3, fisher3 = ctx.eval(theta)
+    assert ll3 == ll and np.array_equal(score3, score) and np.array_equal(fisher3, fisher)
     np.testing.assert_array_equal(fisher, fisher.T)
     assert fisher[0, 0] == n / (2 * theta[0] ** 2)
     assert np.all(np.linalg.eigvalsh(fisher) > 0)
