@@ -12,6 +12,7 @@ import argparse
 import json
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -131,8 +132,7 @@ def batch_bench(args):
         b.set_exec(fbt.Batch.GRAPH)
     elif args.batch_exec == "tuned":
         t0 = time.perf_counter()
-        path = os.path.join(ROOT, "gpurun_out", "batch_tuning.json")
-        os.makedirs(os.path.dirname(path), exist_ok=True)
+        path = os.path.join(tempfile.gettempdir(), "fisherbt_batch_tuning.json")
         b.autotune(thetas, fbt.Batch.EVAL, path)
         with open(path) as f:
             tune = json.load(f)
