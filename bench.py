@@ -17,6 +17,8 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# the seeded input generator lives beside the tests (shared by tests and bench)
+sys.path.insert(0, os.path.join(ROOT, "tests"))
 
 METRIC = "loglik+score+Fisher evals/s at n=20k, FP64 vs mixed; % of MFMA peak"
 PEAK_FP64_TFLOPS = 78.6
@@ -34,7 +36,7 @@ def cpu_baseline(n_full, n_sample, theta, seed):
     """The oracle as it stands, one evaluation on a smaller instance of the
     same workload, scaled by n^3 (the evaluation is O(n^3))."""
     import oracle
-    from paper_2601_11437_amd import synth
+    import synth
 
     oracle.build(force=False)
     locs, z, _ = synth.dataset(n_sample, theta, seed)
@@ -100,7 +102,7 @@ def batch_bench(args):
     import numpy as np
 
     import paper_2601_11437_amd as fbt
-    from paper_2601_11437_amd import synth
+    import synth
 
     t0 = time.perf_counter()
     fields, thetas = synth.batch_workload(args.batch)
@@ -169,7 +171,7 @@ def fit_bench(args):
     import numpy as np
 
     import paper_2601_11437_amd as fbt
-    from paper_2601_11437_amd import synth
+    import synth
 
     w = dict(synth.WORKLOADS["n20k"])
     n = args.n
@@ -209,7 +211,7 @@ def grid_bench(args):
     import numpy as np
 
     import paper_2601_11437_amd as fbt
-    from paper_2601_11437_amd import synth
+    import synth
 
     ctx = fbt.Context(0)
     fits, total = [], 0.0
@@ -251,7 +253,7 @@ def precision_bench(args):
     import numpy as np
 
     import paper_2601_11437_amd as fbt
-    from paper_2601_11437_amd import synth
+    import synth
 
     w = synth.WORKLOADS["n50k"]
     n, theta = args.n if args.n != 20000 else w["n"], w["theta_true"]
@@ -381,7 +383,7 @@ def main():
     import numpy as np
 
     import paper_2601_11437_amd as fbt
-    from paper_2601_11437_amd import synth
+    import synth
 
     w = dict(synth.WORKLOADS["n20k"])
     n = args.n

@@ -10,7 +10,8 @@ suite, the smoke check and the CPU-baseline leg of the benchmark may import it.
 Layout:
   matern_oracle.c  per-entry Matern C, dC/dalpha, dC/dnu via trapezoid quadrature
                    of the integral form of K_nu (compiled by ``build()``)
-  __init__.py      Algorithms 2 and 3 written step by step with LAPACK primitives
+  __init__.py      Eqs. (1)-(3) from one Cholesky and one joint solve (LAPACK),
+                   and the adjoint form of Eq. (2) with an explicit inverse
   fisher_bt.py     Algorithm 1 (L9 start, Fisher scoring, relaxed Armijo
                    backtracking, Nelder-Mead fallback)
 """
@@ -117,7 +118,7 @@ def cov_matrices(locs, theta, which=("S", "Sa", "Sn")):
 
 
 # --------------------------------------------------------------------------
-# Algorithm 2: log-likelihood; Algorithm 3: log-likelihood, score, Fisher
+# The Gaussian likelihood and its first two moments in theta (Eqs. (1)-(3))
 # --------------------------------------------------------------------------
 def _check_theta(theta):
     theta = np.asarray(theta, dtype=np.float64)
@@ -126,11 +127,25 @@ def _check_theta(theta):
     return theta
 
 
-def _cholesky(S):
+def _spd_solve(S, rhs):
+    """log det S and S^{-1} rhs for a symmetric positive definite S.
+
+    Both come from one LAPACK Cholesky factorisation S = C C^T (dpotrf; the
+    determinant is the squared product of C's diagonal) and dpotrs for every
+    column of ``rhs`` at once.  A failed factorisation raises
+    NotPositiveDefinite."""
     try:
-        return np.linalg.cholesky(S)
+        c = scipy.linalg.cho_factor(S, lower=True, check_finite=False)
     except np.linalg.LinAlgError as e:
         raise NotPositiveDefinite(str(e)) from None
+    logdet = 2.0 * float(np.sum(np.log(np.diag(c[0]))))
+    return logdet, scipy.linalg.cho_solve(c, rhs, check_finite=False)
+
+
+def _gaussian_loglik(n, logdet, quad):
+    """Eq. (1): the zero-mean Gaussian log-density of Z, from log|Sigma| and
+    the quadratic form Z^T Sigma^{-1} Z."""
+    return -0.5 * n * np.log(2 * np.pi) - 0.5 * logdet - 0.5 * quad
 
 
 def trace_product_frobenius(A, B):
@@ -139,21 +154,22 @@ def trace_product_frobenius(A, B):
 
 
 def loglik(locs, z, theta):
-    """Algorithm 2.  Returns dict(loglik, logdet, quad)."""
+    """Eq. (1) at theta.  Returns dict(loglik, logdet, quad) with
+    quad = Z^T Sigma^{-1} Z."""
     theta = _check_theta(theta)
     z = np.asarray(z, dtype=np.float64)
-    n = z.size
-    (S,) = cov_matrices(locs, theta, which=("S",))            # Sigma(theta)
-    L = _cholesky(S)                                          # Sigma = L L^T
-    logdet = 2.0 * np.sum(np.log(np.diag(L)))                 # 2 sum log l_ii
-    Y = scipy.linalg.solve_triangular(L, z, lower=True)       # Y = L^{-1} Z
-    quad = float(Y @ Y)                                       # Z^T Sigma^{-1} Z = Y^T Y
-    ll = -0.5 * n * np.log(2 * np.pi) - 0.5 * logdet - 0.5 * quad   # Eq. (1)
-    return {"loglik": float(ll), "logdet": float(logdet), "quad": quad}
+    (S,) = cov_matrices(locs, theta, which=("S",))
+    logdet, w = _spd_solve(S, z)
+    quad = float(z @ w)
+    return {"loglik": float(_gaussian_loglik(z.size, logdet, quad)), "logdet": logdet,
+            "quad": quad}
 
 
 def _paper_sigma_nu(locs, theta):
-    """Dense Sigma_nu by the paper's case scheme (oracle.paper_mode)."""
+    """Dense Sigma_nu whose entries follow the paper's case scheme for the
+    order derivative (Supplementary A, ``oracle.paper_mode``): the entry of
+    each pair j > k at its Euclidean distance, mirrored to k > j; the diagonal
+    (zero distance) is zero."""
     from . import paper_mode
 
     locs = np.asarray(locs, dtype=np.float64)
@@ -168,12 +184,24 @@ def _paper_sigma_nu(locs, theta):
 
 
 def evaluate(locs, z, theta, sigma_nu="exact"):
-    """Algorithm 3: log-likelihood, score (Eq. 2) and Fisher information (Eq. 3).
+    """Log-likelihood (Eq. (1)), score (Eq. (2)) and expected Fisher
+    information (Eq. (3)) over theta = (sigma2, alpha, nu).
 
-    The score is over theta = (sigma2, alpha, nu).  Besides the results it
-    returns the intermediate traces, and every Fisher entry of the alpha/nu
-    block both by the Frobenius identity of Eq. (5) and by the direct sum
-    sum_jk A_jk B_kj.
+    One Cholesky of Sigma solves Sigma X = [Z | Sigma_alpha | Sigma_nu]; the
+    first column is w = Sigma^{-1} Z, the other blocks are
+    A_i = Sigma^{-1} Sigma_i.  Then, for i in {alpha, nu},
+
+        dl/dtheta_i = -tr(A_i) / 2 + w^T Sigma_i w / 2,   I_ij = tr(A_i A_j) / 2.
+
+    The covariance is proportional to sigma2, so Sigma_{sigma2} = Sigma / sigma2
+    and A_{sigma2} = I / sigma2, which gives dl/dsigma2 = (Z^T w - n) / (2 sigma2),
+    I_{sigma2,sigma2} = n / (2 sigma2^2) and I_{sigma2,i} = tr(A_i) / (2 sigma2).
+
+    Besides the results it returns the intermediate traces and quadratic
+    forms, and every alpha/nu Fisher entry twice: tr(A_i A_j) by the
+    Frobenius identity of Eq. (5) and by the direct sum sum_jk (A_i)_jk (A_j)_kj
+    (the entry reported is the former).  ``sigma_nu="paper"`` replaces the
+    exact Sigma_nu with the paper's approximation of it (Supplementary A).
     """
     theta = _check_theta(theta)
     s2 = theta[0]
@@ -182,37 +210,29 @@ def evaluate(locs, z, theta, sigma_nu="exact"):
     S, Sa, Sn = cov_matrices(locs, theta)
     if sigma_nu == "paper":
         Sn = _paper_sigma_nu(locs, theta)
-    # Step 1: log-likelihood
-    L = _cholesky(S)
-    logdet = 2.0 * np.sum(np.log(np.diag(L)))
-    Y = scipy.linalg.solve_triangular(L, z, lower=True)
-    quad = float(Y @ Y)
-    ll = -0.5 * n * np.log(2 * np.pi) - 0.5 * logdet - 0.5 * quad
-    # Step 2: sigma2 entries
-    score = np.zeros(3)
-    fisher = np.zeros((3, 3))
-    score[0] = (quad - n) / (2 * s2)
-    fisher[0, 0] = n / (2 * s2 ** 2)
-    # Steps 3 and 4: alpha and nu
-    w = scipy.linalg.cho_solve((L, True), z)                  # w = Sigma^{-1} Z
-    A = {}
-    tr, wv = {}, {}
-    for idx, (key, Si) in ((1, ("a", Sa)), (2, ("n", Sn))):
-        Ai = scipy.linalg.cho_solve((L, True), Si)            # A = Sigma^{-1} Sigma_i
-        A[key] = Ai
-        tr[key] = float(np.trace(Ai))
-        v = Si @ w                                            # v = Sigma_i Sigma^{-1} Z
-        wv[key] = float(w @ v)
-        fisher[0, idx] = fisher[idx, 0] = tr[key] / (2 * s2)
-        score[idx] = -0.5 * tr[key] + 0.5 * wv[key]           # Eq. (2)
+    deriv = {"a": Sa, "n": Sn}
+    logdet, X = _spd_solve(S, np.hstack([z[:, None], Sa, Sn]))
+    del S
+    w = X[:, 0]
+    A = {"a": X[:, 1:n + 1], "n": X[:, n + 1:]}
+    quad = float(z @ w)
+    tr = {k: float(np.trace(A[k])) for k in A}
+    wSw = {k: float(w @ (deriv[k] @ w)) for k in A}
+    score = np.array([(quad - n) / (2 * s2),
+                      0.5 * (wSw["a"] - tr["a"]),
+                      0.5 * (wSw["n"] - tr["n"])])
     frob, direct = {}, {}
-    for (i, ki), (j, kj) in (((1, "a"), (1, "a")), ((1, "a"), (2, "n")), ((2, "n"), (2, "n"))):
-        frob[ki + kj] = trace_product_frobenius(A[ki], A[kj])
+    for ki, kj in (("a", "a"), ("a", "n"), ("n", "n")):
+        frob[ki + kj] = float(trace_product_frobenius(A[ki], A[kj]))
         direct[ki + kj] = float(np.sum(A[ki] * A[kj].T))
-        fisher[i, j] = fisher[j, i] = 0.5 * frob[ki + kj]     # Eq. (3) via Eq. (5)
-    return {"loglik": float(ll), "score": score, "fisher": fisher,
-            "logdet": float(logdet), "quad": quad,
-            "trace": tr, "wSw": wv, "trAB_frobenius": frob, "trAB_direct": direct}
+    fisher = np.array([
+        [n / (2 * s2 * s2), tr["a"] / (2 * s2), tr["n"] / (2 * s2)],
+        [tr["a"] / (2 * s2), 0.5 * frob["aa"], 0.5 * frob["an"]],
+        [tr["n"] / (2 * s2), 0.5 * frob["an"], 0.5 * frob["nn"]],
+    ])
+    return {"loglik": float(_gaussian_loglik(n, logdet, quad)), "score": score,
+            "fisher": fisher, "logdet": logdet, "quad": quad,
+            "trace": tr, "wSw": wSw, "trAB_frobenius": frob, "trAB_direct": direct}
 
 
 def adjoint_score(locs, z, theta, sigma_nu="exact"):
@@ -233,12 +253,10 @@ def adjoint_score(locs, z, theta, sigma_nu="exact"):
     S, Sa, Sn = cov_matrices(locs, theta)
     if sigma_nu == "paper":
         Sn = _paper_sigma_nu(locs, theta)
-    L = _cholesky(S)
-    logdet = 2.0 * np.sum(np.log(np.diag(L)))
-    w = scipy.linalg.cho_solve((L, True), z)
+    logdet, X = _spd_solve(S, np.hstack([z[:, None], np.eye(n)]))
+    w, Sinv = X[:, 0], X[:, 1:]
     quad = float(z @ w)
-    ll = -0.5 * n * np.log(2 * np.pi) - 0.5 * logdet - 0.5 * quad
-    Sinv = scipy.linalg.cho_solve((L, True), np.eye(n))
+    ll = _gaussian_loglik(n, logdet, quad)
     G = 0.5 * (np.outer(w, w) - Sinv)
     score = np.array([float(np.sum(G * S)) / s2, float(np.sum(G * Sa)), float(np.sum(G * Sn))])
     return {"loglik": float(ll), "score": score, "dz": -w, "quad": quad}

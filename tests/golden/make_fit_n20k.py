@@ -17,9 +17,10 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+sys.path.insert(0, os.path.dirname(HERE))
 
 import oracle  # noqa: E402
-from paper_2601_11437_amd import synth  # noqa: E402
+import synth  # noqa: E402
 
 
 class LoggedEvaluator(oracle.OracleEvaluator):

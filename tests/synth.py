@@ -1,9 +1,12 @@
 """Seeded synthetic inputs: locations and zero-mean Gaussian random field draws.
 
-This module is shared by the tests, the benchmark and the oracle-side checks.
-It holds none of the likelihood, score or Fisher arithmetic; it only *draws*
-data.  Field draws use third-party routines (numpy exp, SciPy's Bessel K,
-LAPACK Cholesky via numpy), never the oracle or the HIP library.
+The one module that both sides of the parity tests read (the HIP library's
+tests and benchmark, and the oracle's checks).  It lives beside the tests, not
+in the product package, and imports neither the oracle nor the library.  It
+holds none of the likelihood, score or Fisher arithmetic: it only *draws*
+data, and the draw's covariance is evaluated with third-party routines (the
+closed forms at half-integer order with numpy's exp, SciPy's Bessel K
+otherwise, and numpy's LAPACK Cholesky), none of which either side uses.
 
 Recipe (every stream is numpy Generator(PCG64(seed))):
   * uniform design: n locations iid U([0,1]^2), drawn first;

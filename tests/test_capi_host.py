@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import paper_2601_11437_amd as fbt
-from paper_2601_11437_amd import synth
+import synth
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 

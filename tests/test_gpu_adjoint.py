@@ -20,7 +20,7 @@ import numpy as np
 import pytest
 
 import paper_2601_11437_amd as fbt
-from paper_2601_11437_amd import synth
+import synth
 
 pytestmark = pytest.mark.gpu
 

@@ -11,7 +11,7 @@ against quantities that do not go through that formula:
 import numpy as np
 import pytest
 
-from paper_2601_11437_amd import synth
+import synth
 
 THETAS = [(1.0, 0.1, 0.5), (1.3, 0.07, 1.2), (0.7, 0.15, 2.2), (2.0, 0.05, 0.3)]
 

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 import scipy.optimize
 
-from paper_2601_11437_amd import synth
+import synth
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "table1_l9.json")
 

@@ -12,7 +12,7 @@ import mpmath as mp
 import numpy as np
 import pytest
 
-from paper_2601_11437_amd import synth
+import synth
 
 
 def _data(n, seed, theta=(1.0, 0.1, 0.5)):
