@@ -25,16 +25,43 @@ PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 # timing class -> kernel that implements it (for the counter summaries)
 DOMINANT_KERNEL = {"left_update": "k_update_nn", "cholesky_update": "k_update_lower",
-                   "right_update": "k_update_lower"}
+                   "right_update": "k_update_lower", "twosided_update": "k_syr2k_lower",
+                   "deferred_update": "k_update_nn"}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def host_info():
+    """CPU model and the thread counts the oracle runs with (OpenMP for its
+    C part, the BLAS behind numpy/SciPy for its LAPACK calls)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = None
+    try:
+        import threadpoolctl
+
+        blas = [{"api": i.get("internal_api"), "threads": i.get("num_threads")}
+                for i in threadpoolctl.threadpool_info()]
+    except Exception:  # threadpoolctl missing or failing: record nothing
+        blas = None
+    omp = os.environ.get("OMP_NUM_THREADS")
+    return {"cpu": model, "logical_cpus": os.cpu_count(),
+            "omp_threads": int(omp) if omp and omp.isdigit() else None, "blas": blas}
+
+
 def cpu_baseline(n_full, n_sample, theta, seed):
-    """The oracle as it stands, one evaluation on a smaller instance of the
-    same workload, scaled by n^3 (the evaluation is O(n^3))."""
+    """The oracle as it stands, one evaluation on a bounded sample of the same
+    workload (the same design and theta at a smaller n), scaled to the full n
+    by n^3 (the evaluation is O(n^3))."""
     import oracle
     import synth
 
@@ -43,12 +70,33 @@ def cpu_baseline(n_full, n_sample, theta, seed):
     t0 = time.perf_counter()
     oracle.evaluate(locs, z, theta)
     dt = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    host = host_info()
+    threads = host["omp_threads"] or host["logical_cpus"]
     return {"value": (1.0 / dt) * (n_sample / n_full) ** 3, "unit": "evals/s",
             "cores": threads, "kind": "oracle",
-            "sample": "one oracle evaluation at n=%d (uniform locations, theta=%s) took %.2f s; "
-                      "scaled by (%d/%d)^3 to n=%d" % (n_sample, list(theta), dt, n_sample, n_full,
-                                                       n_full)}
+            "sample": "one oracle evaluation at n=%d (uniform locations, theta=%s) took %.2f s on "
+                      "the host; scaled by (%d/%d)^3 to n=%d" % (n_sample, list(theta), dt, n_sample,
+                                                              n_full, n_full),
+            "sample_seconds": dt, "host": host}
+
+
+def cpu_full(args):
+    """One oracle evaluation at the full benchmark size (minutes of host
+    time), with the host's CPU model and thread counts."""
+    import oracle
+    import synth
+
+    w = dict(synth.WORKLOADS["n20k"])
+    oracle.build(force=False)
+    locs, z, _ = synth.dataset(args.n, w["theta_true"], w["seed"])
+    log("oracle evaluation at n=%d ..." % args.n)
+    t0 = time.perf_counter()
+    r = oracle.evaluate(locs, z, w["theta_true"])
+    dt = time.perf_counter() - t0
+    print(json.dumps({"what": "one oracle evaluation (Eqs. (1)-(3)) at n=%d, theta=%s"
+                              % (args.n, list(w["theta_true"])),
+                      "seconds": dt, "evals_per_s": 1.0 / dt, "loglik": r["loglik"],
+                      "host": host_info()}), flush=True)
 
 
 def kernel_source_sha256():
@@ -339,7 +387,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=20000)
-    ap.add_argument("--cpu-sample-n", type=int, default=4000)
+    ap.add_argument("--cpu-sample-n", type=int, default=8000,
+                    help="n of the oracle's timed sample (the CPU baseline)")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="only time one oracle evaluation at the full n on the host")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision and adjoint comparisons (profiling runs)")
@@ -375,6 +426,9 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
+    if args.cpu_full:
+        cpu_full(args)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the single-field evaluation is not sharded "
               "across GPUs in this build (see the design notes); use --gpus 1", file=sys.stderr)
@@ -405,11 +459,21 @@ def main():
     dt = time.perf_counter() - t0
     tim = ctx.timing()
     ctx.set_timing(False)
-    # loglik-only rate (Algorithm 2), for context
+    # loglik-only rate (Algorithm 2): generation of Sigma and the Cholesky phase
     t1 = time.perf_counter()
     for i in range(max(1, args.steps)):
         ctx.loglik(theta)
     dt_ll = (time.perf_counter() - t1) / max(1, args.steps)
+    # the W phase alone: a derivative evaluation right after a log-likelihood
+    # call at the same theta reuses its factor (generation of the derivative
+    # matrices, the W phase and the trace reductions)
+    dt_w = 0.0
+    for i in range(max(1, args.steps)):
+        ctx.loglik(theta)
+        t1 = time.perf_counter()
+        ctx.eval_terms(theta)
+        dt_w += time.perf_counter() - t1
+    dt_w /= max(1, args.steps)
 
     mixed = mixed_bf16 = adjoint = None
     if not args.no_mixed:
@@ -475,6 +539,30 @@ def main():
                 "flops_per_launch": d["flops"] / d["launches"]}
     total_fl = sum(v["flops"] for v in tim.values())
     total_ms = sum(v["ms"] for v in tim.values())
+    # fractions of the FP64 peak per phase: algorithmic flops (n^3 / 3 for the
+    # Cholesky phase, 2 n^3 for the W phase of both derivative matrices,
+    # 7 n^3 / 3 for the evaluation) and the flops the kernels execute
+    ms_step = 1e3 * dt / args.steps
+    two_sided = tim.get("twosided_update", {}).get("launches", 0) > 0
+    w_exec = 2.0 * n ** 3 if two_sided else 8.0 * n ** 3 / 3.0
+
+    def frac(fl, ms):
+        return {"tflops": fl / (ms * 1e-3) / 1e12, "frac_fp64_peak": fl / (ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS}
+
+    phase_fracs = {
+        "whole_eval": dict(ms=ms_step, algorithmic_flops=7.0 * n ** 3 / 3.0,
+                           executed_flops=n ** 3 / 3.0 + w_exec,
+                           algorithmic=frac(7.0 * n ** 3 / 3.0, ms_step),
+                           executed=frac(n ** 3 / 3.0 + w_exec, ms_step)),
+        "cholesky_phase": dict(ms=1e3 * dt_ll, algorithmic_flops=n ** 3 / 3.0,
+                               note="fbt_loglik: generation of Sigma, factorisation, log det, "
+                                    "forward solve", algorithmic=frac(n ** 3 / 3.0, 1e3 * dt_ll)),
+        "w_phase": dict(ms=1e3 * dt_w, algorithmic_flops=2.0 * n ** 3, executed_flops=w_exec,
+                        form="two-sided reduction" if two_sided else "block solves",
+                        note="derivative evaluation on the log-likelihood call's factor: "
+                             "generation of Sigma_alpha and Sigma_nu, W phase, trace reductions",
+                        algorithmic=frac(2.0 * n ** 3, 1e3 * dt_w), executed=frac(w_exec, 1e3 * dt_w)),
+    }
     out = {
         "metric": METRIC,
         "value": evals_per_s,
@@ -494,6 +582,7 @@ def main():
         "roofline": roofline,
         "whole_eval_tflops": total_fl / (total_ms * 1e-3) / 1e12 if total_ms else None,
         "fp64_frac_whole_eval": total_fl / dt / 1e12 / PEAK_FP64_TFLOPS,
+        "phase_fractions": phase_fracs,
         "loglik_only_evals_per_s": 1.0 / dt_ll,
         "phases": phases,
         "mixed": mixed,

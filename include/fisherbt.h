@@ -200,7 +200,9 @@ void fbt_fit_options_default(fbt_fit_options *o);
  * relaxed Armijo backtracking of Eq. (4), stop at ||grad|| <= grad_tol, shift
  * to Nelder-Mead when a call budget is exceeded, then one Fisher evaluation
  * at the result.  Every l and derivative evaluation runs on the GPU.
- * Errors: FBT_EINVAL, FBT_ENODATA, FBT_ENOTPD (every L9 candidate failed),
+ * Errors: FBT_EINVAL (also for a context in FBT_MIXED_FP32_ALL: its
+ * log-likelihood is not the FP64 one that the acceptance tests of Eq. (4)
+ * take), FBT_ENODATA, FBT_ENOTPD (every L9 candidate failed),
  * FBT_EBUDGET (budget exhausted with nelder_mead = 0; *out still holds the
  * last iterate), FBT_EDEVICE. */
 fbt_status fbt_fit(fbt_ctx *ctx, const fbt_fit_options *opt, fbt_fit_result *out);
@@ -314,6 +316,24 @@ fbt_status fbt_batch_load_tuning(fbt_batch *b, const char *path);
 typedef enum { FBT_SIGMA_NU_EXACT = 0, FBT_SIGMA_NU_PAPER = 1 } fbt_sigma_nu_mode;
 fbt_status fbt_set_sigma_nu_mode(fbt_ctx *ctx, int32_t mode);
 
+/* Form of the W phase of fbt_eval / fbt_eval_terms / fbt_fit: the matrices
+ * W_i = L^{-1} Sigma_i L^{-T}, i in {alpha, nu}, whose traces and Frobenius
+ * products give the score and Fisher information (Eqs. (2), (3), (5)).
+ *   FBT_WPHASE_TWO_SIDED (default): a blocked two-sided reduction.  Per block
+ *     step k it forms W_kk = L_kk^{-1} S_kk L_kk^{-T}, Y = S_ik L_kk^{-T} - L_ik W_kk / 2
+ *     and M = Y - L_ik W_kk / 2, updates the trailing lower blocks by
+ *     S -= Y L^T + L Y^T, and solves L^{-1} M for the blocks below the
+ *     diagonal after the last step: n^3 flops per matrix.  FP64 only.
+ *   FBT_WPHASE_SOLVES: the left block solve X_i = L^{-1} Sigma_i followed by
+ *     the lower half of X_i L^{-T} (4 n^3 / 3 flops per matrix).  The mixed
+ *     precisions (fbt_precision) always take this form.
+ * Both forms give the same nine terms up to rounding.  If the two-sided
+ * form's extra device memory (about 32 NB n_pad + 16 NB^2 (n_pad / NB) bytes,
+ * NB = 256) cannot be allocated, the evaluation takes the block solves.
+ * Errors: FBT_EINVAL (NULL context or unknown form). */
+typedef enum { FBT_WPHASE_TWO_SIDED = 0, FBT_WPHASE_SOLVES = 1 } fbt_wphase;
+fbt_status fbt_set_wphase(fbt_ctx *ctx, int32_t form);
+
 /* Per-kernel-class timing with HIP events recorded on the context's stream.
  * enable != 0 starts recording (and clears the counters); 0 stops it. */
 fbt_status fbt_set_timing(fbt_ctx *ctx, int32_t enable);
@@ -321,7 +341,10 @@ fbt_status fbt_set_timing(fbt_ctx *ctx, int32_t enable);
  * 3 trailing Cholesky update, 4 left-solve diagonal apply, 5 left-solve update,
  * 6 right-solve panel with trace reductions, 7 right-solve update, 8 reductions,
  * 9 inverse of the factor (adjoint), 10 X^T X product (adjoint),
- * 11 adjoint fill / extraction / contraction with the regenerated derivatives.
+ * 11 adjoint fill / extraction / contraction with the regenerated derivatives,
+ * 12 two-sided W phase: diagonal blocks, 13 its panels (Y, M), 14 its symmetric
+ * rank-2k trailing updates, 15 its deferred solve's diagonal apply, 16 the
+ * deferred solve's updates, 17 its rank-2k updates of the next block columns.
  * Returns launches, summed milliseconds and summed algorithmic flops of the
  * class since timing was enabled (timing must have been enabled). */
 fbt_status fbt_get_timing(fbt_ctx *ctx, int32_t kernel_class, int64_t *launches, double *ms,

@@ -21,7 +21,9 @@ OK, EINVAL, ENOTPD, ENOMEM, EDEVICE, ENONFINITE, EBUDGET, ENODATA = 0, -1, -2, -
 # kernel classes of fbt_get_timing
 KERNEL_CLASSES = ("generation", "diag_factor_inverse", "panel_solve", "cholesky_update",
                   "left_diag_apply", "left_update", "right_panel_reduce", "right_update",
-                  "reductions", "adjoint_inverse", "adjoint_xtx", "adjoint_contraction")
+                  "reductions", "adjoint_inverse", "adjoint_xtx", "adjoint_contraction",
+                  "twosided_diag", "twosided_panel", "twosided_update", "deferred_diag_apply",
+                  "deferred_update", "twosided_lookahead")
 
 _lib = None
 _d = ctypes.c_double
@@ -56,6 +58,7 @@ class Config(ctypes.Structure):
 
 FP64, MIXED_FP32, MIXED_FP32_ALL, MIXED_BF16 = 0, 1, 2, 3
 SIGMA_NU_EXACT, SIGMA_NU_PAPER = 0, 1
+WPHASE_TWO_SIDED, WPHASE_SOLVES = 0, 1
 
 
 class Evaluator(ctypes.Structure):
@@ -84,6 +87,7 @@ SIGNATURES = {
     "fbt_last_notpd_pivot": (_i64, [_p]),
     "fbt_grad": (ctypes.c_int, [_p, _p, _p, _p, _p]),
     "fbt_set_sigma_nu_mode": (ctypes.c_int, [_p, _i32]),
+    "fbt_set_wphase": (ctypes.c_int, [_p, _i32]),
     "fbt_batch_create": (ctypes.c_int, [ctypes.POINTER(Config), _i32, ctypes.POINTER(_p)]),
     "fbt_batch_destroy": (None, [_p]),
     "fbt_batch_set_fields": (ctypes.c_int, [_p, _i32, _p, _p, _p]),
@@ -344,6 +348,13 @@ class Context:
         """SIGMA_NU_EXACT (0, default) or SIGMA_NU_PAPER (1: the case scheme of
         Supplementary A for dSigma/dnu)."""
         self._check(lib().fbt_set_sigma_nu_mode(self._h, int(mode)))
+
+    def set_wphase(self, form: int):
+        """WPHASE_TWO_SIDED (0, default: blocked two-sided reduction, n^3 flops
+        per derivative matrix, FP64) or WPHASE_SOLVES (1: left block solve and
+        lower-half right solve, 4 n^3 / 3 per matrix; the mixed precisions
+        always take it) for the W phase of the following evaluations."""
+        self._check(lib().fbt_set_wphase(self._h, int(form)))
 
     def set_timing(self, enable: bool):
         self._check(lib().fbt_set_timing(self._h, 1 if enable else 0))

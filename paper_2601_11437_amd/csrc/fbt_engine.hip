@@ -17,12 +17,18 @@ using namespace fbt;
 
 namespace {
 
-constexpr int NCLASS = 12;
+constexpr int NCLASS = 18;
 enum KClass {
     KC_GEN, KC_DIAG, KC_PANEL, KC_SYRK, KC_LAPPLY, KC_LUPD, KC_RPANEL, KC_RUPD, KC_RED,
     KC_INV,   // adjoint: X = L'^{-1} (diagonal apply and updates)
     KC_LAUUM, // adjoint: P = X^T X
-    KC_ADJ    // adjoint: contraction with the regenerated derivatives
+    KC_ADJ,   // adjoint: contraction with the regenerated derivatives
+    KC_SDIAG, // two-sided W phase: diagonal blocks W_kk
+    KC_SPANEL,// two-sided W phase: panels Y, M
+    KC_SUPD,  // two-sided W phase: symmetric rank-2k trailing updates
+    KC_DAPPLY,// two-sided W phase: deferred solve, diagonal apply
+    KC_DUPD,  // two-sided W phase: deferred solve, updates
+    KC_SLOOK  // two-sided W phase: rank-2k updates of the next block columns (lookahead)
 };
 
 struct Timed {
@@ -39,6 +45,8 @@ struct fbt_ctx {
     hipStream_t stream2 = nullptr; // s1: bulk trailing updates (lookahead), joined back to s0
     hipStream_t stream3 = nullptr; // s1 of the factorisation: bulk updates on all CUs but a reserve
     hipEvent_t evP = nullptr, evB = nullptr;
+    hipStream_t stream4 = nullptr; // two-sided W phase: the deferred solve's critical path
+    hipEvent_t evP2 = nullptr, evB2 = nullptr, evD = nullptr; // its chain, bulk and end
     bool own_stream = false;
     int precision = FBT_FP64; // see fbt_precision
     int sigma_nu_mode = FBT_SIGMA_NU_EXACT;
@@ -65,6 +73,14 @@ struct fbt_ctx {
     // the FP64 operands when staging, with bitwise the same results)
     float *Lf = nullptr, *Xf = nullptr;
     size_t cap_lf = 0, cap_xf = 0;
+    // W phase by the two-sided reduction (FBT_WPHASE_TWO_SIDED, FP64): Y of the
+    // current pair of block steps (two slots by pair parity, both matrices,
+    // npad x 2 NB each), V_k = -W_kk / 2 of every step (both matrices, T NB^2
+    // each) and the diagonal kernel's scratch (2 NB^2); allocated at the first
+    // evaluation in that form
+    int wphase = FBT_WPHASE_TWO_SIDED;
+    double *Ysl = nullptr, *Vd = nullptr, *Pd = nullptr;
+    size_t cap_ysl = 0, cap_vd = 0, cap_pd = 0;
 
     // fields held: 1 for the single-field API; G >= 1 inside a batched group
     int G = 1;
@@ -273,6 +289,12 @@ GenParams setup_theta(fbt_ctx *c, const double *th, int f, int64_t n)
     return gp;
 }
 
+// ---- ordering between the critical-path and bulk streams ----
+// A context whose streams are all one stream needs no events (they are then
+// null): its launches are ordered by the stream itself.
+hipError_t ev_record(hipEvent_t e, hipStream_t s) { return e ? hipEventRecord(e, s) : hipSuccess; }
+hipError_t ev_wait(hipStream_t s, hipEvent_t e) { return e ? hipStreamWaitEvent(s, e, 0) : hipSuccess; }
+
 // ---- timing helpers: HIP events around each launch on the launch's stream ----
 void tbegin(fbt_ctx *c, hipStream_t st, hipEvent_t *a, hipEvent_t *b)
 {
@@ -344,6 +366,56 @@ void free_buffers(fbt_ctx *c)
     c->Lf = nullptr;
     c->Xf = nullptr;
     c->cap_lf = c->cap_xf = 0;
+    (void)hipFree(c->Ysl);
+    (void)hipFree(c->Vd);
+    (void)hipFree(c->Pd);
+    c->Ysl = c->Vd = c->Pd = nullptr;
+    c->cap_ysl = c->cap_vd = c->cap_pd = 0;
+}
+
+// Buffer sizes of the two-sided W phase per field (doubles)
+int64_t sy_stride(const fbt_ctx *c) { return (int64_t)2 * 2 * c->npad * (2 * NB); }
+int64_t vd_stride(const fbt_ctx *c) { return (int64_t)2 * c->T * NB * NB; }
+int64_t pd_stride() { return (int64_t)2 * NB * NB; }
+
+// The two-sided W phase's buffers for the current fields; false if they
+// cannot be allocated (the W phase then takes the block solves).
+bool ensure_sygst(fbt_ctx *c)
+{
+    struct {
+        double **p;
+        size_t *cap;
+        size_t bytes;
+    } req[] = {{&c->Ysl, &c->cap_ysl, (size_t)c->G * sy_stride(c) * 8},
+               {&c->Vd, &c->cap_vd, (size_t)c->G * vd_stride(c) * 8},
+               {&c->Pd, &c->cap_pd, (size_t)c->G * pd_stride() * 8}};
+    for (auto &r : req) {
+        if (r.bytes <= *r.cap)
+            continue;
+        (void)hipFree(*r.p);
+        *r.p = nullptr;
+        *r.cap = 0;
+        if (hipMalloc((void **)r.p, r.bytes) != hipSuccess) {
+            *r.p = nullptr;
+            (void)hipGetLastError();
+            return false;
+        }
+        *r.cap = r.bytes;
+    }
+    return true;
+}
+
+// The W phase takes the two-sided reduction in FP64 when selected and its
+// buffers exist (allocated here unless `may_alloc` is false); the mixed
+// precisions take the block solves.
+bool use_two_sided(fbt_ctx *c, bool may_alloc = true)
+{
+    if (c->wphase != FBT_WPHASE_TWO_SIDED || c->precision != FBT_FP64)
+        return false;
+    if (may_alloc)
+        return ensure_sygst(c);
+    return c->cap_ysl >= (size_t)c->G * sy_stride(c) * 8 &&
+           c->cap_vd >= (size_t)c->G * vd_stride(c) * 8 && c->cap_pd >= (size_t)c->G * pd_stride() * 8;
 }
 
 // The FP32 copies for the current fields (FBT_MIXED_FP32 and FBT_MIXED_BF16).  A failed
@@ -512,7 +584,7 @@ fbt_status factorize_enqueue(fbt_ctx *c, const GenParams &gp, int mode)
     // step widths do not change the results.
     auto rows_from = [&](int64_t r) { return (double)std::max<int64_t>(0, n - r); };
     auto width = [&](int b) { return T - b <= FACT_SINGLE_TAIL ? 1 : std::min(2, T - b); };
-    HIPCHK(c, hipEventRecord(c->evB, s0));
+    HIPCHK(c, ev_record(c->evB, s0));
     for (int b = 0, nb = 1; b < T; b += nb) {
         nb = width(b);
         const int64_t r0 = (int64_t)b * NB, rn = r0 + (int64_t)nb * NB;
@@ -533,25 +605,25 @@ fbt_status factorize_enqueue(fbt_ctx *c, const GenParams &gp, int mode)
                 TIMED(c, s0, KC_PANEL, rows_from(rn) * dNB * dNB,
                       launch_panel(s0, c->F, A + rn + r1 * ld, ld, npad - rn, Lk(b + 1)));
         }
-        HIPCHK(c, hipEventRecord(c->evP, s0));
+        HIPCHK(c, ev_record(c->evP, s0));
         if (rn >= npad)
             break;
         // columns of the next step
         const int64_t la = std::min<int64_t>((int64_t)width(b + nb) * NB, npad - rn);
-        HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
+        HIPCHK(c, ev_wait(s0, c->evB));
         TIMED(c, s0, KC_SYRK, 2.0 * rows_from(rn) * (double)la * K,
               launch_update_rect(s0, c->F, c->F.sA, c->F.sA, 1, A + rn + rn * ld, nullptr, ld, A + rn + r0 * ld, nullptr,
                                  ld, A + rn + r0 * ld, ld, npad - rn, la, K, mix));
-        HIPCHK(c, hipStreamWaitEvent(s1, c->evP, 0));
+        HIPCHK(c, ev_wait(s1, c->evP));
         const int64_t t0 = rn + la;
         if (t0 < npad)
             TIMED(c, s1, KC_SYRK, rows_from(t0) * rows_from(t0) * K,
                   launch_update_lower(s1, c->F, c->F.sA, c->F.sA, 1, A + t0 + t0 * ld, nullptr, ld, A + t0 + r0 * ld,
                                       nullptr, ld, A + t0 + r0 * ld, ld, (int)((npad - t0) / NB), K,
                                       mix));
-        HIPCHK(c, hipEventRecord(c->evB, s1));
+        HIPCHK(c, ev_record(c->evB, s1));
     }
-    HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
+    HIPCHK(c, ev_wait(s0, c->evB));
     TIMED(c, s0, KC_RED, 0.0, launch_reduce_loglik(s0, c->F, A, ld, n, T, c->logdet, c->out));
     HIPCHK(c, hipMemcpyAsync(c->h_out, c->out, (size_t)c->G * 16 * sizeof(double),
                              hipMemcpyDeviceToHost, s0));
@@ -610,6 +682,7 @@ bool same_theta(const fbt_ctx *c, const double *th)
 }
 
 fbt_status wphase_enqueue(fbt_ctx *c);
+fbt_status wphase_sygst_enqueue(fbt_ctx *c);
 fbt_status wphase_results(fbt_ctx *c, double *terms);
 
 // W phase of Algorithm 3 on a valid factor: out[0..8] (see fbt_eval_terms).
@@ -630,9 +703,14 @@ fbt_status derivative_terms(fbt_ctx *c, const double *th, double terms[9])
         return st;
     }
     c->factor_valid = false; // reuse is for one derivative evaluation only
-    ensure_f32(c);
-    if ((st = wphase_enqueue(c)) != FBT_OK)
-        return st;
+    if (use_two_sided(c)) {
+        if ((st = wphase_sygst_enqueue(c)) != FBT_OK)
+            return st;
+    } else {
+        ensure_f32(c);
+        if ((st = wphase_enqueue(c)) != FBT_OK)
+            return st;
+    }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     tcollect(c);
     return wphase_results(c, terms);
@@ -681,7 +759,7 @@ fbt_status wphase_enqueue(fbt_ctx *c)
     auto real_rows = [&](int64_t r, int64_t cnt) {
         return (double)std::max<int64_t>(0, std::min<int64_t>(n - r, cnt));
     };
-    HIPCHK(c, hipEventRecord(c->evB, s0));
+    HIPCHK(c, ev_record(c->evB, s0));
     for (int b = 0; b < T; b += 2) {
         const int nb = std::min(2, T - b);
         const int64_t r0 = (int64_t)b * NB, rn = r0 + (int64_t)nb * NB;
@@ -696,20 +774,20 @@ fbt_status wphase_enqueue(fbt_ctx *c)
                   launch_diag_apply(s0, c->F, c->F.sS2, 2, c->S2, ld, r0 + NB, Lk(b + 1), ncols, npad,
                                     copies ? xslot(b) : nullptr, NB));
         }
-        HIPCHK(c, hipEventRecord(c->evP, s0));
+        HIPCHK(c, ev_record(c->evP, s0));
         if (rn >= npad)
             break;
         const int64_t la = std::min<int64_t>(2 * NB, npad - rn); // rows of the next pair
-        HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
+        HIPCHK(c, ev_wait(s0, c->evB));
         TIMED(c, s0, KC_LUPD, 2.0 * real_rows(rn, la) * K * 2.0 * dn,
               left_update(s0, rn, la, b, nb, K));
-        HIPCHK(c, hipStreamWaitEvent(s1, c->evP, 0));
+        HIPCHK(c, ev_wait(s1, c->evP));
         if (rn + la < npad)
             TIMED(c, s1, KC_LUPD, 2.0 * real_rows(rn + la, npad) * K * 2.0 * dn,
                   left_update(s1, rn + la, npad - rn - la, b, nb, K));
-        HIPCHK(c, hipEventRecord(c->evB, s1));
+        HIPCHK(c, ev_record(c->evB, s1));
     }
-    HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
+    HIPCHK(c, ev_wait(s0, c->evB));
 
     // Right solve W = X L'^{-T} (block-lower) with the fused reductions, block
     // columns in pairs as in the factorisation: on s0 the panel of block b
@@ -717,7 +795,7 @@ fbt_status wphase_enqueue(fbt_ctx *c)
     // the panel of block b + 1; then the lookahead update of the next pair of
     // block columns by both panels (K = 2 NB) on s0 and the rest on s1.
     int64_t groups = 0;
-    HIPCHK(c, hipEventRecord(c->evB, s0));
+    HIPCHK(c, ev_record(c->evB, s0));
     for (int b = 0; b < T; b += 2) {
         const int nb = std::min(2, T - b);
         const int64_t r0 = (int64_t)b * NB, rn = r0 + (int64_t)nb * NB;
@@ -739,17 +817,17 @@ fbt_status wphase_enqueue(fbt_ctx *c)
                                       c->partials + 8 * groups));
             groups += (npad - r1) / 64;
         }
-        HIPCHK(c, hipEventRecord(c->evP, s0));
+        HIPCHK(c, ev_record(c->evP, s0));
         if (rn >= npad)
             break;
         const int64_t la = std::min<int64_t>(2 * NB, npad - rn);
         const double mn = std::max<int64_t>(0, n - rn);
-        HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
+        HIPCHK(c, ev_wait(s0, c->evB));
         TIMED(c, s0, KC_RUPD, 2.0 * 2.0 * mn * (double)la * K,
               launch_update_rect(s0, c->F, c->F.sS2, c->F.sA, 2, Sa + rn + rn * ld, Sn + rn + rn * ld, ld,
                                  Sa + rn + r0 * ld, Sn + rn + r0 * ld, ld, A + rn + r0 * ld, ld,
                                  npad - rn, la, K, mix));
-        HIPCHK(c, hipStreamWaitEvent(s1, c->evP, 0));
+        HIPCHK(c, ev_wait(s1, c->evP));
         const int64_t t0 = rn + la;
         const double mt = std::max<int64_t>(0, n - t0);
         if (t0 < npad)
@@ -757,10 +835,147 @@ fbt_status wphase_enqueue(fbt_ctx *c)
                   launch_update_lower(s1, c->F, c->F.sS2, c->F.sA, 2, Sa + t0 + t0 * ld, Sn + t0 + t0 * ld, ld,
                                       Sa + t0 + r0 * ld, Sn + t0 + r0 * ld, ld, A + t0 + r0 * ld,
                                       ld, (int)((npad - t0) / NB), K, mix));
-        HIPCHK(c, hipEventRecord(c->evB, s1));
+        HIPCHK(c, ev_record(c->evB, s1));
     }
-    HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
+    HIPCHK(c, ev_wait(s0, c->evB));
     TIMED(c, s0, KC_RED, 0.0, launch_reduce_terms(s0, c->F, c->partials, groups, c->out));
+    HIPCHK(c, hipMemcpyAsync(c->h_out, c->out, (size_t)c->G * 16 * sizeof(double),
+                             hipMemcpyDeviceToHost, s0));
+    return FBT_OK;
+}
+
+// W phase of Algorithm 3 by the two-sided reduction (see the kernels): block
+// steps k = 0..T-1 over both derivative matrices form W_kk, Y and M of block
+// column k and update the trailing lower blocks by Y L^T + L Y^T; the deferred
+// left solve W_strict = L'^{-1} M (block row r over columns < r NB) follows
+// them one pair of block rows behind; then the trace reductions over the
+// block-lower part.  Both take steps in pairs with one step of lookahead on a
+// chain and a bulk stream, as the factorisation: on the chain the steps of the
+// pair (b, b + 1) and the update of the next pair's block columns (rows) once
+// the previous bulk update has finished; on the bulk stream the rest of the
+// trailing update by both steps at once.  Y of a pair goes to the slot of its
+// parity, so a pair's chain never overwrites Y that the previous pair's bulk
+// update still reads.
+fbt_status wphase_sygst_enqueue(fbt_ctx *c)
+{
+    hipStream_t s0 = c->stream, s1 = c->stream2;
+    const int64_t npad = c->npad, ld = c->ld, n = c->n;
+    const int T = c->T;
+    double *S2 = c->S2, *A = c->A;
+    const int64_t mofs = npad * ld;
+    const int64_t sY = sy_stride(c), ymofs = npad * (2 * NB), ldy = npad;
+    const int64_t sVd = vd_stride(c), vofs = (int64_t)T * NB * NB, sPd = pd_stride();
+    const double dNB = NB;
+    auto Lk = [&](int k) { return c->Linv + (size_t)k * NB * NB; };
+    auto Vk = [&](int k) { return c->Vd + (size_t)k * NB * NB; };
+    auto slot = [&](int b) { return c->Ysl + (size_t)((b / 2) & 1) * (2 * npad * (2 * NB)); };
+    auto real = [&](int64_t r, int64_t cnt) {
+        return (double)std::max<int64_t>(0, std::min<int64_t>(n - r, cnt));
+    };
+    auto diag = [&](int k) {
+        TIMED(c, s0, KC_SDIAG, 4.0 * dNB * dNB * dNB,
+              launch_sygst_diag(s0, c->F, S2, ld, mofs, (int64_t)k * NB, Lk(k), c->Pd, sPd, Vk(k),
+                                vofs, sVd));
+    };
+    // panel of step k on rows [r, npad), Y to the slot columns at Y
+    auto panel = [&](int k, int64_t r, double *Y) {
+        if (r < npad)
+            TIMED(c, s0, KC_SPANEL, 6.0 * real(r, npad) * dNB * dNB,
+                  launch_sygst_panel(s0, c->F, S2, ld, mofs, A, r, npad - r, (int64_t)k * NB, Lk(k),
+                                     Vk(k), vofs, sVd, Y, ldy, ymofs, sY));
+    };
+    // rows [r, npad) x cols [q, q + w) by the KS / NB steps from block kb (Y of their slot)
+    auto rect = [&](int64_t r, int64_t q, int64_t w, int kb, int KS, const double *Y) {
+        if (r < npad && w > 0)
+            TIMED(c, s0, KC_SLOOK, 2.0 * 2.0 * 2.0 * real(r, npad) * real(q, w) * KS,
+                  launch_syr2k_rect(s0, c->F, S2, ld, mofs, A, r, npad - r, q, w, (int64_t)kb * NB,
+                                    KS, Y, ldy, ymofs, sY));
+    };
+
+    // The deferred solve of block rows (b, b + 1) needs their M complete, i.e.
+    // the block steps up to b + 1, and their diagonal blocks spent (zeroed
+    // here; they are W_kk's S_kk).  Its rows and columns never meet the block
+    // steps that follow (those write columns >= (b + 2) NB, it writes columns
+    // < (b + 1) NB), so it runs one pair behind the block steps on streams of
+    // its own (chain sd, bulk sdb): its launches fill the block steps' gaps and
+    // the other way round.  Its bulk stream is the factorisation's (all CUs but
+    // one per XCD); a capturable context has none and shares s1.
+    hipStream_t sd = c->stream4, sdb = c->capturable ? c->stream2 : c->stream3;
+    auto deferred_pair = [&](int b) -> fbt_status {
+        const int nb = std::min(2, T - b);
+        const int64_t r0 = (int64_t)b * NB, rn = r0 + (int64_t)nb * NB;
+        HIPCHK(c, ev_wait(sd, c->evP));
+        launch_zero_diag_blocks(sd, c->F, S2, ld, mofs, b, nb);
+        TIMED(c, sd, KC_DAPPLY, 2.0 * dNB * dNB * real(0, r0),
+              launch_diag_apply(sd, c->F, c->F.sS2, 2, S2, ld, r0, Lk(b), r0, npad));
+        if (nb == 2) {
+            TIMED(c, sd, KC_DUPD, 2.0 * 2.0 * real(r0 + NB, NB) * dNB * real(0, r0),
+                  launch_update_nn(sd, c->F, c->F.sS2, 2, S2, ld, A, ld, r0 + NB, r0, NB, r0, npad,
+                                   NB, 0));
+            TIMED(c, sd, KC_DAPPLY, 2.0 * dNB * dNB * real(0, r0 + NB),
+                  launch_diag_apply(sd, c->F, c->F.sS2, 2, S2, ld, r0 + NB, Lk(b + 1), r0 + NB,
+                                    npad));
+        }
+        HIPCHK(c, ev_record(c->evP2, sd));
+        if (rn >= npad)
+            return FBT_OK;
+        // the pair's rows hold W over columns < (b + nb - 1) NB (block row b's
+        // diagonal block is zero)
+        const int64_t cols = (int64_t)(b + nb - 1) * NB;
+        const int K = nb * NB;
+        const int64_t la = std::min<int64_t>(2 * NB, npad - rn);
+        HIPCHK(c, ev_wait(sd, c->evB2));
+        TIMED(c, sd, KC_DUPD, 2.0 * 2.0 * real(rn, la) * K * real(0, cols),
+              launch_update_nn(sd, c->F, c->F.sS2, 2, S2, ld, A, ld, rn, r0, la, cols, npad, K, 0));
+        HIPCHK(c, ev_wait(sdb, c->evP2));
+        if (rn + la < npad)
+            TIMED(c, sdb, KC_DUPD, 2.0 * 2.0 * real(rn + la, npad) * K * real(0, cols),
+                  launch_update_nn(sdb, c->F, c->F.sS2, 2, S2, ld, A, ld, rn + la, r0,
+                                   npad - rn - la, cols, npad, K, 0));
+        HIPCHK(c, ev_record(c->evB2, sdb));
+        return FBT_OK;
+    };
+
+    // ---- block steps, and the deferred solve one pair behind ----
+    HIPCHK(c, ev_record(c->evB, s0));
+    HIPCHK(c, ev_record(c->evB2, s0));
+    fbt_status st = FBT_OK;
+    for (int b = 0; b < T; b += 2) {
+        const int nb = std::min(2, T - b);
+        const int64_t r0 = (int64_t)b * NB, r1 = r0 + NB, rn = r0 + (int64_t)nb * NB;
+        double *Y = slot(b);
+        diag(b);
+        panel(b, r1, Y);
+        if (nb == 2) {
+            rect(r1, r1, NB, b, NB, Y);
+            diag(b + 1);
+            panel(b + 1, rn, Y + NB * ldy);
+        }
+        HIPCHK(c, ev_record(c->evP, s0));
+        if (rn < npad) {
+            const int KS = nb * NB;
+            const int64_t la = std::min<int64_t>(2 * NB, npad - rn); // columns of the next pair
+            HIPCHK(c, ev_wait(s0, c->evB));
+            rect(rn, rn, la, b, KS, Y);
+            HIPCHK(c, ev_wait(s1, c->evP));
+            const int64_t t0 = rn + la;
+            if (t0 < npad)
+                TIMED(c, s1, KC_SUPD, 2.0 * 2.0 * real(t0, npad) * real(t0, npad) * KS,
+                      launch_syr2k_lower(s1, c->F, S2, ld, mofs, A, t0, (int)((npad - t0) / NB), r0,
+                                         KS, Y, ldy, ymofs, sY, 0));
+            HIPCHK(c, ev_record(c->evB, s1));
+        }
+        if ((st = deferred_pair(b)) != FBT_OK)
+            return st;
+    }
+    HIPCHK(c, ev_wait(s0, c->evB));
+    HIPCHK(c, ev_record(c->evD, sd));
+    HIPCHK(c, ev_wait(s0, c->evD));
+    HIPCHK(c, ev_wait(s0, c->evB2));
+    TIMED(c, s0, KC_RED, 0.0,
+          launch_sygst_reduce(s0, c->F, S2, ld, mofs, c->Vd, vofs, sVd, T, n, c->partials));
+    TIMED(c, s0, KC_RED, 0.0,
+          launch_reduce_terms(s0, c->F, c->partials, (int64_t)T * (T + 1) / 2, c->out));
     HIPCHK(c, hipMemcpyAsync(c->h_out, c->out, (size_t)c->G * 16 * sizeof(double),
                              hipMemcpyDeviceToHost, s0));
     return FBT_OK;
@@ -822,24 +1037,24 @@ fbt_status adjoint_terms(fbt_ctx *c, const double *th, double g[2])
     TIMED(c, s0, KC_ADJ, 0.0, launch_fill_identity(s0, X, ld, npad, ncols));
     TIMED(c, s0, KC_INV, 2.0 * dNB * dNB * (double)cols(0),
           launch_diag_apply(s0, c->F, c->F.sS2, 1, X, ld, 0, Lk(0), cols(0), 0));
-    HIPCHK(c, hipEventRecord(c->evP, s0));
-    HIPCHK(c, hipEventRecord(c->evB, s0));
+    HIPCHK(c, ev_record(c->evP, s0));
+    HIPCHK(c, ev_record(c->evB, s0));
     for (int k = 0; k + 1 < T; ++k) {
         const int64_t kc = (int64_t)k * NB, r1 = kc + NB, r2 = r1 + NB;
         const int64_t ck = cols(k);
-        HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
+        HIPCHK(c, ev_wait(s0, c->evB));
         TIMED(c, s0, KC_INV, 2.0 * dNB * dNB * (double)ck,
               launch_update_nn(s0, c->F, c->F.sS2, 1, X, ld, A, ld, r1, kc, NB, ck, 0, NB, 0));
         TIMED(c, s0, KC_INV, 2.0 * dNB * dNB * (double)cols(k + 1),
               launch_diag_apply(s0, c->F, c->F.sS2, 1, X, ld, r1, Lk(k + 1), cols(k + 1), 0));
-        HIPCHK(c, hipStreamWaitEvent(s1, c->evP, 0));
+        HIPCHK(c, ev_wait(s1, c->evP));
         if (k + 2 < T)
             TIMED(c, s1, KC_INV, 2.0 * (double)(npad - r2) * dNB * (double)ck,
                   launch_update_nn(s1, c->F, c->F.sS2, 1, X, ld, A, ld, r2, kc, npad - r2, ck, 0, NB, 0));
-        HIPCHK(c, hipEventRecord(c->evB, s1));
-        HIPCHK(c, hipEventRecord(c->evP, s0));
+        HIPCHK(c, ev_record(c->evB, s1));
+        HIPCHK(c, ev_record(c->evP, s0));
     }
-    HIPCHK(c, hipStreamWaitEvent(s0, c->evB, 0));
+    HIPCHK(c, ev_wait(s0, c->evB));
     {
         // flops of the block-lower 128-tiles below ncols: sum over tiles of 2 128^2 (npad - m0)
         double fl = 0.0;
@@ -970,6 +1185,7 @@ fbt_status fbt::group_prepare(fbt_ctx *c, int G, const int64_t *n, const double 
     if (st != FBT_OK)
         return st;
     ensure_f32(c);
+    (void)use_two_sided(c); // its buffers, if that form is selected (group_enqueue allocates nothing)
     c->nf.assign(n, n + G);
     std::vector<double> xs((size_t)G * npad, 0.0), ys((size_t)G * npad, 0.0), zs((size_t)G * npad, 0.0);
     for (int f = 0; f < G; ++f)
@@ -1015,7 +1231,9 @@ fbt_status fbt::group_enqueue(fbt_ctx *c, int mode)
         return st;
     if ((st = factorize_enqueue(c, c->h_gpa[0], mode == 1 ? GEN_SIGMA : GEN_ALL)) != FBT_OK)
         return st;
-    return mode == 2 ? wphase_enqueue(c) : FBT_OK;
+    if (mode != 2)
+        return FBT_OK;
+    return use_two_sided(c, false) ? wphase_sygst_enqueue(c) : wphase_enqueue(c);
 }
 
 // Per-field outputs once the enqueued evaluation has completed.
@@ -1177,7 +1395,11 @@ fbt_status fbt_create(const fbt_config *cfg, fbt_ctx **out)
     }
     if (hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->evP, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->evB, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&c->evB, hipEventDisableTiming) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->stream4, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->evP2, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->evB2, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->evD, hipEventDisableTiming) != hipSuccess) {
         fbt_destroy(c);
         return FBT_EDEVICE;
     }
@@ -1213,6 +1435,13 @@ void fbt_destroy(fbt_ctx *c)
         (void)hipEventDestroy(c->evP);
     if (c->evB)
         (void)hipEventDestroy(c->evB);
+    for (hipEvent_t e : {c->evP2, c->evB2, c->evD})
+        if (e)
+            (void)hipEventDestroy(e);
+    if (c->stream4) {
+        (void)hipStreamSynchronize(c->stream4);
+        (void)hipStreamDestroy(c->stream4);
+    }
     if (c->own_stream && c->stream)
         (void)hipStreamDestroy(c->stream);
     delete c;
@@ -1350,6 +1579,14 @@ fbt_status fbt_set_precision(fbt_ctx *ctx, int32_t precision)
         (precision == FBT_MIXED_FP32_ALL || ctx->precision == FBT_MIXED_FP32_ALL))
         ctx->factor_valid = false;
     ctx->precision = precision;
+    return FBT_OK;
+}
+
+fbt_status fbt_set_wphase(fbt_ctx *ctx, int32_t form)
+{
+    if (!ctx || (form != FBT_WPHASE_TWO_SIDED && form != FBT_WPHASE_SOLVES))
+        return fail(ctx, FBT_EINVAL, "unknown W-phase form");
+    ctx->wphase = form;
     return FBT_OK;
 }
 

@@ -385,6 +385,11 @@ fbt_status fbt_fit(fbt_ctx *ctx, const fbt_fit_options *opt, fbt_fit_result *out
     if (!ctx || !opt || !(opt->mixed_switch >= 0))
         return FBT_EINVAL;
     const int32_t prec = fbt::ctx_precision(ctx);
+    // The line search's acceptance tests (Eq. (4)) take FP64 log-likelihoods;
+    // under FBT_MIXED_FP32_ALL fbt_loglik carries FP32 rounding of the
+    // factorisation, which no refinement of the solves removes.
+    if (prec == FBT_MIXED_FP32_ALL)
+        return FBT_EINVAL;
     GpuFit g = {ctx, prec == FBT_FP64, opt->mixed_switch, 0, 0, 0, -1};
     fbt_evaluator ev = {&g, gpu_loglik, gpu_eval};
     const fbt_status s = fbt_fit_evaluator(&ev, opt, out);

@@ -119,6 +119,29 @@ void launch_reduce_loglik(hipStream_t s, const Fields &F, const double *A, int64
                           int64_t n, int T, const double *logdet_part, double *out);
 void launch_reduce_terms(hipStream_t s, const Fields &F, const double *partials, int64_t count,
                          double *out);
+// two-sided reduction of the W phase (see fbt_kernels.hip).  Both derivative
+// matrices: matrix 1 at +mofs (S2), +vofs (Vd), +ymofs (Y); per-field strides
+// sPd, sVd, sY (Pd, Vd, Y), F.sS2 (S2), F.sA (A), F.sLinv, F.sPart.
+void launch_sygst_diag(hipStream_t s, const Fields &F, const double *S2, int64_t ld, int64_t mofs,
+                       int64_t krow, const double *Linv, double *Pd, int64_t sPd, double *Vd,
+                       int64_t vofs, int64_t sVd);
+void launch_sygst_panel(hipStream_t s, const Fields &F, double *S2, int64_t ld, int64_t mofs,
+                        const double *A, int64_t r0, int64_t rows, int64_t krow,
+                        const double *Linv, const double *Vd, int64_t vofs, int64_t sVd,
+                        double *Y, int64_t ldy, int64_t ymofs, int64_t sY);
+// (the blocks among the first `skip` block rows of the trailing part are left out)
+void launch_syr2k_lower(hipStream_t s, const Fields &F, double *S2, int64_t ld, int64_t mofs,
+                        const double *A, int64_t t0, int nblk, int64_t kcol, int KS,
+                        const double *Y, int64_t ldy, int64_t ymofs, int64_t sY, int skip);
+void launch_syr2k_rect(hipStream_t s, const Fields &F, double *S2, int64_t ld, int64_t mofs,
+                       const double *A, int64_t r0, int64_t rows, int64_t c0, int64_t ncol,
+                       int64_t kcol, int KS, const double *Y, int64_t ldy, int64_t ymofs,
+                       int64_t sY);
+void launch_zero_diag_blocks(hipStream_t s, const Fields &F, double *S2, int64_t ld, int64_t mofs,
+                             int k0, int count);
+void launch_sygst_reduce(hipStream_t s, const Fields &F, const double *S2, int64_t ld,
+                         int64_t mofs, const double *Vd, int64_t vofs, int64_t sVd, int T,
+                         int64_t n, double *partials);
 // adjoint gradient
 void launch_fill_identity(hipStream_t s, double *X, int64_t ld, int64_t rows, int64_t ncols);
 void launch_lauum(hipStream_t s, double *P, const double *X, int64_t ld, int64_t npad,

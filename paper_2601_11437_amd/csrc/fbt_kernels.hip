@@ -1648,6 +1648,338 @@ void launch_reduce_terms(hipStream_t s, const Fields &F, const double *partials,
 }
 
 // ---------------------------------------------------------------------------
+// Two-sided reduction W_i = L^{-1} Sigma_i L^{-T} (the W phase of Algorithm 3
+// with n^3 flops per derivative matrix instead of the 4 n^3 / 3 of a left
+// solve followed by a lower-half right solve).  With L = [[L11, 0], [L21, L22]]
+// (L11 one NB-block) and S = Sigma_i partitioned alike, L W L^T = S gives
+//   W11 = L11^{-1} S11 L11^{-T},
+//   L22 W21 = M21 = S21 L11^{-T} - L21 W11,
+//   L22 W22 L22^T = S22 - Y21 L21^T - L21 Y21^T,  Y21 = S21 L11^{-T} - L21 W11 / 2,
+// so one block step forms W11, Y21 and M21 and applies a symmetric rank-2 NB
+// update to the trailing S22 (only its lower blocks are kept); the solves
+// L22^{-1} M21 of all steps are deferred.  Since M21 of step k is zero above
+// block row k + 1, they are one left solve W_strict = L^{-1} M of the
+// block-strictly-lower matrix M, whose block row r has nonzeros in columns
+// < r NB only (n^3 / 3 flops per matrix; the steps cost 2 n^3 / 3).
+// Storage: M replaces S's strictly lower blocks; V_k = -W_kk / 2 (full,
+// exactly symmetric) goes to a separate NB x NB block per step; Y of the
+// current pair of steps to a slot of npad x 2 NB per matrix.
+// ---------------------------------------------------------------------------
+
+// Diagonal block of step k for both matrices (blockIdx.y): with P = S_kk Linv_k^T
+// (scratch Pd, NB x NB per matrix), W_kk = Linv_k P; stores V = -W_kk / 2,
+// its lower triangle and the mirror of it, so V is exactly symmetric.  A
+// workgroup forms 64 columns of P and then the same 64 columns of W.
+__global__ __launch_bounds__(256) void k_sygst_diag(Fields F, const double *S2, int64_t ld,
+                                                    int64_t mofs, int64_t krow,
+                                                    const double *Linv, double *Pd,
+                                                    int64_t sPd, double *Vd, int64_t vofs,
+                                                    int64_t sVd)
+{
+    using TA = Tile<4, 1, false>;
+    using TB = Tile<4, 1, true>;
+    static_assert(TA::LDS == TB::LDS, "one LDS buffer for both products");
+    __shared__ double lds[TA::LDS];
+    const int m = blockIdx.y, f = blockIdx.z; // matrix, field
+    const int c0 = 64 * blockIdx.x;
+    const double *S = S2 + f * F.sS2 + m * mofs + krow + krow * ld;
+    Linv += f * F.sLinv;
+    double *P = Pd + f * sPd + m * (NB * NB);
+    double *V = Vd + f * sVd + m * vofs;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    d4 acc[4][4];
+    TA::zero(acc);
+    // P[:, c0 + j] = S_kk Linv[c0 + j, :]^T: row c0 + j of Linv vanishes past column c0 + j
+    TA::run(acc, S, ld, Linv + c0, NB, c0 + 64, lds);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                P[TA::row(i, lane, wave) + (int64_t)(c0 + TA::col(j, r, lane, 0)) * NB] = acc[i][j][r];
+    // the other waves read these columns of P below
+    __threadfence();
+    __syncthreads();
+    TB::zero(acc);
+    // W[:, c0 + j] = Linv P[:, c0 + j]: rows 64 wave.. of Linv vanish past column 64 wave + 63
+    TB::run(acc, Linv, NB, P + (int64_t)c0 * NB, NB, NB, lds, 4 * (wave + 1));
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int a = TB::row(i, lane, wave), b = c0 + TB::col(j, r, lane, 0);
+                if (a >= b) {
+                    const double v = -0.5 * acc[i][j][r];
+                    V[a + b * NB] = v;
+                    if (a != b)
+                        V[b + a * NB] = v;
+                }
+            }
+}
+
+void launch_sygst_diag(hipStream_t s, const Fields &F, const double *S2, int64_t ld, int64_t mofs,
+                       int64_t krow, const double *Linv, double *Pd, int64_t sPd, double *Vd,
+                       int64_t vofs, int64_t sVd)
+{
+    hipLaunchKernelGGL(k_sygst_diag, dim3(NB / 64, 2, F.count), dim3(256), 0, s, F, S2, ld, mofs,
+                       krow, Linv, Pd, sPd, Vd, vofs, sVd);
+}
+
+// Panel of step k, rows r0.., both matrices: with P = S[rows, k] Linv_k^T and
+// Q = L[rows, k] W_kk,
+//   Y = P - Q / 2 -> the slot (ld ldy),  M = P - Q -> in place of S[rows, k].
+// A workgroup owns 128 full rows of the block column (blockIdx.x: row tile,
+// y: matrix + 2 field) and forms them as two 128 x 128 tiles with the tile
+// engine of the bulk updates.  The right tile (columns 128..255) goes first:
+// its P reads S over all 256 columns, the left tile's only over columns
+// 0..127, so each tile's M can be stored in place as soon as it is formed.
+// -Q / 2 = L V is formed first and parked in the slot, where the lane that
+// stored it reads it back (program order) after P has been added.
+__global__ __launch_bounds__(256) void k_sygst_panel(Fields F, double *S2, int64_t ld,
+                                                        int64_t mofs, const double *A, int64_t r0,
+                                                        int64_t krow, const double *Linv,
+                                                        const double *Vd, int64_t vofs,
+                                                        int64_t sVd, double *Y, int64_t ldy,
+                                                        int64_t ymofs, int64_t sY)
+{
+    using TL = Tile<2, 2, false>;
+    __shared__ double lds[TL::LDS];
+    const int m = blockIdx.y & 1, f = blockIdx.y >> 1; // matrix, field
+    const int64_t mr = r0 + 128 * (int64_t)blockIdx.x;
+    double *S = S2 + f * F.sS2 + m * mofs + mr + krow * ld;
+    const double *Lp = A + f * F.sA + mr + krow * ld;
+    Linv += f * F.sLinv;
+    const double *V = Vd + f * sVd + m * vofs;
+    double *Yp = Y + f * sY + m * ymofs + mr;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wm = wave % 2, wn = wave / 2;
+#pragma unroll 1
+    for (int ct = 1; ct >= 0; --ct) {
+        const int c0 = 128 * ct;
+        d4 acc[4][4];
+        TL::zero(acc);
+        TL::run(acc, Lp, ld, V + c0, NB, NB, lds); // -Q / 2 (V symmetric)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    Yp[TL::row(i, lane, wm) + (int64_t)(c0 + TL::col(j, r, lane, wn)) * ldy] =
+                        acc[i][j][r];
+        // += S Linv^T over columns c0..: row c0 + j of Linv vanishes past column
+        // c0 + j, so the tile needs depth c0 + 128 and the wave's 64 columns
+        // depth c0 + 64 (wn + 1)
+        TL::run(acc, S, ld, Linv + c0, NB, c0 + 128, lds, (c0 + 64 * (wn + 1)) / 16);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int a = TL::row(i, lane, wm), b = c0 + TL::col(j, r, lane, wn);
+                    const double y = acc[i][j][r], h = Yp[a + (int64_t)b * ldy];
+                    S[a + (int64_t)b * ld] = y + h;
+                    Yp[a + (int64_t)b * ldy] = y;
+                }
+    }
+}
+
+void launch_sygst_panel(hipStream_t s, const Fields &F, double *S2, int64_t ld, int64_t mofs,
+                        const double *A, int64_t r0, int64_t rows, int64_t krow,
+                        const double *Linv, const double *Vd, int64_t vofs, int64_t sVd,
+                        double *Y, int64_t ldy, int64_t ymofs, int64_t sY)
+{
+    if (rows <= 0)
+        return;
+    hipLaunchKernelGGL(k_sygst_panel, dim3((unsigned)(rows / 128), 2 * F.count), dim3(256), 0, s,
+                       F, S2, ld, mofs, A, r0, krow, Linv, Vd, vofs, sVd, Y, ldy, ymofs, sY);
+}
+
+// C -= Y L^T + L Y^T on one 128 x 128 tile at (m0, n0) of matrix m: the
+// symmetric update by the KS / NB steps whose Y fill slot columns 0..KS and
+// whose factor columns start at kcol.  The two products are accumulated
+// one after the other onto C (held in the accumulators), so a tile is read and
+// written once for a 2 KS-deep update.
+template <int KS>
+__device__ __forceinline__ void syr2k_tile(double *C, int64_t ld, const double *Ym, int64_t ldy,
+                                           const double *L, int64_t kcol, int64_t m0, int64_t n0,
+                                           double *lds)
+{
+    using TL = Tile<2, 2, false, true>;
+    d4 acc[4][4];
+    TL::load_c(acc, C + m0 + n0 * ld, ld);
+    // one copy of the main loop for both products (two inlined copies cost
+    // registers and the second workgroup per CU)
+#pragma unroll 1
+    for (int q = 0; q < 2; ++q) {
+        const double *Aq = q ? L + m0 + kcol * ld : Ym + m0;
+        const double *Bq = q ? Ym + n0 : L + n0 + kcol * ld;
+        TL::run(acc, Aq, q ? ld : ldy, Bq, q ? ldy : ld, KS, lds);
+    }
+    TL::store_c(acc, C + m0 + n0 * ld, ld);
+}
+
+// over the block-lower tiles of the trailing nblk x nblk blocks from t0
+// (both 128-tiles above the diagonal inside a diagonal NB-block included),
+// block pairs (I, J) in row-major order from the p0-th on (p0 = skip (skip + 1)
+// / 2 leaves out the blocks among the first `skip` block rows)
+template <int KS>
+__global__ __launch_bounds__(256) void k_syr2k_lower(Fields F, double *S2, int64_t ld,
+                                                     int64_t mofs, const double *A, int64_t t0,
+                                                     int64_t kcol, const double *Y, int64_t ldy,
+                                                     int64_t ymofs, int64_t sY, int64_t p0)
+{
+    __shared__ double lds[Tile<2, 2, false, true>::LDS];
+    const int64_t p = p0 + (blockIdx.x >> 2);
+    const int s = blockIdx.x & 3;
+    int64_t I = (int64_t)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+    while ((I + 1) * (I + 2) / 2 <= p)
+        ++I;
+    while (I * (I + 1) / 2 > p)
+        --I;
+    const int64_t J = p - I * (I + 1) / 2;
+    const int64_t m0 = t0 + I * NB + 128 * (s >> 1), n0 = t0 + J * NB + 128 * (s & 1);
+    const int m = blockIdx.y & 1, f = blockIdx.y >> 1; // matrix, field
+    syr2k_tile<KS>(S2 + f * F.sS2 + m * mofs, ld, Y + f * sY + m * ymofs, ldy, A + f * F.sA, kcol,
+                   m0, n0, lds);
+}
+
+// on a rectangle of rows x ncol from (r0, c0) (lookahead of the next block columns)
+template <int KS>
+__global__ __launch_bounds__(256) void k_syr2k_rect(Fields F, double *S2, int64_t ld, int64_t mofs,
+                                                    const double *A, int64_t r0, int64_t c0,
+                                                    int64_t kcol, const double *Y, int64_t ldy,
+                                                    int64_t ymofs, int64_t sY)
+{
+    __shared__ double lds[Tile<2, 2, false, true>::LDS];
+    const int64_t m0 = r0 + 128 * (int64_t)blockIdx.x, n0 = c0 + 128 * (int64_t)blockIdx.y;
+    const int m = blockIdx.z & 1, f = blockIdx.z >> 1; // matrix, field
+    syr2k_tile<KS>(S2 + f * F.sS2 + m * mofs, ld, Y + f * sY + m * ymofs, ldy, A + f * F.sA, kcol,
+                   m0, n0, lds);
+}
+
+void launch_syr2k_lower(hipStream_t s, const Fields &F, double *S2, int64_t ld, int64_t mofs,
+                        const double *A, int64_t t0, int nblk, int64_t kcol, int KS,
+                        const double *Y, int64_t ldy, int64_t ymofs, int64_t sY, int skip)
+{
+    if (nblk <= skip || (KS != NB && KS != 2 * NB))
+        return;
+    // block pairs with I < skip come first in the enumeration: start past them
+    const int64_t first = (int64_t)skip * (skip + 1) / 2;
+    const int64_t pairs = (int64_t)nblk * (nblk + 1) / 2;
+    const dim3 g((unsigned)(4 * (pairs - first)), (unsigned)(2 * F.count));
+    hipLaunchKernelGGL(KS == NB ? k_syr2k_lower<NB> : k_syr2k_lower<2 * NB>, g, dim3(256),
+                       0, s, F, S2, ld, mofs, A, t0, kcol, Y, ldy, ymofs, sY, first);
+}
+
+void launch_syr2k_rect(hipStream_t s, const Fields &F, double *S2, int64_t ld, int64_t mofs,
+                       const double *A, int64_t r0, int64_t rows, int64_t c0, int64_t ncol,
+                       int64_t kcol, int KS, const double *Y, int64_t ldy, int64_t ymofs,
+                       int64_t sY)
+{
+    if (rows <= 0 || ncol <= 0 || (KS != NB && KS != 2 * NB))
+        return;
+    const dim3 g((unsigned)(rows / 128), (unsigned)(ncol / 128), (unsigned)(2 * F.count));
+    hipLaunchKernelGGL(KS == NB ? k_syr2k_rect<NB> : k_syr2k_rect<2 * NB>, g, dim3(256), 0, s, F,
+                       S2, ld, mofs, A, r0, c0, kcol, Y, ldy, ymofs, sY);
+}
+
+// Zero the NB x NB diagonal blocks k0, k0 + 1, .. of both matrices (blockIdx.x
+// = block, y = matrix, z = field): after their block steps they hold spent
+// S_kk, and the deferred solve reads block row k over columns up to (k + 1) NB.
+__global__ __launch_bounds__(256) void k_zero_diag_blocks(Fields F, double *S2, int64_t ld,
+                                                          int64_t mofs, int kfirst)
+{
+    const int64_t k0 = (int64_t)(kfirst + blockIdx.x) * NB;
+    double *B = S2 + blockIdx.z * F.sS2 + blockIdx.y * mofs + k0 + k0 * ld;
+    for (int c = 0; c < NB; ++c)
+        B[threadIdx.x + c * ld] = 0.0;
+}
+
+void launch_zero_diag_blocks(hipStream_t s, const Fields &F, double *S2, int64_t ld, int64_t mofs,
+                             int k0, int count)
+{
+    if (count <= 0)
+        return;
+    hipLaunchKernelGGL(k_zero_diag_blocks, dim3((unsigned)count, 2, F.count), dim3(256), 0, s, F,
+                       S2, ld, mofs, k0);
+}
+
+// Trace reductions of the two-sided form over the block-lower NB-blocks
+// (I >= J, one workgroup each, thread t on row t of the block): W is V_k * -2
+// on a diagonal block (stored in full) and the deferred solve's result below
+// it.  Over entries (a, b) with a, b < n:
+//   t_i = sum W_i[a][a],  F_ij = sum w_ab W_i[a][b] W_j[a][b]
+// with w_ab = 1 in a diagonal block and 2 below it, and u_i = W_i[n][n]
+// (= y^T W_i y, the observation border).  Seven partial sums per workgroup
+// go to partials[8 blockIdx.x + 0..6] (t_a, t_n, u_a, u_n, F_aa, F_an, F_nn).
+__global__ __launch_bounds__(256) void k_sygst_reduce(Fields F, const double *S2, int64_t ld,
+                                                      int64_t mofs, const double *Vd,
+                                                      int64_t vofs, int64_t sVd, int64_t n1,
+                                                      double *partials)
+{
+    __shared__ double sh[4];
+    const int f = blockIdx.y;
+    const int64_t n = F.n ? F.n[f] : n1;
+    const int64_t p = blockIdx.x;
+    int64_t I = (int64_t)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+    while ((I + 1) * (I + 2) / 2 <= p)
+        ++I;
+    while (I * (I + 1) / 2 > p)
+        --I;
+    const int64_t J = p - I * (I + 1) / 2;
+    const int t = threadIdx.x;
+    const int64_t a = I * NB + t;
+    double s[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (I == J) {
+        const double *Va = Vd + f * sVd + I * (NB * NB), *Vn = Va + vofs;
+        for (int c = 0; c < NB; ++c) {
+            const int64_t b = J * NB + c;
+            const double wa = -2.0 * Va[t + c * NB], wn = -2.0 * Vn[t + c * NB];
+            if (a < n && b < n) {
+                s[4] = fma(wa, wa, s[4]);
+                s[5] = fma(wa, wn, s[5]);
+                s[6] = fma(wn, wn, s[6]);
+                if (a == b) {
+                    s[0] += wa;
+                    s[1] += wn;
+                }
+            } else if (a == n && b == n) {
+                s[2] = wa;
+                s[3] = wn;
+            }
+        }
+    } else if (a < n) {
+        const double *Wa = S2 + f * F.sS2 + a + J * NB * ld, *Wn = Wa + mofs;
+        const int64_t cend = n - J * NB < NB ? n - J * NB : NB;
+        for (int64_t c = 0; c < cend; ++c) {
+            const double wa = Wa[c * ld], wn = Wn[c * ld];
+            s[4] = fma(2.0 * wa, wa, s[4]);
+            s[5] = fma(2.0 * wa, wn, s[5]);
+            s[6] = fma(2.0 * wn, wn, s[6]);
+        }
+    }
+    for (int q = 0; q < 7; ++q) {
+        const double v = block_sum(s[q], sh);
+        if (t == 0)
+            partials[f * F.sPart + 8 * p + q] = v;
+    }
+}
+
+void launch_sygst_reduce(hipStream_t s, const Fields &F, const double *S2, int64_t ld,
+                         int64_t mofs, const double *Vd, int64_t vofs, int64_t sVd, int T,
+                         int64_t n, double *partials)
+{
+    const int64_t blocks = (int64_t)T * (T + 1) / 2;
+    hipLaunchKernelGGL(k_sygst_reduce, dim3((unsigned)blocks, F.count), dim3(256), 0, s, F, S2,
+                       ld, mofs, Vd, vofs, sVd, n, partials);
+}
+
+// ---------------------------------------------------------------------------
 // Adjoint gradient (score without the W matrices).  With w = Sigma^{-1} Z,
 //   dl/dtheta_i = 1/2 w^T Sigma_i w - 1/2 tr(Sigma^{-1} Sigma_i)
 //               = sum_ab (1/2 w_a w_b - 1/2 (Sigma^{-1})_ab) (Sigma_i)_ab,

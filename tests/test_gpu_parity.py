@@ -78,14 +78,26 @@ CASES = [(1, THETAS[0]), (2, THETAS[1]), (100, THETAS[2]), (255, THETAS[0]), (25
          (1500, THETAS[0]), (1500, THETAS[3])]
 
 
-@pytest.mark.parametrize("n,theta", CASES)
-def test_eval_parity(ctx, oracle_mod, n, theta):
-    say("eval n=%d theta=%s" % (n, theta))
+WPHASES = [fbt.WPHASE_TWO_SIDED, fbt.WPHASE_SOLVES]
+
+
+@pytest.mark.parametrize("wphase", WPHASES, ids=["two_sided", "solves"])
+@pytest.mark.parametrize("n,theta", CASES + [(3000, THETAS[0]), (3000, THETAS[3])])
+def test_eval_parity(ctx, oracle_mod, n, theta, wphase):
+    say("eval n=%d theta=%s wphase=%d" % (n, theta, wphase))
     locs, z, _ = synth.dataset(n, (1.0, 0.1, 0.5), 1000 + n)
     if n > 2:
         kappa = _cond(locs, theta, oracle_mod)
         assert np.finfo(float).eps * kappa <= 1e-6, kappa
     ctx.set_data(locs, z)
+    ctx.set_wphase(wphase)
+    try:
+        _eval_parity(ctx, oracle_mod, locs, z, n, theta)
+    finally:
+        ctx.set_wphase(fbt.WPHASE_TWO_SIDED)
+
+
+def _eval_parity(ctx, oracle_mod, locs, z, n, theta):
     want = oracle_mod.evaluate(locs, z, theta)
     ll = ctx.loglik(theta)
     assert abs(ll - want["loglik"]) <= 1e-10 * abs(want["loglik"])
