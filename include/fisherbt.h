@@ -334,6 +334,33 @@ fbt_status fbt_set_sigma_nu_mode(fbt_ctx *ctx, int32_t mode);
 typedef enum { FBT_WPHASE_TWO_SIDED = 0, FBT_WPHASE_SOLVES = 1 } fbt_wphase;
 fbt_status fbt_set_wphase(fbt_ctx *ctx, int32_t form);
 
+/* ---- Allocation-free evaluation ------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * result as fbt_eval (log-likelihood, score, Fisher information; FP64, exact
+ * Sigma_nu, two-sided W phase) for one field of 1 <= n <= FBT_NOALLOC_MAX_N
+ * observations, with no context and no allocation: every device buffer lives
+ * in one static array of the library (about 50 MB per GPU, held by each GPU
+ * the library runs on from the library's load until the process ends; its
+ * address on a device is looked up on the first call there).
+ *   device      HIP device ordinal (< 16); made current for the call.
+ *   hip_stream  hipStream_t the work is ordered on (NULL: the null stream);
+ *               the call waits for it before returning.
+ *   d_locs_xy   device, n x 2 row-major locations (x_i, y_i); read only.
+ *   d_z         device, n observations; read only.
+ *   theta, loglik, score[3], fisher[9] (row-major): host, as in fbt_eval.
+ * The inputs stay owned by the caller.  Calls on one GPU share its array,
+ * which keeps the last call's contents: calls that overlap on one GPU (from
+ * several host threads, or on streams that run concurrently) race and must
+ * be serialised by the caller.  Calls on different GPUs are independent.
+ * Errors: FBT_EINVAL (NULL pointer, theta not finite and > 0, n out of range,
+ * device >= 16, a non-finite location or observation), FBT_ENOTPD,
+ * FBT_ENONFINITE, FBT_EDEVICE. */
+#define FBT_NOALLOC_MAX_N 1023
+fbt_status fbt_eval_noalloc(int32_t device, void *hip_stream, int64_t n, const double *d_locs_xy,
+                            const double *d_z, const double theta[3], double *loglik,
+                            double score[3], double fisher[9]);
+
 /* Per-kernel-class timing with HIP events recorded on the context's stream.
  * enable != 0 starts recording (and clears the counters); 0 stops it. */
 fbt_status fbt_set_timing(fbt_ctx *ctx, int32_t enable);

@@ -88,6 +88,7 @@ SIGNATURES = {
     "fbt_grad": (ctypes.c_int, [_p, _p, _p, _p, _p]),
     "fbt_set_sigma_nu_mode": (ctypes.c_int, [_p, _i32]),
     "fbt_set_wphase": (ctypes.c_int, [_p, _i32]),
+    "fbt_eval_noalloc": (ctypes.c_int, [_i32, _p, _i64, _p, _p, _p, _p, _p, _p]),
     "fbt_batch_create": (ctypes.c_int, [ctypes.POINTER(Config), _i32, ctypes.POINTER(_p)]),
     "fbt_batch_destroy": (None, [_p]),
     "fbt_batch_set_fields": (ctypes.c_int, [_p, _i32, _p, _p, _p]),

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1322,9 +1323,165 @@ fbt_status fbt::fit_eval(fbt_ctx *c, const double *th, double mixed_switch, int 
 int fbt::ctx_precision(const fbt_ctx *c) { return c->precision; }
 
 // =========================================================================
+// Allocation-free evaluation (fbt_eval_noalloc): every device buffer of one
+// evaluation of up to FBT_NOALLOC_MAX_N observations lives in one file-scope
+// device array, `scratch`, which each GPU the library runs on holds from the
+// load of the library until the process ends.  Host code never passes the
+// array's name to a kernel or a copy: each device's address of it comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+// =========================================================================
+namespace {
+
+constexpr int64_t NA_NPAD = NB * ((FBT_NOALLOC_MAX_N + 1 + NB - 1) / NB);
+constexpr int NA_T = (int)(NA_NPAD / NB);
+constexpr int NA_MAXDEV = 16;
+// regions (doubles), each rounded up to 256 bytes
+constexpr int64_t na_round(int64_t v) { return (v + 31) / 32 * 32; }
+constexpr int64_t NA_X = 0;
+constexpr int64_t NA_Y = NA_X + na_round(NA_NPAD);
+constexpr int64_t NA_Z = NA_Y + na_round(NA_NPAD);
+constexpr int64_t NA_A = NA_Z + na_round(NA_NPAD);
+constexpr int64_t NA_S2 = NA_A + na_round(NA_NPAD * NA_NPAD);
+constexpr int64_t NA_LINV = NA_S2 + na_round(2 * NA_NPAD * NA_NPAD);
+constexpr int64_t NA_LOG = NA_LINV + na_round((int64_t)NA_T * NB * NB);
+constexpr int64_t NA_PART = NA_LOG + na_round(NA_T);
+constexpr int64_t NA_OUT = NA_PART + na_round((int64_t)NA_T * (NA_NPAD / 64) * 8);
+constexpr int64_t NA_FLAG = NA_OUT + na_round(16);
+constexpr int64_t NA_INFO = NA_FLAG + na_round(1);
+constexpr int64_t NA_TAB = NA_INFO + na_round(64 / 2);
+constexpr int64_t NA_YSL = NA_TAB + na_round((int64_t)(TAB_BYTES + 7) / 8);
+constexpr int64_t NA_VD = NA_YSL + na_round((int64_t)2 * 2 * NA_NPAD * (2 * NB));
+constexpr int64_t NA_PD = NA_VD + na_round((int64_t)2 * NA_T * NB * NB);
+constexpr int64_t NA_TOTAL = NA_PD + na_round((int64_t)2 * NB * NB);
+
+// host staging of the per-theta tables and of the results, per device
+Node na_htab[NA_MAXDEV][(TAB_BYTES + sizeof(Node) - 1) / sizeof(Node)];
+double na_hout[NA_MAXDEV][16];
+int na_hinfo[NA_MAXDEV][64];
+double na_hflag[NA_MAXDEV];
+GenParams na_hgpa[NA_MAXDEV];
+double *na_ptr[NA_MAXDEV];
+std::mutex na_mu;
+
+} // namespace
+
+static __device__ __align__(256) double scratch[NA_TOTAL];
+
+namespace {
+
+// This device's address of `scratch` (taken on the first call on the device,
+// with the device current), or nullptr on failure.
+double *noalloc_scratch(int device)
+{
+    std::lock_guard<std::mutex> lk(na_mu);
+    if (!na_ptr[device]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        na_ptr[device] = static_cast<double *>(p);
+    }
+    return na_ptr[device];
+}
+
+} // namespace
+
+// =========================================================================
 // C ABI
 // =========================================================================
 extern "C" {
+
+fbt_status fbt_eval_noalloc(int32_t device, void *hip_stream, int64_t n, const double *d_locs_xy,
+                            const double *d_z, const double theta[3], double *loglik,
+                            double score[3], double fisher[9])
+{
+    if (!d_locs_xy || !d_z || !theta_ok(theta) || !loglik || !score || !fisher)
+        return FBT_EINVAL;
+    if (n < 1 || n > FBT_NOALLOC_MAX_N || device < 0 || device >= NA_MAXDEV)
+        return FBT_EINVAL;
+    if (hipSetDevice(device) != hipSuccess)
+        return FBT_EDEVICE;
+    double *base = noalloc_scratch(device);
+    if (!base)
+        return FBT_EDEVICE;
+    // A context view of the scratch: one stream (the caller's), no events, the
+    // buffers of a single field of padded order npad <= NA_NPAD at their
+    // regions.  Nothing here allocates; the work is fbt_eval's launch sequence.
+    fbt_ctx c;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    c.device = device;
+    c.stream = c.stream2 = c.stream3 = c.stream4 = st;
+    c.precision = FBT_FP64;
+    c.sigma_nu_mode = FBT_SIGMA_NU_EXACT;
+    c.wphase = FBT_WPHASE_TWO_SIDED;
+    c.n = n;
+    c.npad = NB * ((n + 1 + NB - 1) / NB);
+    c.ld = c.npad;
+    c.T = (int)(c.npad / NB);
+    c.ncols = 128 * ((n + 127) / 128);
+    c.x = base + NA_X;
+    c.y = base + NA_Y;
+    c.z = base + NA_Z;
+    c.A = base + NA_A;
+    c.S2 = base + NA_S2;
+    c.Linv = base + NA_LINV;
+    c.logdet = base + NA_LOG;
+    c.partials = base + NA_PART;
+    c.out = base + NA_OUT;
+    c.info = reinterpret_cast<int *>(base + NA_INFO);
+    c.tab = reinterpret_cast<Node *>(base + NA_TAB);
+    c.Ysl = base + NA_YSL;
+    c.Vd = base + NA_VD;
+    c.Pd = base + NA_PD;
+    c.cap_ysl = (size_t)(NA_VD - NA_YSL) * 8;
+    c.cap_vd = (size_t)(NA_PD - NA_VD) * 8;
+    c.cap_pd = (size_t)(NA_TOTAL - NA_PD) * 8;
+    c.h_tab = na_htab[device];
+    c.h_out = na_hout[device];
+    c.h_info = na_hinfo[device];
+    c.h_gpa = &na_hgpa[device];
+    c.G = 1;
+    c.batched = false;
+    c.F.count = 1;
+    c.F.sA = c.npad * c.npad;
+    c.F.sS2 = 2 * c.npad * c.npad;
+    c.F.sLinv = (int64_t)c.T * NB * NB;
+    c.F.sVec = c.npad;
+    c.F.sPart = (int64_t)c.T * (c.npad / 64) * 8;
+    c.F.sLog = c.T;
+    c.F.n = nullptr;
+    c.F.sXf = 0;
+    launch_pack_data(st, d_locs_xy, d_z, n, c.npad, c.x, c.y, c.z, base + NA_FLAG);
+    GenParams gp;
+    fbt_status s = upload_theta(&c, theta, &gp);
+    if (s == FBT_OK)
+        s = factorize_enqueue(&c, gp, GEN_ALL);
+    if (s == FBT_OK && !use_two_sided(&c, false))
+        s = FBT_EDEVICE; // the scratch holds the two-sided buffers: cannot happen
+    if (s == FBT_OK)
+        s = wphase_sygst_enqueue(&c);
+    if (s == FBT_OK &&
+        hipMemcpyAsync(&na_hflag[device], base + NA_FLAG, sizeof(double), hipMemcpyDeviceToHost,
+                       st) != hipSuccess)
+        s = FBT_EDEVICE;
+    if (hipStreamSynchronize(st) != hipSuccess)
+        return FBT_EDEVICE;
+    if (s != FBT_OK)
+        return s;
+    if (na_hflag[device] != 0.0)
+        return FBT_EINVAL; // a location or observation is not finite
+    if (na_hinfo[device][0] != 0x7fffffff)
+        return FBT_ENOTPD;
+    double t[9];
+    for (int i = 0; i < 9; ++i) {
+        t[i] = na_hout[device][i];
+        if (!std::isfinite(t[i]))
+            return FBT_ENONFINITE;
+    }
+    assemble(n, theta, t, loglik, score, fisher);
+    return FBT_OK;
+}
 
 const char *fbt_status_string(fbt_status s)
 {

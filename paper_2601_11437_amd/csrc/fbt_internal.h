@@ -142,6 +142,10 @@ void launch_zero_diag_blocks(hipStream_t s, const Fields &F, double *S2, int64_t
 void launch_sygst_reduce(hipStream_t s, const Fields &F, const double *S2, int64_t ld,
                          int64_t mofs, const double *Vd, int64_t vofs, int64_t sVd, int T,
                          int64_t n, double *partials);
+// allocation-free entry point: SoA observations (npad, zero padded) from the
+// caller's device arrays; flag[0] = 1 if an input is not finite
+void launch_pack_data(hipStream_t s, const double *locs, const double *zin, int64_t n, int64_t npad,
+                      double *x, double *y, double *z, double *flag);
 // adjoint gradient
 void launch_fill_identity(hipStream_t s, double *X, int64_t ld, int64_t rows, int64_t ncols);
 void launch_lauum(hipStream_t s, double *P, const double *X, int64_t ld, int64_t npad,

@@ -1979,6 +1979,45 @@ void launch_sygst_reduce(hipStream_t s, const Fields &F, const double *S2, int64
                        ld, mofs, Vd, vofs, sVd, n, partials);
 }
 
+// Observations of the allocation-free entry point: x, y, z (npad each, zero
+// past n) from the caller's device arrays (locations n x 2 row-major, z);
+// flag[0] = 1 if any input is not finite, else 0.  One workgroup.
+__global__ __launch_bounds__(256) void k_pack_data(const double *__restrict__ locs,
+                                                   const double *__restrict__ zin, int64_t n,
+                                                   int64_t npad, double *__restrict__ x,
+                                                   double *__restrict__ y, double *__restrict__ z,
+                                                   double *__restrict__ flag)
+{
+    __shared__ int bad;
+    if (threadIdx.x == 0)
+        bad = 0;
+    __syncthreads();
+    int b = 0;
+    for (int64_t i = threadIdx.x; i < npad; i += 256) {
+        double xi = 0.0, yi = 0.0, zi = 0.0;
+        if (i < n) {
+            xi = locs[2 * i];
+            yi = locs[2 * i + 1];
+            zi = zin[i];
+            b |= !(isfinite(xi) && isfinite(yi) && isfinite(zi));
+        }
+        x[i] = xi;
+        y[i] = yi;
+        z[i] = zi;
+    }
+    if (b)
+        atomicOr(&bad, 1);
+    __syncthreads();
+    if (threadIdx.x == 0)
+        flag[0] = bad ? 1.0 : 0.0;
+}
+
+void launch_pack_data(hipStream_t s, const double *locs, const double *zin, int64_t n, int64_t npad,
+                      double *x, double *y, double *z, double *flag)
+{
+    hipLaunchKernelGGL(k_pack_data, dim3(1), dim3(256), 0, s, locs, zin, n, npad, x, y, z, flag);
+}
+
 // ---------------------------------------------------------------------------
 // Adjoint gradient (score without the W matrices).  With w = Sigma^{-1} Z,
 //   dl/dtheta_i = 1/2 w^T Sigma_i w - 1/2 tr(Sigma^{-1} Sigma_i)

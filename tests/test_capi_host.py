@@ -68,6 +68,19 @@ def test_null_arguments_are_rejected():
     assert L.fbt_batch_autotune(None, None, None, None) == fbt.EINVAL
     assert L.fbt_batch_load_tuning(None, b"x.json") == fbt.EINVAL
     L.fbt_batch_destroy(None)                # NULL-safe
+    # allocation-free entry point: every argument error is caught before the
+    # device is touched (host memory stands in for the device arrays)
+    locs, z = np.zeros((8, 2)), np.zeros(8)
+    ll, sc, fi = np.zeros(1), np.zeros(3), np.zeros(9)
+    ptrs = [fbt._ptr(a) for a in (locs, z, th, ll, sc, fi)]
+    na = L.fbt_eval_noalloc
+    assert na(0, None, 8, None, *ptrs[1:]) == fbt.EINVAL
+    assert na(0, None, 0, *ptrs) == fbt.EINVAL
+    assert na(0, None, 1024, *ptrs) == fbt.EINVAL                    # above the maximum n
+    assert na(16, None, 8, *ptrs) == fbt.EINVAL
+    bad = np.array([1.0, -0.1, 0.5])
+    assert na(0, None, 8, ptrs[0], ptrs[1], fbt._ptr(bad), *ptrs[3:]) == fbt.EINVAL
+    assert na(0, None, 8, *ptrs[:5], None) == fbt.EINVAL
 
 
 def test_batch_create_without_gpu_fails_cleanly():
