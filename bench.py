@@ -91,7 +91,8 @@ def cpu_full(args):
     locs, z, _ = synth.dataset(args.n, w["theta_true"], w["seed"])
     log("oracle evaluation at n=%d ..." % args.n)
     t0 = time.perf_counter()
-    r = oracle.evaluate(locs, z, w["theta_true"])
+    r = oracle.evaluate(locs, z, w["theta_true"],
+                        progress=lambda what: log("  %s (%.0f s)" % (what, time.perf_counter() - t0)))
     dt = time.perf_counter() - t0
     print(json.dumps({"what": "one oracle evaluation (Eqs. (1)-(3)) at n=%d, theta=%s"
                               % (args.n, list(w["theta_true"])),

@@ -47,12 +47,14 @@ typedef enum {
 
 /* Arithmetic of the evaluation path.
  * FBT_FP64: everything in IEEE FP64 (the default).
- * FBT_MIXED_FP32: the trailing updates of the two block solves that form
+ * FBT_MIXED_FP32: the O(n^3) updates of the W phase that forms
  *   W_i = L^{-1} Sigma_i L^{-T} (the trace terms of the score and Fisher
- *   information, about 8/9 of the flops of fbt_eval) multiply on FP32 MFMA
- *   with FP32 accumulation.  The Cholesky factorisation, log-determinant and
+ *   information, about 6/7 of the flops of fbt_eval): the rank-2k and
+ *   deferred-solve updates of the two-sided form, or the trailing updates of
+ *   the block solves (fbt_set_wphase), multiply on FP32 MFMA with FP32 sums
+ *   per 256-deep slice.  The Cholesky factorisation, log-determinant and
  *   quadratic form (so the log-likelihood and every line-search test), the
- *   Bessel terms, diagonal blocks, panel solves and all reductions stay FP64:
+ *   Bessel terms, diagonal blocks, panels and all reductions stay FP64:
  *   fbt_loglik is unchanged and fbt_eval returns the FP64 log-likelihood.
  * FBT_MIXED_FP32_ALL: the Cholesky trailing updates in FP32 as well.  The
  *   log-likelihood then carries FP32 rounding amplified by the conditioning
@@ -60,7 +62,7 @@ typedef enum {
  * FBT_MIXED_BF16: as FBT_MIXED_FP32, with the operands of those updates
  *   rounded to bfloat16 (8-bit significand) and the products summed in FP32
  *   (v_mfma_f32_16x16x16_bf16).  The log-likelihood is the FP64 one; score and
- *   Fisher carry bfloat16 rounding of both block solves, amplified by the
+ *   Fisher carry bfloat16 rounding of the W phase's updates, amplified by the
  *   conditioning of Sigma (errors of order 1e-3 relative or worse). */
 typedef enum {
     FBT_FP64 = 0,
@@ -323,10 +325,11 @@ fbt_status fbt_set_sigma_nu_mode(fbt_ctx *ctx, int32_t mode);
  *     step k it forms W_kk = L_kk^{-1} S_kk L_kk^{-T}, Y = S_ik L_kk^{-T} - L_ik W_kk / 2
  *     and M = Y - L_ik W_kk / 2, updates the trailing lower blocks by
  *     S -= Y L^T + L Y^T, and solves L^{-1} M for the blocks below the
- *     diagonal after the last step: n^3 flops per matrix.  FP64 only.
+ *     diagonal: n^3 flops per matrix.
  *   FBT_WPHASE_SOLVES: the left block solve X_i = L^{-1} Sigma_i followed by
- *     the lower half of X_i L^{-T} (4 n^3 / 3 flops per matrix).  The mixed
- *     precisions (fbt_precision) always take this form.
+ *     the lower half of X_i L^{-T} (4 n^3 / 3 flops per matrix).
+ * In the mixed precisions (fbt_precision) the O(n^3) updates of either form
+ * are the low-precision ones.
  * Both forms give the same nine terms up to rounding.  If the two-sided
  * form's extra device memory (about 32 NB n_pad + 16 NB^2 (n_pad / NB) bytes,
  * NB = 256) cannot be allocated, the evaluation takes the block solves.

@@ -183,7 +183,7 @@ def _paper_sigma_nu(locs, theta):
     return Sn
 
 
-def evaluate(locs, z, theta, sigma_nu="exact"):
+def evaluate(locs, z, theta, sigma_nu="exact", progress=None):
     """Log-likelihood (Eq. (1)), score (Eq. (2)) and expected Fisher
     information (Eq. (3)) over theta = (sigma2, alpha, nu).
 
@@ -202,6 +202,8 @@ def evaluate(locs, z, theta, sigma_nu="exact"):
     Frobenius identity of Eq. (5) and by the direct sum sum_jk (A_i)_jk (A_j)_kj
     (the entry reported is the former).  ``sigma_nu="paper"`` replaces the
     exact Sigma_nu with the paper's approximation of it (Supplementary A).
+    ``progress``, if given, is called with a short text after the matrices
+    are generated and after the joint solve (long evaluations report there).
     """
     theta = _check_theta(theta)
     s2 = theta[0]
@@ -211,8 +213,12 @@ def evaluate(locs, z, theta, sigma_nu="exact"):
     if sigma_nu == "paper":
         Sn = _paper_sigma_nu(locs, theta)
     deriv = {"a": Sa, "n": Sn}
+    if progress:
+        progress("covariance and derivative matrices generated")
     logdet, X = _spd_solve(S, np.hstack([z[:, None], Sa, Sn]))
     del S
+    if progress:
+        progress("Cholesky factorisation and joint solve done")
     w = X[:, 0]
     A = {"a": X[:, 1:n + 1], "n": X[:, n + 1:]}
     quad = float(z @ w)

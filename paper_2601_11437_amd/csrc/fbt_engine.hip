@@ -406,12 +406,11 @@ bool ensure_sygst(fbt_ctx *c)
     return true;
 }
 
-// The W phase takes the two-sided reduction in FP64 when selected and its
-// buffers exist (allocated here unless `may_alloc` is false); the mixed
-// precisions take the block solves.
+// The W phase takes the two-sided reduction when selected and its buffers
+// exist (allocated here unless `may_alloc` is false).
 bool use_two_sided(fbt_ctx *c, bool may_alloc = true)
 {
-    if (c->wphase != FBT_WPHASE_TWO_SIDED || c->precision != FBT_FP64)
+    if (c->wphase != FBT_WPHASE_TWO_SIDED)
         return false;
     if (may_alloc)
         return ensure_sygst(c);
@@ -867,6 +866,9 @@ fbt_status wphase_sygst_enqueue(fbt_ctx *c)
     const int64_t sY = sy_stride(c), ymofs = npad * (2 * NB), ldy = npad;
     const int64_t sVd = vd_stride(c), vofs = (int64_t)T * NB * NB, sPd = pd_stride();
     const double dNB = NB;
+    // the rank-2k updates and the deferred solve's updates: FP32 (1) or BF16
+    // operands (2) with FP32 sums in the mixed precisions; everything else FP64
+    const int mix = c->precision == FBT_FP64 ? 0 : c->precision == FBT_MIXED_BF16 ? 2 : 1;
     auto Lk = [&](int k) { return c->Linv + (size_t)k * NB * NB; };
     auto Vk = [&](int k) { return c->Vd + (size_t)k * NB * NB; };
     auto slot = [&](int b) { return c->Ysl + (size_t)((b / 2) & 1) * (2 * npad * (2 * NB)); };
@@ -890,7 +892,7 @@ fbt_status wphase_sygst_enqueue(fbt_ctx *c)
         if (r < npad && w > 0)
             TIMED(c, s0, KC_SLOOK, 2.0 * 2.0 * 2.0 * real(r, npad) * real(q, w) * KS,
                   launch_syr2k_rect(s0, c->F, S2, ld, mofs, A, r, npad - r, q, w, (int64_t)kb * NB,
-                                    KS, Y, ldy, ymofs, sY));
+                                    KS, Y, ldy, ymofs, sY, mix));
     };
 
     // The deferred solve of block rows (b, b + 1) needs their M complete, i.e.
@@ -912,7 +914,7 @@ fbt_status wphase_sygst_enqueue(fbt_ctx *c)
         if (nb == 2) {
             TIMED(c, sd, KC_DUPD, 2.0 * 2.0 * real(r0 + NB, NB) * dNB * real(0, r0),
                   launch_update_nn(sd, c->F, c->F.sS2, 2, S2, ld, A, ld, r0 + NB, r0, NB, r0, npad,
-                                   NB, 0));
+                                   NB, mix));
             TIMED(c, sd, KC_DAPPLY, 2.0 * dNB * dNB * real(0, r0 + NB),
                   launch_diag_apply(sd, c->F, c->F.sS2, 2, S2, ld, r0 + NB, Lk(b + 1), r0 + NB,
                                     npad));
@@ -927,12 +929,12 @@ fbt_status wphase_sygst_enqueue(fbt_ctx *c)
         const int64_t la = std::min<int64_t>(2 * NB, npad - rn);
         HIPCHK(c, ev_wait(sd, c->evB2));
         TIMED(c, sd, KC_DUPD, 2.0 * 2.0 * real(rn, la) * K * real(0, cols),
-              launch_update_nn(sd, c->F, c->F.sS2, 2, S2, ld, A, ld, rn, r0, la, cols, npad, K, 0));
+              launch_update_nn(sd, c->F, c->F.sS2, 2, S2, ld, A, ld, rn, r0, la, cols, npad, K, mix));
         HIPCHK(c, ev_wait(sdb, c->evP2));
         if (rn + la < npad)
             TIMED(c, sdb, KC_DUPD, 2.0 * 2.0 * real(rn + la, npad) * K * real(0, cols),
                   launch_update_nn(sdb, c->F, c->F.sS2, 2, S2, ld, A, ld, rn + la, r0,
-                                   npad - rn - la, cols, npad, K, 0));
+                                   npad - rn - la, cols, npad, K, mix));
         HIPCHK(c, ev_record(c->evB2, sdb));
         return FBT_OK;
     };
@@ -963,7 +965,7 @@ fbt_status wphase_sygst_enqueue(fbt_ctx *c)
             if (t0 < npad)
                 TIMED(c, s1, KC_SUPD, 2.0 * 2.0 * real(t0, npad) * real(t0, npad) * KS,
                       launch_syr2k_lower(s1, c->F, S2, ld, mofs, A, t0, (int)((npad - t0) / NB), r0,
-                                         KS, Y, ldy, ymofs, sY, 0));
+                                         KS, Y, ldy, ymofs, sY, 0, mix));
             HIPCHK(c, ev_record(c->evB, s1));
         }
         if ((st = deferred_pair(b)) != FBT_OK)

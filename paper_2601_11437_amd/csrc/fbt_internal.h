@@ -130,13 +130,15 @@ void launch_sygst_panel(hipStream_t s, const Fields &F, double *S2, int64_t ld, 
                         const double *Linv, const double *Vd, int64_t vofs, int64_t sVd,
                         double *Y, int64_t ldy, int64_t ymofs, int64_t sY);
 // (the blocks among the first `skip` block rows of the trailing part are left out)
+// mixed: 0 FP64, 1 FP32 MFMA with FP32 sums per NB-deep slice, 2 BF16 operands
 void launch_syr2k_lower(hipStream_t s, const Fields &F, double *S2, int64_t ld, int64_t mofs,
                         const double *A, int64_t t0, int nblk, int64_t kcol, int KS,
-                        const double *Y, int64_t ldy, int64_t ymofs, int64_t sY, int skip);
+                        const double *Y, int64_t ldy, int64_t ymofs, int64_t sY, int skip,
+                        int mixed);
 void launch_syr2k_rect(hipStream_t s, const Fields &F, double *S2, int64_t ld, int64_t mofs,
                        const double *A, int64_t r0, int64_t rows, int64_t c0, int64_t ncol,
                        int64_t kcol, int KS, const double *Y, int64_t ldy, int64_t ymofs,
-                       int64_t sY);
+                       int64_t sY, int mixed);
 void launch_zero_diag_blocks(hipStream_t s, const Fields &F, double *S2, int64_t ld, int64_t mofs,
                              int k0, int count);
 void launch_sygst_reduce(hipStream_t s, const Fields &F, const double *S2, int64_t ld,

@@ -1801,39 +1801,59 @@ void launch_sygst_panel(hipStream_t s, const Fields &F, double *S2, int64_t ld, 
 
 // C -= Y L^T + L Y^T on one 128 x 128 tile at (m0, n0) of matrix m: the
 // symmetric update by the KS / NB steps whose Y fill slot columns 0..KS and
-// whose factor columns start at kcol.  The two products are accumulated
-// one after the other onto C (held in the accumulators), so a tile is read and
-// written once for a 2 KS-deep update.
-template <int KS>
+// whose factor columns start at kcol.  FP64 (MIX = 0): the two products are
+// accumulated one after the other onto C (held in the accumulators), so a
+// tile is read and written once for a 2 KS-deep update.  MIX = 1 (FP32) and 2
+// (BF16 operands): TileF / TileB, FP32 sums per NB-deep slice subtracted from
+// the FP64 C tile.
+template <int MIX, int KS>
 __device__ __forceinline__ void syr2k_tile(double *C, int64_t ld, const double *Ym, int64_t ldy,
                                            const double *L, int64_t kcol, int64_t m0, int64_t n0,
                                            double *lds)
 {
-    using TL = Tile<2, 2, false, true>;
-    d4 acc[4][4];
-    TL::load_c(acc, C + m0 + n0 * ld, ld);
-    // one copy of the main loop for both products (two inlined copies cost
-    // registers and the second workgroup per CU)
+    if constexpr (MIX == 0) {
+        using TL = Tile<2, 2, false, true>;
+        d4 acc[4][4];
+        TL::load_c(acc, C + m0 + n0 * ld, ld);
+        // one copy of the main loop for both products (two inlined copies cost
+        // registers and the second workgroup per CU)
 #pragma unroll 1
-    for (int q = 0; q < 2; ++q) {
-        const double *Aq = q ? L + m0 + kcol * ld : Ym + m0;
-        const double *Bq = q ? Ym + n0 : L + n0 + kcol * ld;
-        TL::run(acc, Aq, q ? ld : ldy, Bq, q ? ldy : ld, KS, lds);
+        for (int q = 0; q < 2; ++q) {
+            const double *Aq = q ? L + m0 + kcol * ld : Ym + m0;
+            const double *Bq = q ? Ym + n0 : L + n0 + kcol * ld;
+            TL::run(acc, Aq, q ? ld : ldy, Bq, q ? ldy : ld, KS, lds);
+        }
+        TL::store_c(acc, C + m0 + n0 * ld, ld);
+    } else {
+        using TF = typename std::conditional<MIX == 2, TileB<2, 2, false>, TileF<2, 2, false>>::type;
+        using E = typename std::conditional<MIX == 2, unsigned short, float>::type;
+#pragma unroll 1
+        for (int q = 0; q < 2; ++q) {
+            const double *Aq = q ? L + m0 + kcol * ld : Ym + m0;
+            const double *Bq = q ? Ym + n0 : L + n0 + kcol * ld;
+            TF::update(C + m0 + n0 * ld, ld, Aq, q ? ld : ldy, Bq, q ? ldy : ld, KS, (E *)lds);
+        }
     }
-    TL::store_c(acc, C + m0 + n0 * ld, ld);
 }
+
+template <int MIX>
+struct Syr2kLds {
+    static constexpr int N = MIX == 2   ? (TileB<2, 2, false>::LDS + 3) / 4
+                             : MIX == 1 ? (TileF<2, 2, false>::LDS + 1) / 2
+                                        : Tile<2, 2, false, true>::LDS;
+};
 
 // over the block-lower tiles of the trailing nblk x nblk blocks from t0
 // (both 128-tiles above the diagonal inside a diagonal NB-block included),
 // block pairs (I, J) in row-major order from the p0-th on (p0 = skip (skip + 1)
 // / 2 leaves out the blocks among the first `skip` block rows)
-template <int KS>
+template <int MIX, int KS>
 __global__ __launch_bounds__(256) void k_syr2k_lower(Fields F, double *S2, int64_t ld,
                                                      int64_t mofs, const double *A, int64_t t0,
                                                      int64_t kcol, const double *Y, int64_t ldy,
                                                      int64_t ymofs, int64_t sY, int64_t p0)
 {
-    __shared__ double lds[Tile<2, 2, false, true>::LDS];
+    __shared__ double lds[Syr2kLds<MIX>::N];
     const int64_t p = p0 + (blockIdx.x >> 2);
     const int s = blockIdx.x & 3;
     int64_t I = (int64_t)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
@@ -1844,27 +1864,39 @@ __global__ __launch_bounds__(256) void k_syr2k_lower(Fields F, double *S2, int64
     const int64_t J = p - I * (I + 1) / 2;
     const int64_t m0 = t0 + I * NB + 128 * (s >> 1), n0 = t0 + J * NB + 128 * (s & 1);
     const int m = blockIdx.y & 1, f = blockIdx.y >> 1; // matrix, field
-    syr2k_tile<KS>(S2 + f * F.sS2 + m * mofs, ld, Y + f * sY + m * ymofs, ldy, A + f * F.sA, kcol,
-                   m0, n0, lds);
+    syr2k_tile<MIX, KS>(S2 + f * F.sS2 + m * mofs, ld, Y + f * sY + m * ymofs, ldy, A + f * F.sA,
+                        kcol, m0, n0, lds);
 }
 
 // on a rectangle of rows x ncol from (r0, c0) (lookahead of the next block columns)
-template <int KS>
+template <int MIX, int KS>
 __global__ __launch_bounds__(256) void k_syr2k_rect(Fields F, double *S2, int64_t ld, int64_t mofs,
                                                     const double *A, int64_t r0, int64_t c0,
                                                     int64_t kcol, const double *Y, int64_t ldy,
                                                     int64_t ymofs, int64_t sY)
 {
-    __shared__ double lds[Tile<2, 2, false, true>::LDS];
+    __shared__ double lds[Syr2kLds<MIX>::N];
     const int64_t m0 = r0 + 128 * (int64_t)blockIdx.x, n0 = c0 + 128 * (int64_t)blockIdx.y;
     const int m = blockIdx.z & 1, f = blockIdx.z >> 1; // matrix, field
-    syr2k_tile<KS>(S2 + f * F.sS2 + m * mofs, ld, Y + f * sY + m * ymofs, ldy, A + f * F.sA, kcol,
-                   m0, n0, lds);
+    syr2k_tile<MIX, KS>(S2 + f * F.sS2 + m * mofs, ld, Y + f * sY + m * ymofs, ldy, A + f * F.sA,
+                        kcol, m0, n0, lds);
+}
+
+template <int KS>
+static decltype(&k_syr2k_lower<0, KS>) syr2k_lower_kernel(int mixed)
+{
+    return mixed == 2 ? k_syr2k_lower<2, KS> : mixed == 1 ? k_syr2k_lower<1, KS> : k_syr2k_lower<0, KS>;
+}
+template <int KS>
+static decltype(&k_syr2k_rect<0, KS>) syr2k_rect_kernel(int mixed)
+{
+    return mixed == 2 ? k_syr2k_rect<2, KS> : mixed == 1 ? k_syr2k_rect<1, KS> : k_syr2k_rect<0, KS>;
 }
 
 void launch_syr2k_lower(hipStream_t s, const Fields &F, double *S2, int64_t ld, int64_t mofs,
                         const double *A, int64_t t0, int nblk, int64_t kcol, int KS,
-                        const double *Y, int64_t ldy, int64_t ymofs, int64_t sY, int skip)
+                        const double *Y, int64_t ldy, int64_t ymofs, int64_t sY, int skip,
+                        int mixed)
 {
     if (nblk <= skip || (KS != NB && KS != 2 * NB))
         return;
@@ -1872,20 +1904,20 @@ void launch_syr2k_lower(hipStream_t s, const Fields &F, double *S2, int64_t ld, 
     const int64_t first = (int64_t)skip * (skip + 1) / 2;
     const int64_t pairs = (int64_t)nblk * (nblk + 1) / 2;
     const dim3 g((unsigned)(4 * (pairs - first)), (unsigned)(2 * F.count));
-    hipLaunchKernelGGL(KS == NB ? k_syr2k_lower<NB> : k_syr2k_lower<2 * NB>, g, dim3(256),
-                       0, s, F, S2, ld, mofs, A, t0, kcol, Y, ldy, ymofs, sY, first);
+    hipLaunchKernelGGL(KS == NB ? syr2k_lower_kernel<NB>(mixed) : syr2k_lower_kernel<2 * NB>(mixed),
+                       g, dim3(256), 0, s, F, S2, ld, mofs, A, t0, kcol, Y, ldy, ymofs, sY, first);
 }
 
 void launch_syr2k_rect(hipStream_t s, const Fields &F, double *S2, int64_t ld, int64_t mofs,
                        const double *A, int64_t r0, int64_t rows, int64_t c0, int64_t ncol,
                        int64_t kcol, int KS, const double *Y, int64_t ldy, int64_t ymofs,
-                       int64_t sY)
+                       int64_t sY, int mixed)
 {
     if (rows <= 0 || ncol <= 0 || (KS != NB && KS != 2 * NB))
         return;
     const dim3 g((unsigned)(rows / 128), (unsigned)(ncol / 128), (unsigned)(2 * F.count));
-    hipLaunchKernelGGL(KS == NB ? k_syr2k_rect<NB> : k_syr2k_rect<2 * NB>, g, dim3(256), 0, s, F,
-                       S2, ld, mofs, A, r0, c0, kcol, Y, ldy, ymofs, sY);
+    hipLaunchKernelGGL(KS == NB ? syr2k_rect_kernel<NB>(mixed) : syr2k_rect_kernel<2 * NB>(mixed), g,
+                       dim3(256), 0, s, F, S2, ld, mofs, A, r0, c0, kcol, Y, ldy, ymofs, sY);
 }
 
 // Zero the NB x NB diagonal blocks k0, k0 + 1, .. of both matrices (blockIdx.x

@@ -271,16 +271,17 @@ def test_mixed_precision(ctx, oracle_mod, n, theta):
 
 
 @pytest.mark.parametrize("n,theta", [(600, (1.0, 0.1, 0.5)), (1500, (1.5, 0.07, 1.0))])
-def test_mixed_bf16(ctx, n, theta):
+def test_mixed_bf16(ctx, oracle_mod, n, theta):
     """BF16 operands with FP32 sums in the trace-phase updates: the
     log-likelihood is the FP64 one bit for bit, the sigma2 score too; the other
     score terms and the Fisher entries carry bfloat16 rounding (eps = 2^-8) of
-    both block solves: measured 1e-4 .. 1.3e-2 of the per-term scale and
-    4e-4 .. 1.4e-2 relative on these cases; the gates are 5e-2."""
+    the W phase's updates: measured against the oracle on MI355X (two-sided
+    W phase) 1.8e-5 .. 3.2e-3 of the per-term scale and 3.3e-4 .. 2.0e-2
+    relative in Fisher; the gates are 5e-2."""
     say("bf16 n=%d theta=%s" % (n, theta))
     locs, z, _ = synth.dataset(n, (1.0, 0.1, 0.5), 3000 + n)
     ctx.set_data(locs, z)
-    t = ctx.eval_terms(theta)
+    want = oracle_mod.evaluate(locs, z, theta)
     ll64, s64, f64 = ctx.eval(theta)
     ctx.set_precision(fbt.MIXED_BF16)
     try:
@@ -288,13 +289,51 @@ def test_mixed_bf16(ctx, n, theta):
     finally:
         ctx.set_precision(fbt.FP64)
     assert ll == ll64 and score[0] == s64[0]
-    scale = np.array([(t[1] + n) / (2 * theta[0]), 0.5 * (abs(t[2]) + abs(t[4])),
-                      0.5 * (abs(t[3]) + abs(t[5]))])
-    err = np.abs(score - s64) / scale
-    d = np.sqrt(np.outer(np.diag(f64), np.diag(f64)))
-    say("score err / scale", err, "fisher rel", np.max(np.abs(fisher - f64) / d))
-    assert np.all(err <= 5e-2) and np.all(np.abs(fisher - f64) <= 5e-2 * d)
-    assert np.any(err[1:] > 0)                        # the BF16 path really ran
+    scale = np.array([(want["quad"] + n) / (2 * theta[0]),
+                      0.5 * (abs(want["trace"]["a"]) + abs(want["wSw"]["a"])),
+                      0.5 * (abs(want["trace"]["n"]) + abs(want["wSw"]["n"]))])
+    err = np.abs(score - want["score"]) / scale
+    I = want["fisher"]
+    d = np.sqrt(np.outer(np.diag(I), np.diag(I)))
+    say("against the oracle: score err / scale", err, "fisher rel", np.max(np.abs(fisher - I) / d))
+    assert abs(ll - want["loglik"]) <= 1e-10 * abs(want["loglik"])
+    assert np.all(err <= 5e-2) and np.all(np.abs(fisher - I) <= 5e-2 * d)
+    assert np.any(np.abs(score - s64)[1:] > 0)          # the BF16 path really ran
+
+
+@pytest.mark.parametrize("n,theta", [(600, (1.0, 0.1, 0.5)), (1500, (1.5, 0.07, 1.0))])
+def test_mixed_fp32_all(ctx, oracle_mod, n, theta):
+    """FBT_MIXED_FP32_ALL: the Cholesky trailing updates in FP32 as well, so
+    the log-likelihood carries FP32 rounding of the factorisation (its
+    log-determinant cannot be refined); against the oracle (measured on
+    MI355X): loglik 1.9e-8 / 1.3e-5 relative, score 1.1e-7 / 3.0e-5 of its
+    per-term scale, Fisher 1.2e-6 / 3.0e-6 relative at n = 600 / 1,500.  Gates:
+    loglik 1e-4, score 3e-4, Fisher 1e-4.  A fit refuses the form."""
+    say("fp32-all n=%d theta=%s" % (n, theta))
+    locs, z, _ = synth.dataset(n, (1.0, 0.1, 0.5), 3000 + n)
+    ctx.set_data(locs, z)
+    want = oracle_mod.evaluate(locs, z, theta)
+    ctx.set_precision(fbt.MIXED_FP32_ALL)
+    try:
+        ll, score, fisher = ctx.eval(theta)
+        ll_only = ctx.loglik(theta)
+        with pytest.raises(fbt.FisherBTError) as e:
+            ctx.fit()
+        assert e.value.status == fbt.EINVAL
+    finally:
+        ctx.set_precision(fbt.FP64)
+    scale = np.array([(want["quad"] + n) / (2 * theta[0]),
+                      0.5 * (abs(want["trace"]["a"]) + abs(want["wSw"]["a"])),
+                      0.5 * (abs(want["trace"]["n"]) + abs(want["wSw"]["n"]))])
+    e_ll = abs(ll - want["loglik"]) / abs(want["loglik"])
+    err = np.abs(score - want["score"]) / scale
+    I = want["fisher"]
+    d = np.sqrt(np.outer(np.diag(I), np.diag(I)))
+    e_f = np.max(np.abs(fisher - I) / d)
+    say("against the oracle: loglik %.2e score/scale %s fisher %.2e" % (e_ll, err, e_f))
+    assert ll_only == ll
+    assert e_ll <= 1e-4 and np.all(err <= 3e-4) and e_f <= 1e-4
+    assert e_ll > 0                                     # the FP32 factorisation really ran
 
 
 def test_mixed_fit_switches_to_fp64(ctx):
