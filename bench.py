@@ -388,7 +388,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=20000)
-    ap.add_argument("--cpu-sample-n", type=int, default=8000,
+    ap.add_argument("--cpu-sample-n", type=int, default=10000,
                     help="n of the oracle's timed sample (the CPU baseline)")
     ap.add_argument("--cpu-full", action="store_true",
                     help="only time one oracle evaluation at the full n on the host")
