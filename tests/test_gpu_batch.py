@@ -220,3 +220,55 @@ def test_batch_argument_errors(fields):
     with pytest.raises(fbt.FisherBTError):
         b.eval(thetas[:3], [2, 2, 7])
     b.close()
+
+
+def test_batch_fields_against_oracle(oracle_mod):
+    """Four fields of the many-field workload (n_f ~ U[500, 4000], theta_f
+    drawn as there) evaluated in one batched call, each against the oracle at
+    the FP64 parity bar: loglik 1e-10 relative, score 1e-10 of its per-term
+    scale, Fisher 1e-8 of sqrt(I_ii I_jj).  The four are the workload's first
+    fields with n below 1,500 (the oracle's cost) whose covariance at theta_f
+    has eps cond(Sigma) <= 1e-8: the workload's draws reach cond ~ 1e15, and
+    at cond = 1.5e9 (eps cond = 3e-7) the loglik already differs by 1.2e-10
+    relative (measured; rounding amplified by the conditioning)."""
+    g = synth.rng(5000)
+    ns = g.integers(500, 4001, 256)
+    thetas_all = synth.batch_redraw_thetas(np.zeros((256, 3)), np.ones(256, bool), g)
+    data, thetas, pick = [], [], []
+    for f in range(256):
+        if ns[f] >= 1500:
+            continue
+        locs, z, _ = synth.dataset(int(ns[f]), (1.0, 0.1, 0.5), 5001 + f)
+        kappa = np.linalg.cond(oracle_mod.cov_matrices(locs, thetas_all[f], which=("S",))[0])
+        say("field %d n=%d theta=%s cond=%.1e" % (f, ns[f], np.round(thetas_all[f], 4), kappa))
+        if np.finfo(float).eps * kappa > 1e-8:
+            continue
+        data.append((locs, z))
+        thetas.append(thetas_all[f])
+        pick.append(f)
+        if len(pick) == 4:
+            break
+    thetas = np.array(thetas)
+    say("batch vs oracle: fields %s, n %s" % (pick, [int(ns[f]) for f in pick]))
+    b = fbt.Batch(2)
+    b.set_fields(data)
+    ll, sc, fi, st = b.eval(thetas, fbt.Batch.EVAL)
+    b.close()
+    assert len(pick) == 4
+    for k, (locs, z) in enumerate(data):
+        th = thetas[k]
+        want = oracle_mod.evaluate(locs, z, th)
+        n = z.size
+        assert st[k] == fbt.OK
+        scale = np.array([(want["quad"] + n) / (2 * th[0]),
+                          0.5 * (abs(want["trace"]["a"]) + abs(want["wSw"]["a"])),
+                          0.5 * (abs(want["trace"]["n"]) + abs(want["wSw"]["n"]))])
+        I = want["fisher"]
+        d = np.sqrt(np.outer(np.diag(I), np.diag(I)))
+        say("field %d: loglik %.1e score/scale %s fisher %.1e"
+            % (pick[k], abs(ll[k] - want["loglik"]) / abs(want["loglik"]),
+               np.array2string(np.abs(sc[k] - want["score"]) / scale, precision=1),
+               np.max(np.abs(fi[k] - I) / d)))
+        assert abs(ll[k] - want["loglik"]) <= 1e-10 * abs(want["loglik"])
+        assert np.all(np.abs(sc[k] - want["score"]) <= 1e-10 * scale)
+        assert np.all(np.abs(fi[k] - I) <= 1e-8 * d)
