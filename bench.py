@@ -312,10 +312,15 @@ def precision_bench(args):
     ctx = fbt.Context(0)
     ctx.set_data(locs, z)
     res = {}
-    for name, prec in (("fp64", fbt.FP64), ("mixed_fp32", fbt.MIXED_FP32),
-                       ("mixed_fp32_all", fbt.MIXED_FP32_ALL), ("mixed_bf16", fbt.MIXED_BF16)):
+    # MIXED_FP32_ALL with its default two refinement steps of w, and without
+    for name, prec, refine in (("fp64", fbt.FP64, 2), ("mixed_fp32", fbt.MIXED_FP32, 2),
+                               ("mixed_fp32_all", fbt.MIXED_FP32_ALL, 2),
+                               ("mixed_fp32_all_unrefined", fbt.MIXED_FP32_ALL, 0),
+                               ("mixed_bf16", fbt.MIXED_BF16, 2)):
         ctx.set_precision(prec)
+        ctx.set_refinement(refine)
         try:
+            ctx.loglik(theta)                    # untimed (buffers, FP32 copies)
             t0 = time.perf_counter()
             ll_only = ctx.loglik(theta)
             t1 = time.perf_counter()
@@ -330,6 +335,7 @@ def precision_bench(args):
         res[name] = {"loglik": ll, "score": sc.tolist(), "fisher": fi.tolist(), "terms": terms.tolist(),
                      "loglik_s": t1 - t0, "eval_s": t3 - t2, "w_phase_s": t2 - t1}
         log("%s: loglik %.3f s, eval %.3f s" % (name, t1 - t0, t3 - t2))
+    ctx.set_refinement(2)
     if args.precision_fits:
         # Fisher-BT from the L9 start in FP64 and in the FP32 and BF16 mixed forms
         # (both switch to FP64 near the optimum).  No Nelder-Mead fallback: a
@@ -363,11 +369,12 @@ def precision_bench(args):
     scale = np.array([(t[1] + n) / (2 * theta[0]), 0.5 * (abs(t[2]) + abs(t[4])),
                       0.5 * (abs(t[3]) + abs(t[5]))])
     fd = np.diag(np.array(ref["fisher"]))
-    for name in ("mixed_fp32", "mixed_fp32_all", "mixed_bf16"):
+    for name in ("mixed_fp32", "mixed_fp32_all", "mixed_fp32_all_unrefined", "mixed_bf16"):
         r = res[name]
         if "loglik" not in r:
             continue
         r["loglik_rel_err_vs_fp64"] = abs(r["loglik"] - ref["loglik"]) / abs(ref["loglik"])
+        r["loglik_speedup_vs_fp64"] = ref["loglik_s"] / r["loglik_s"]
         r["score_err_per_term_vs_fp64"] = (np.abs(np.array(r["score"]) - ref["score"]) / scale).tolist()
         r["fisher_rel_err_vs_fp64"] = float(np.max(np.abs(np.array(r["fisher"]) - ref["fisher"])
                                                    / np.sqrt(np.outer(fd, fd))))

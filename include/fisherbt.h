@@ -57,8 +57,11 @@ typedef enum {
  *   Bessel terms, diagonal blocks, panels and all reductions stay FP64:
  *   fbt_loglik is unchanged and fbt_eval returns the FP64 log-likelihood.
  * FBT_MIXED_FP32_ALL: the Cholesky trailing updates in FP32 as well.  The
- *   log-likelihood then carries FP32 rounding amplified by the conditioning
- *   of Sigma, and the factorisation can fail for ill-conditioned Sigma.
+ *   solve for w = Sigma^{-1} Z is won back by iterative refinement (see
+ *   fbt_set_refinement), so the quadratic forms Z^T Sigma^{-1} Z and
+ *   w^T Sigma_i w are FP64-accurate; the log-determinant and the traces keep
+ *   FP32 rounding amplified by the conditioning of Sigma, and the
+ *   factorisation can fail for ill-conditioned Sigma.  fbt_fit refuses it.
  * FBT_MIXED_BF16: as FBT_MIXED_FP32, with the operands of those updates
  *   rounded to bfloat16 (8-bit significand) and the products summed in FP32
  *   (v_mfma_f32_16x16x16_bf16).  The log-likelihood is the FP64 one; score and
@@ -317,6 +320,17 @@ fbt_status fbt_batch_load_tuning(fbt_batch *b, const char *path);
  * Errors: FBT_EINVAL (NULL context or unknown mode). */
 typedef enum { FBT_SIGMA_NU_EXACT = 0, FBT_SIGMA_NU_PAPER = 1 } fbt_sigma_nu_mode;
 fbt_status fbt_set_sigma_nu_mode(fbt_ctx *ctx, int32_t mode);
+
+/* Iterative refinement under FBT_MIXED_FP32_ALL (ignored otherwise and in
+ * batched groups): after the factorisation, `iterations` steps (default 2)
+ *   w <- w + (L L^T)^{-1} (Z - Sigma w),   w_0 = (L L^T)^{-1} Z,
+ * with the residual in FP64 and the entries of Sigma regenerated (no FP64
+ * copy of Sigma), L the factor with FP32 trailing updates; then
+ * Z^T Sigma^{-1} Z = Z^T w, and in fbt_eval w^T Sigma_i w with Sigma_i
+ * regenerated.  Each step costs a regeneration of Sigma (both triangles) and
+ * two triangular solves with the factor.  0 turns it off.
+ * Errors: FBT_EINVAL (NULL context, iterations outside [0, 16]). */
+fbt_status fbt_set_refinement(fbt_ctx *ctx, int32_t iterations);
 
 /* Form of the W phase of fbt_eval / fbt_eval_terms / fbt_fit: the matrices
  * W_i = L^{-1} Sigma_i L^{-T}, i in {alpha, nu}, whose traces and Frobenius

@@ -88,6 +88,7 @@ SIGNATURES = {
     "fbt_grad": (ctypes.c_int, [_p, _p, _p, _p, _p]),
     "fbt_set_sigma_nu_mode": (ctypes.c_int, [_p, _i32]),
     "fbt_set_wphase": (ctypes.c_int, [_p, _i32]),
+    "fbt_set_refinement": (ctypes.c_int, [_p, _i32]),
     "fbt_eval_noalloc": (ctypes.c_int, [_i32, _p, _i64, _p, _p, _p, _p, _p, _p]),
     "fbt_batch_create": (ctypes.c_int, [ctypes.POINTER(Config), _i32, ctypes.POINTER(_p)]),
     "fbt_batch_destroy": (None, [_p]),
@@ -356,6 +357,11 @@ class Context:
         lower-half right solve, 4 n^3 / 3 per matrix; the mixed precisions
         always take it) for the W phase of the following evaluations."""
         self._check(lib().fbt_set_wphase(self._h, int(form)))
+
+    def set_refinement(self, iterations: int):
+        """Refinement steps of w = Sigma^{-1} Z under MIXED_FP32_ALL (default 2;
+        0 turns it off)."""
+        self._check(lib().fbt_set_refinement(self._h, int(iterations)))
 
     def set_timing(self, enable: bool):
         self._check(lib().fbt_set_timing(self._h, 1 if enable else 0))

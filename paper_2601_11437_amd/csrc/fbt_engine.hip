@@ -60,7 +60,9 @@ struct fbt_ctx {
     double *A = nullptr;  // Sigma' -> bordered factor L' (lower)
     double *S2 = nullptr; // [Sigma_alpha' | Sigma_nu'] -> X -> W (npad x 2 npad)
     double *Linv = nullptr, *logdet = nullptr, *partials = nullptr, *out = nullptr;
-    double *wv = nullptr; // w = Sigma^{-1} Z (adjoint gradient)
+    double *wv = nullptr; // w = Sigma^{-1} Z (adjoint gradient; refinement)
+    double *rv = nullptr; // refinement: residual / correction (npad) and matvec partials (8 npad)
+    int refine_iters = 2; // FBT_MIXED_FP32_ALL: refinement steps of w (fbt_set_refinement)
     int *info = nullptr;
     Node *tab = nullptr;   // per field: node table + paper-mode coefficients (TAB_BYTES)
     Node *h_tab = nullptr; // pinned staging
@@ -349,7 +351,7 @@ void free_buffers(fbt_ctx *c)
                     (void **)&c->A,        (void **)&c->S2,   (void **)&c->Linv,
                     (void **)&c->logdet,   (void **)&c->partials, (void **)&c->out,
                     (void **)&c->wv,       (void **)&c->info, (void **)&c->tab,
-                    (void **)&c->d_nf,     (void **)&c->d_gpa};
+                    (void **)&c->d_nf,     (void **)&c->d_gpa, (void **)&c->rv};
     for (void **p : dev) {
         (void)hipFree(*p);
         *p = nullptr;
@@ -468,6 +470,7 @@ fbt_status alloc_fields(fbt_ctx *c, int64_t nmax, int G, bool batched)
         {(void **)&c->logdet, g * (size_t)T * 8, false}, {(void **)&c->partials, g * part * 8, false},
         {(void **)&c->out, g * 16 * 8, false},        {(void **)&c->info, std::max<size_t>(64, g * 4), false},
         {(void **)&c->wv, g * ld * 8, false},         {(void **)&c->tab, g * TAB_BYTES, false},
+        {(void **)&c->rv, g * ld * 9 * 8, false},
         {(void **)&c->d_nf, g * 8, false},            {(void **)&c->d_gpa, g * sizeof(GenParams), false},
         {(void **)&c->h_tab, g * TAB_BYTES, true},    {(void **)&c->h_out, g * 16 * 8, true},
         {(void **)&c->h_info, std::max<size_t>(64, g * 4), true},
@@ -646,6 +649,38 @@ void factor_results(fbt_ctx *c)
     }
 }
 
+// FBT_MIXED_FP32_ALL: the factor's trailing updates ran in FP32, so w =
+// Sigma^{-1} Z (and with it q = Z^T w) is won back by iterative refinement:
+// w from the factor, then c->refine_iters steps w += Sigma~^{-1} (Z - Sigma w)
+// with the residual in FP64 and the entries of Sigma regenerated (no FP64
+// copy of Sigma is kept), Sigma~ = L L^T the factor's matrix.  The log
+// determinant keeps the factor's rounding.  Sets c->factor_out[1] = Z^T w;
+// c->wv holds w.
+fbt_status refine_w(fbt_ctx *c, const GenParams &gp)
+{
+    hipStream_t s0 = c->stream;
+    const int64_t npad = c->npad, ld = c->ld, n = c->n;
+    double *w = c->wv, *r = c->rv, *part = c->rv + npad;
+    constexpr int NQ = 8; // column chunks of the residual's matrix-vector product
+    HIPCHK(c, hipMemcpyAsync(w, c->z, (size_t)npad * 8, hipMemcpyDeviceToDevice, s0));
+    launch_solve_sigma(s0, w, c->A, ld, n, npad, c->Linv);
+    for (int it = 0; it < c->refine_iters; ++it) {
+        launch_residual(s0, gp, c->x, c->y, c->tab, c->z, w, NQ, part, r);
+        launch_solve_sigma(s0, r, c->A, ld, n, npad, c->Linv);
+        launch_axpy_dot(s0, w, r, c->z, n, npad, nullptr);
+    }
+    launch_axpy_dot(s0, w, nullptr, c->z, n, npad, c->out + 1);
+    HIPCHK(c, hipMemcpyAsync(c->h_out + 1, c->out + 1, sizeof(double), hipMemcpyDeviceToHost, s0));
+    HIPCHK(c, hipStreamSynchronize(s0));
+    c->factor_out[1] = c->h_out[1];
+    return FBT_OK;
+}
+
+bool refines(const fbt_ctx *c)
+{
+    return c->precision == FBT_MIXED_FP32_ALL && c->refine_iters > 0 && !c->batched;
+}
+
 fbt_status factorize(fbt_ctx *c, const double *th, int mode)
 {
     GenParams gp;
@@ -666,6 +701,8 @@ fbt_status factorize(fbt_ctx *c, const double *th, int mode)
     }
     c->factor_out[0] = c->h_out[0];
     c->factor_out[1] = c->h_out[1];
+    if (refines(c) && (st = refine_w(c, gp)) != FBT_OK)
+        return st;
     if (!std::isfinite(c->factor_out[0]) || !std::isfinite(c->factor_out[1]))
         return fail(c, FBT_ENONFINITE, "log-determinant or quadratic form is not finite");
     c->factor_valid = true;
@@ -713,7 +750,26 @@ fbt_status derivative_terms(fbt_ctx *c, const double *th, double terms[9])
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     tcollect(c);
-    return wphase_results(c, terms);
+    if ((st = wphase_results(c, terms)) != FBT_OK || !refines(c))
+        return st;
+    // u_i = w^T Sigma_i w with the refined w and Sigma_i regenerated (the W
+    // phase's u_i comes from the factor's y); pairs of 64 x 64 tiles as in the
+    // adjoint contraction
+    GenParams gp;
+    stage_theta(c, th, &gp);
+    const int64_t nt = (c->n + 63) / 64, pairs = nt * (nt + 1) / 2;
+    if (2 * pairs > (int64_t)c->T * (c->npad / 64) * 8)
+        return fail(c, FBT_EINVAL, "internal: quadratic-form partials exceed the partials buffer");
+    launch_adjoint(c->stream, gp, c->x, c->y, c->tab, nullptr, c->wv, c->partials);
+    launch_reduce_pairs(c->stream, c->partials, pairs, c->out + 10);
+    HIPCHK(c, hipMemcpyAsync(c->h_out + 10, c->out + 10, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    terms[4] = c->h_out[10];
+    terms[5] = c->h_out[11];
+    if (!std::isfinite(terms[4]) || !std::isfinite(terms[5]))
+        return fail(c, FBT_ENONFINITE, "a quadratic form is not finite");
+    return FBT_OK;
 }
 
 // Launches of the W phase on a factor in place (derivative matrices already
@@ -1738,6 +1794,15 @@ fbt_status fbt_set_precision(fbt_ctx *ctx, int32_t precision)
         (precision == FBT_MIXED_FP32_ALL || ctx->precision == FBT_MIXED_FP32_ALL))
         ctx->factor_valid = false;
     ctx->precision = precision;
+    return FBT_OK;
+}
+
+fbt_status fbt_set_refinement(fbt_ctx *ctx, int32_t iterations)
+{
+    if (!ctx || iterations < 0 || iterations > 16)
+        return fail(ctx, FBT_EINVAL, "refinement steps must be in [0, 16]");
+    ctx->refine_iters = iterations;
+    ctx->factor_valid = false;
     return FBT_OK;
 }
 

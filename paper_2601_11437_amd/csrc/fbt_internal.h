@@ -129,8 +129,9 @@ void launch_sygst_panel(hipStream_t s, const Fields &F, double *S2, int64_t ld, 
                         const double *A, int64_t r0, int64_t rows, int64_t krow,
                         const double *Linv, const double *Vd, int64_t vofs, int64_t sVd,
                         double *Y, int64_t ldy, int64_t ymofs, int64_t sY);
-// (the blocks among the first `skip` block rows of the trailing part are left out)
-// mixed: 0 FP64, 1 FP32 MFMA with FP32 sums per NB-deep slice, 2 BF16 operands
+// Rank-2k lower update of the trailing part (the blocks among the first `skip`
+// block rows are left out).  mixed: 0 FP64, 1 FP32 MFMA with FP32 sums per
+// NB-deep slice, 2 BF16 operands
 void launch_syr2k_lower(hipStream_t s, const Fields &F, double *S2, int64_t ld, int64_t mofs,
                         const double *A, int64_t t0, int nblk, int64_t kcol, int KS,
                         const double *Y, int64_t ldy, int64_t ymofs, int64_t sY, int skip,
@@ -148,6 +149,21 @@ void launch_sygst_reduce(hipStream_t s, const Fields &F, const double *S2, int64
 // caller's device arrays; flag[0] = 1 if an input is not finite
 void launch_pack_data(hipStream_t s, const double *locs, const double *zin, int64_t n, int64_t npad,
                       double *x, double *y, double *z, double *flag);
+// iterative refinement of w = Sigma^{-1} Z (FBT_MIXED_FP32_ALL): x <- L^{-1} x
+// (trans 0) or L^{-T} x (trans 1) on the block-lower factor with its diagonal
+// inverses; r = z - Sigma w with Sigma regenerated (part: npad x nq doubles);
+// x += d and out[0] = z^T x (d or out may be null)
+void launch_trsv(hipStream_t s, double *x, const double *L, int64_t ld, int64_t npad,
+                 const double *Linv, int trans);
+// x <- Sigma^{-1} x for x zero past n: L^{-1} with the bordered factor, the
+// border and padding entries cleared, then L^{-T}
+void launch_solve_sigma(hipStream_t s, double *x, const double *L, int64_t ld, int64_t n,
+                        int64_t npad, const double *Linv);
+void launch_residual(hipStream_t s, const GenParams &gp, const double *xs, const double *ys,
+                     const Node *tab, const double *z, const double *w, int nq, double *part,
+                     double *r);
+void launch_axpy_dot(hipStream_t s, double *x, const double *d, const double *z, int64_t n,
+                     int64_t npad, double *out);
 // adjoint gradient
 void launch_fill_identity(hipStream_t s, double *X, int64_t ld, int64_t rows, int64_t ncols);
 void launch_lauum(hipStream_t s, double *P, const double *X, int64_t ld, int64_t npad,

@@ -2051,6 +2051,202 @@ void launch_pack_data(hipStream_t s, const double *locs, const double *zin, int6
 }
 
 // ---------------------------------------------------------------------------
+// Iterative refinement of w = Sigma^{-1} Z on a factor whose trailing updates
+// ran in FP32 (FBT_MIXED_FP32_ALL): residuals r = Z - Sigma w in FP64 with the
+// entries of Sigma regenerated by the generation quadrature (no FP64 copy of
+// Sigma is kept), corrections from the factor by blocked triangular solves.
+// ---------------------------------------------------------------------------
+
+// Forward block step of x = L^{-1} x: x_k <- Linv_k x_k (one workgroup; thread
+// t owns row t of the block, fixed summation order).
+__global__ __launch_bounds__(256) void k_trsv_diag(double *x, int64_t krow, const double *Linv,
+                                                   int trans)
+{
+    __shared__ double xs[NB];
+    const int t = threadIdx.x;
+    xs[t] = x[krow + t];
+    __syncthreads();
+    double v = 0.0;
+    if (!trans) { // (Linv x)_t = sum_{j <= t} Linv[t][j] x_j
+        for (int j = 0; j <= t; ++j)
+            v = fma(Linv[t + (int64_t)j * NB], xs[j], v);
+    } else { // (Linv^T x)_t = sum_{j >= t} Linv[j][t] x_j
+        for (int j = t; j < NB; ++j)
+            v = fma(Linv[j + (int64_t)t * NB], xs[j], v);
+    }
+    x[krow + t] = v;
+}
+
+// Forward update: x[r] -= sum_j L[r][krow + j] x[krow + j] for rows r >= r0
+// (one thread per row; the block's 256 values staged in LDS).
+__global__ __launch_bounds__(256) void k_trsv_update(double *x, const double *L, int64_t ld,
+                                                     int64_t krow, int64_t r0, int64_t npad)
+{
+    __shared__ double xs[NB];
+    const int t = threadIdx.x;
+    xs[t] = x[krow + t];
+    __syncthreads();
+    const int64_t r = r0 + (int64_t)blockIdx.x * 256 + t;
+    if (r >= npad)
+        return;
+    double v = 0.0;
+    for (int j = 0; j < NB; ++j)
+        v = fma(L[r + (krow + j) * ld], xs[j], v);
+    x[r] -= v;
+}
+
+// Backward update of x = L^{-T} x after block k is solved: x[c] -= sum_i
+// L[krow + i][c] x[krow + i] for columns c < krow.  A workgroup takes 64
+// columns; its four waves split the block's 256 rows and the column sums are
+// added in a fixed order.
+__global__ __launch_bounds__(256) void k_trsv_update_t(double *x, const double *L, int64_t ld,
+                                                       int64_t krow)
+{
+    __shared__ double xs[NB];
+    __shared__ double part[4][64];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    xs[t] = x[krow + t];
+    __syncthreads();
+    const int64_t c = (int64_t)blockIdx.x * 64 + lane;
+    double v = 0.0;
+    if (c < krow)
+        for (int i = wv * 64; i < wv * 64 + 64; ++i)
+            v = fma(L[krow + i + c * ld], xs[i], v);
+    part[wv][lane] = v;
+    __syncthreads();
+    if (t < 64 && c < krow)
+        x[c] -= ((part[0][t] + part[1][t]) + part[2][t]) + part[3][t];
+}
+
+void launch_trsv(hipStream_t s, double *x, const double *L, int64_t ld, int64_t npad,
+                 const double *Linv, int trans)
+{
+    const int T = (int)(npad / NB);
+    if (!trans) {
+        for (int k = 0; k < T; ++k) {
+            const int64_t krow = (int64_t)k * NB;
+            hipLaunchKernelGGL(k_trsv_diag, dim3(1), dim3(256), 0, s, x, krow,
+                               Linv + (int64_t)k * NB * NB, 0);
+            if (krow + NB < npad)
+                hipLaunchKernelGGL(k_trsv_update, dim3((unsigned)((npad - krow - NB + 255) / 256)),
+                                   dim3(256), 0, s, x, L, ld, krow, krow + NB, npad);
+        }
+    } else {
+        for (int k = T - 1; k >= 0; --k) {
+            const int64_t krow = (int64_t)k * NB;
+            hipLaunchKernelGGL(k_trsv_diag, dim3(1), dim3(256), 0, s, x, krow,
+                               Linv + (int64_t)k * NB * NB, 1);
+            if (krow > 0)
+                hipLaunchKernelGGL(k_trsv_update_t, dim3((unsigned)(krow / 64)), dim3(256), 0, s,
+                                   x, L, ld, krow);
+        }
+    }
+}
+
+// Residual of the refinement, partial sums: part[a + npad q] = sum over the
+// q-th of `nq` column chunks of C(h_ab) w_b, for rows a < n (the entries of
+// Sigma regenerated as in k_gen; both triangles).  blockIdx.x: 64-row tile,
+// y: chunk; four waves split the chunk's columns and add in a fixed order.
+__global__ __launch_bounds__(256) void k_sigma_matvec(GenParams gp, const double *__restrict__ xs,
+                                                      const double *__restrict__ ys,
+                                                      const Node *__restrict__ gtab,
+                                                      const double *__restrict__ w, int nq,
+                                                      double *__restrict__ part)
+{
+    __shared__ Node tab[TAB_MAX];
+    __shared__ double red[4][64];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int ntab = gp.off[NLEV - 1] + gp.len[NLEV - 1];
+    for (int i = t; i < ntab; i += 256)
+        tab[i] = gtab[i];
+    const int64_t n = gp.n;
+    const int64_t a = (int64_t)blockIdx.x * 64 + lane;
+    const int64_t clen = (n + nq - 1) / nq, b0 = (int64_t)blockIdx.y * clen;
+    const int64_t b1 = b0 + clen < n ? b0 + clen : n;
+    const double xa = a < n ? xs[a] : 0.0, ya = a < n ? ys[a] : 0.0;
+    const double inv_alpha = 1.0 / gp.alpha;
+    __syncthreads();
+    double v = 0.0;
+    if (a < n)
+        for (int64_t b = b0 + wv; b < b1; b += 4) {
+            const double dx = xa - xs[b], dy = ya - ys[b];
+            double c, ca, cn;
+            matern3(gp, tab, sqrt(dx * dx + dy * dy) * inv_alpha, GEN_SIGMA, c, ca, cn);
+            v = fma(c, w[b], v);
+        }
+    red[wv][lane] = v;
+    __syncthreads();
+    if (t < 64)
+        part[a + gp.npad * (int64_t)blockIdx.y] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
+}
+
+// r[a] = z[a] - sum_q part[a + npad q] (a < n; 0 beyond), the chunks in order.
+__global__ __launch_bounds__(256) void k_residual(const double *z, const double *part, int nq,
+                                                  int64_t n, int64_t npad, double *r)
+{
+    const int64_t a = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (a >= npad)
+        return;
+    double v = 0.0;
+    for (int q = 0; q < nq; ++q)
+        v += part[a + npad * q];
+    r[a] = a < n ? z[a] - v : 0.0;
+}
+
+void launch_residual(hipStream_t s, const GenParams &gp, const double *xs, const double *ys,
+                     const Node *tab, const double *z, const double *w, int nq, double *part,
+                     double *r)
+{
+    const int64_t nt = (gp.n + 63) / 64;
+    hipLaunchKernelGGL(k_sigma_matvec, dim3((unsigned)nt, (unsigned)nq), dim3(256), 0, s, gp, xs,
+                       ys, tab, w, nq, part);
+    hipLaunchKernelGGL(k_residual, dim3((unsigned)((gp.npad + 255) / 256)), dim3(256), 0, s, z, part,
+                       nq, gp.n, gp.npad, r);
+}
+
+// x[a] = 0 for n <= a < npad: between the forward and the backward solve with
+// the bordered factor, whose row n (y^T, 1) must not feed back into x[< n]
+__global__ __launch_bounds__(256) void k_zero_tail(double *x, int64_t n, int64_t npad)
+{
+    const int64_t a = n + (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (a < npad)
+        x[a] = 0.0;
+}
+
+void launch_solve_sigma(hipStream_t s, double *x, const double *L, int64_t ld, int64_t n,
+                        int64_t npad, const double *Linv)
+{
+    launch_trsv(s, x, L, ld, npad, Linv, 0);
+    hipLaunchKernelGGL(k_zero_tail, dim3((unsigned)((npad - n + 255) / 256)), dim3(256), 0, s, x, n,
+                       npad);
+    launch_trsv(s, x, L, ld, npad, Linv, 1);
+}
+
+// x[a] += d[a] (a < npad); out[0] = sum_a z[a] x[a] over a < n when out is set
+// (one workgroup, fixed order)
+__global__ __launch_bounds__(256) void k_axpy_dot(double *x, const double *d, const double *z,
+                                                  int64_t n, int64_t npad, double *out)
+{
+    __shared__ double sh[4];
+    double v = 0.0;
+    for (int64_t a = threadIdx.x; a < npad; a += 256) {
+        const double xa = d ? x[a] + d[a] : x[a];
+        x[a] = xa;
+        if (a < n)
+            v = fma(z[a], xa, v);
+    }
+    v = block_sum(v, sh);
+    if (out && threadIdx.x == 0)
+        out[0] = v;
+}
+
+void launch_axpy_dot(hipStream_t s, double *x, const double *d, const double *z, int64_t n,
+                     int64_t npad, double *out)
+{
+    hipLaunchKernelGGL(k_axpy_dot, dim3(1), dim3(256), 0, s, x, d, z, n, npad, out);
+}
+
+// ---------------------------------------------------------------------------
 // Adjoint gradient (score without the W matrices).  With w = Sigma^{-1} Z,
 //   dl/dtheta_i = 1/2 w^T Sigma_i w - 1/2 tr(Sigma^{-1} Sigma_i)
 //               = sum_ab (1/2 w_a w_b - 1/2 (Sigma^{-1})_ab) (Sigma_i)_ab,
@@ -2176,7 +2372,8 @@ __global__ __launch_bounds__(256) void k_adjoint(GenParams gp, const double *__r
         const double dx = xa - xs[b], dy = ya - ys[b];
         double c, ca, cn;
         matern3(gp, tab, sqrt(dx * dx + dy * dy) * inv_alpha, GEN_DERIV, c, ca, cn);
-        const double g = fma(wa, w[b], -0.5 * P[a + b * ld]);
+        // without P: the plain quadratic form sum_ab w_a w_b (Sigma_i)_ab
+        const double g = P ? fma(wa, w[b], -0.5 * P[a + b * ld]) : wa * w[b];
         sa = fma(g, ca, sa);
         sn = fma(g, cn, sn);
     }

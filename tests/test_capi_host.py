@@ -52,6 +52,7 @@ def test_null_arguments_are_rejected():
     assert L.fbt_set_timing(None, 1) == fbt.EINVAL
     assert L.fbt_set_sigma_nu_mode(None, 0) == fbt.EINVAL
     assert L.fbt_set_wphase(None, fbt.WPHASE_TWO_SIDED) == fbt.EINVAL
+    assert L.fbt_set_refinement(None, 2) == fbt.EINVAL
     assert L.fbt_set_precision(None, 0) == fbt.EINVAL
     assert (fbt.FP64, fbt.MIXED_FP32, fbt.MIXED_FP32_ALL, fbt.MIXED_BF16) == (0, 1, 2, 3)
     L.fbt_destroy(None)                      # NULL-safe

@@ -1,0 +1,79 @@
+"""Whole Fisher-BT fits (Algorithm 1 from the L9 start of Table 1, the
+simulation bounds) on the 3 x 3 simulation grid of jittered 100 x 100 grids
+(n = 10,000; sigma2 = 1, beta in {0.03, 0.1, 0.3}, nu in {0.5, 1.0, 2.5}, one
+realisation per setting) against the oracle's fits of the same fields, stored
+by tests/golden/make_grid_fits.py.  A setting whose oracle fit has not been
+stored yet is skipped.
+
+For a fit that converges by scoring the GPU driver takes the oracle's path:
+the same numbers of log-likelihood and derivative evaluations, and theta-hat
+within 1e-6 relative (the evaluations agree to about 1e-12, the stopping test
+is taken on the score's 2-norm, and theta-hat is a stationary point, so its
+error is of the order of the score's error over the curvature).
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import paper_2601_11437_amd as fbt
+import synth
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "grid_fits_n10k_oracle.json")
+ORDER = [(ib, inu) for ib in range(3) for inu in range(3)]
+
+
+def _stored():
+    if not os.path.exists(GOLDEN):
+        return {}
+    with open(GOLDEN) as f:
+        return {(g["i_beta"], g["i_nu"]): g for g in json.load(f)["fits"]}
+
+
+STORED = _stored()
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = fbt.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("ib,inu", ORDER)
+def test_grid_fit_matches_oracle(ctx, ib, inu):
+    g = STORED.get((ib, inu))
+    if g is None:
+        pytest.skip("the oracle's fit of this setting has not been stored")
+    w = synth.grid_workload(ib, inu)
+    assert tuple(g["theta_true"]) == tuple(w["theta_true"]) and g["seed"] == w["seed"]
+    locs, z, info = synth.dataset(w["n"], w["theta_true"], w["seed"], design=w["design"])
+    assert info["redraws"] == g["redraws"]
+    ctx.set_data(locs, z)
+    say("grid fit beta=%g nu=%g" % (w["theta_true"][1], w["theta_true"][2]))
+    got = ctx.fit(lo=g["bounds"]["lower"], hi=g["bounds"]["upper"])
+    say("gpu %s (%d ll, %d grad, nm %s) oracle %s (%d ll, %d grad, nm %s)" % (
+        np.array2string(got["theta"], precision=10), got["n_loglik_calls"], got["n_grad_calls"],
+        bool(got["used_nelder_mead"]), g["theta"], g["n_loglik_calls"], g["n_grad_calls"],
+        g["used_nelder_mead"]))
+    assert bool(got["converged"]) == g["converged"]
+    assert bool(got["used_nelder_mead"]) == g["used_nelder_mead"]
+    if not g["used_nelder_mead"]:
+        assert (got["n_loglik_calls"], got["n_grad_calls"]) == \
+            (g["n_loglik_calls"], g["n_grad_calls"])
+        np.testing.assert_allclose(got["theta"], g["theta"], rtol=1e-6)
+        assert abs(got["loglik"] - g["loglik"]) <= 1e-10 * abs(g["loglik"])
+    else:
+        # Nelder-Mead's simplex path branches on comparisons of log-likelihoods
+        # that agree only to rounding: compare the optimum it reaches
+        assert abs(got["loglik"] - g["loglik"]) <= 1e-7 * abs(g["loglik"])
+        np.testing.assert_allclose(got["theta"], g["theta"], rtol=1e-3)

@@ -304,11 +304,14 @@ def test_mixed_bf16(ctx, oracle_mod, n, theta):
 @pytest.mark.parametrize("n,theta", [(600, (1.0, 0.1, 0.5)), (1500, (1.5, 0.07, 1.0))])
 def test_mixed_fp32_all(ctx, oracle_mod, n, theta):
     """FBT_MIXED_FP32_ALL: the Cholesky trailing updates in FP32 as well, so
-    the log-likelihood carries FP32 rounding of the factorisation (its
-    log-determinant cannot be refined); against the oracle (measured on
-    MI355X): loglik 1.9e-8 / 1.3e-5 relative, score 1.1e-7 / 3.0e-5 of its
-    per-term scale, Fisher 1.2e-6 / 3.0e-6 relative at n = 600 / 1,500.  Gates:
-    loglik 1e-4, score 3e-4, Fisher 1e-4.  A fit refuses the form."""
+    the log-likelihood carries FP32 rounding of the factorisation's
+    log-determinant (the quadratic form is refined, see
+    test_fp32_all_refinement); against the oracle (measured on MI355X with the
+    default two refinement steps): loglik 1.1e-7 / 2.6e-7 relative, score
+    1.6e-7 / 7.0e-8 of its per-term scale (the traces), Fisher 1.2e-6 / 3.0e-6
+    relative at n = 600 / 1,500 (without refinement: loglik 1.9e-8 / 1.3e-5,
+    score 1.1e-7 / 3.0e-5).  Gates: loglik 1e-4, score 3e-4, Fisher 1e-4.  A
+    fit refuses the form."""
     say("fp32-all n=%d theta=%s" % (n, theta))
     locs, z, _ = synth.dataset(n, (1.0, 0.1, 0.5), 3000 + n)
     ctx.set_data(locs, z)
@@ -334,6 +337,49 @@ def test_mixed_fp32_all(ctx, oracle_mod, n, theta):
     assert ll_only == ll
     assert e_ll <= 1e-4 and np.all(err <= 3e-4) and e_f <= 1e-4
     assert e_ll > 0                                     # the FP32 factorisation really ran
+
+
+@pytest.mark.parametrize("n,theta", [(600, (1.0, 0.1, 0.5)), (1500, (1.5, 0.07, 1.0))])
+def test_fp32_all_refinement(ctx, oracle_mod, n, theta):
+    """FBT_MIXED_FP32_ALL with iterative refinement of w = Sigma^{-1} Z (the
+    residual in FP64 with Sigma regenerated, corrections from the FP32-updated
+    factor): the quadratic forms q = Z^T Sigma^{-1} Z and u_i = w^T Sigma_i w
+    against the oracle, without refinement and after the default two steps.
+    Refinement leaves log det and the traces untouched (bitwise) and brings q
+    and u_i to FP64 accuracy (gate 1e-10 relative, and at least 100 times
+    below the unrefined error).  Measured on MI355X: unrefined 2.3e-7 - 5.0e-7
+    (n = 600) and 1.0e-5 - 3.7e-5 (n = 1,500), refined 8e-16 - 2.8e-15 and
+    2.2e-11 - 7.2e-11."""
+    say("fp32-all refinement n=%d theta=%s" % (n, theta))
+    locs, z, _ = synth.dataset(n, (1.0, 0.1, 0.5), 3000 + n)
+    ctx.set_data(locs, z)
+    want = oracle_mod.evaluate(locs, z, theta)
+    ctx.set_precision(fbt.MIXED_FP32_ALL)
+    try:
+        with pytest.raises(fbt.FisherBTError) as e:
+            ctx.set_refinement(17)
+        assert e.value.status == fbt.EINVAL
+        ctx.set_refinement(0)
+        t0 = ctx.eval_terms(theta)
+        ctx.set_refinement(2)
+        t2 = ctx.eval_terms(theta)
+        ll2 = ctx.loglik(theta)
+    finally:
+        ctx.set_refinement(2)
+        ctx.set_precision(fbt.FP64)
+    ref = np.array([want["quad"], want["wSw"]["a"], want["wSw"]["n"]])
+
+    def errs(t):
+        return np.abs(np.array([t[1], t[4], t[5]]) - ref) / np.abs(ref)
+
+    e0, e2 = errs(t0), errs(t2)
+    say("q, u_alpha, u_nu relative error: unrefined %s refined %s" % (e0, e2))
+    assert np.array_equal(t0[[0, 2, 3, 6, 7, 8]], t2[[0, 2, 3, 6, 7, 8]])
+    assert np.all(e2 <= 1e-10)
+    assert np.all(e2 <= 1e-2 * e0)
+    # the log-likelihood takes the refined q: only log det keeps FP32 rounding
+    ll_terms = -0.5 * n * np.log(2 * np.pi) - 0.5 * t2[0] - 0.5 * t2[1]
+    assert abs(ll2 - ll_terms) <= 1e-14 * abs(ll_terms)
 
 
 def test_mixed_fit_switches_to_fp64(ctx):
