@@ -281,7 +281,10 @@ const char *fbt_batch_last_error(const fbt_batch *b);
  *     call).  Adjoint-mode fields run after the graph, one by one.
  * Results are bitwise the same in both.  In this build FBT_BATCH_GRAPH is
  * switched off (its first capture and replay crashed the host process with a
- * segmentation fault; the cause is not identified): asking for it returns
+ * segmentation fault; a host-only check of the capture sequence against a
+ * recording stand-in of the runtime finds every stream joined, every waited
+ * event captured, no allocation or host wait inside the capture and every
+ * copy in bounds, so the cause is not identified): asking for it returns
  * FBT_EINVAL with the reason in fbt_batch_last_error.  Errors: FBT_EINVAL. */
 typedef enum { FBT_BATCH_WORKERS = 0, FBT_BATCH_GRAPH = 1 } fbt_batch_exec;
 fbt_status fbt_batch_set_exec(fbt_batch *b, int32_t exec);

@@ -285,8 +285,13 @@ const char *fbt_batch_last_error(const fbt_batch *b) { return b ? b->err.c_str()
 // The graph execution is switched off: its first capture and replay ended the
 // host process with a segmentation fault inside the capture / instantiate /
 // launch sequence, the cause is not identified, and the path stays closed
-// until it is.  Asking for it is an error; the code is kept for that work.
-constexpr bool GRAPH_EXEC_ENABLED = false;
+// until it is.  Asking for it is an error; the code is kept for that work
+// (FBT_GRAPH_EXEC=1 builds it in, for the host-only check of its capture
+// sequence against a recording stand-in of the runtime).
+#ifndef FBT_GRAPH_EXEC
+#define FBT_GRAPH_EXEC 0
+#endif
+constexpr bool GRAPH_EXEC_ENABLED = FBT_GRAPH_EXEC != 0;
 
 fbt_status fbt_batch_set_exec(fbt_batch *b, int32_t exec)
 {
