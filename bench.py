@@ -305,7 +305,7 @@ def precision_bench(args):
     import synth
 
     w = synth.WORKLOADS["n50k"]
-    n, theta = args.n if args.n != 20000 else w["n"], w["theta_true"]
+    n, theta = args.precision_n or w["n"], w["theta_true"]
     gen = synth.rng(w["seed"])
     locs = synth.uniform_locations(n, gen)
     z = synth.rff_field(locs, theta, gen)
@@ -416,6 +416,8 @@ def main():
                     help="instead of the evaluation rate, the 3x3 grid of FP64 fits at n=10,000")
     ap.add_argument("--precision", action="store_true",
                     help="instead of the evaluation rate, FP64 vs the mixed forms at n=50,000")
+    ap.add_argument("--precision-n", type=int, default=0,
+                    help="with --precision, the number of points (default 50,000)")
     ap.add_argument("--precision-fits", action="store_true",
                     help="with --precision, also one FP64 and two mixed Fisher-BT fits (minutes)")
     args = ap.parse_args()

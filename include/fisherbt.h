@@ -327,12 +327,14 @@ fbt_status fbt_set_sigma_nu_mode(fbt_ctx *ctx, int32_t mode);
 /* Iterative refinement under FBT_MIXED_FP32_ALL (ignored otherwise and in
  * batched groups): after the factorisation, `iterations` steps (default 2)
  *   w <- w + (L L^T)^{-1} (Z - Sigma w),   w_0 = (L L^T)^{-1} Z,
- * with the residual in FP64 and the entries of Sigma regenerated (no FP64
- * copy of Sigma), L the factor with FP32 trailing updates; then
- * Z^T Sigma^{-1} Z = Z^T w, and in fbt_eval w^T Sigma_i w with Sigma_i
- * regenerated.  Each step costs a regeneration of Sigma (both triangles) and
- * two triangular solves with the factor.  0 turns it off.
- * Errors: FBT_EINVAL (NULL context, iterations outside [0, 16]). */
+ * with the residual in FP64 from a copy of Sigma taken before the
+ * factorisation (8 npad^2 more bytes of device memory while the form is in
+ * use), L the factor with FP32 trailing updates; then Z^T Sigma^{-1} Z =
+ * Z^T w, and in fbt_eval w^T Sigma_i w from the derivative matrices.  Each
+ * step costs one product with Sigma and two triangular solves with the
+ * factor.  0 turns it off.
+ * Errors: FBT_EINVAL (NULL context, iterations outside [0, 16]); fbt_loglik
+ * and the evaluations return FBT_ENOMEM if the copy cannot be allocated. */
 fbt_status fbt_set_refinement(fbt_ctx *ctx, int32_t iterations);
 
 /* Form of the W phase of fbt_eval / fbt_eval_terms / fbt_fit: the matrices

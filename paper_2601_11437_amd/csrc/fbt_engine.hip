@@ -62,6 +62,8 @@ struct fbt_ctx {
     double *Linv = nullptr, *logdet = nullptr, *partials = nullptr, *out = nullptr;
     double *wv = nullptr; // w = Sigma^{-1} Z (adjoint gradient; refinement)
     double *rv = nullptr; // refinement: residual / correction (npad) and matvec partials (8 npad)
+    double *Sc = nullptr; // refinement: Sigma (both triangles) taken before the factorisation
+    size_t cap_sc = 0;
     int refine_iters = 2; // FBT_MIXED_FP32_ALL: refinement steps of w (fbt_set_refinement)
     int *info = nullptr;
     Node *tab = nullptr;   // per field: node table + paper-mode coefficients (TAB_BYTES)
@@ -121,6 +123,9 @@ constexpr int FACT_CU_RESERVE = 8;
 // trailing update, bounds each step, and a 2 NB-deep lookahead update would
 // lengthen the chain (its time is per-workgroup latency, not throughput).
 constexpr int FACT_SINGLE_TAIL = 40;
+// column chunks of the refinement's matrix-vector products (workgroups per
+// 256 rows; 79 x 8 at n = 20,000)
+constexpr int REFINE_NQ = 8;
 
 // node table followed by the paper-mode coefficient table (one upload)
 constexpr size_t TAB_BYTES = TAB_MAX * sizeof(Node) + PC_SIZE * sizeof(double);
@@ -374,6 +379,9 @@ void free_buffers(fbt_ctx *c)
     (void)hipFree(c->Pd);
     c->Ysl = c->Vd = c->Pd = nullptr;
     c->cap_ysl = c->cap_vd = c->cap_pd = 0;
+    (void)hipFree(c->Sc);
+    c->Sc = nullptr;
+    c->cap_sc = 0;
 }
 
 // Buffer sizes of the two-sided W phase per field (doubles)
@@ -418,6 +426,30 @@ bool use_two_sided(fbt_ctx *c, bool may_alloc = true)
         return ensure_sygst(c);
     return c->cap_ysl >= (size_t)c->G * sy_stride(c) * 8 &&
            c->cap_vd >= (size_t)c->G * vd_stride(c) * 8 && c->cap_pd >= (size_t)c->G * pd_stride() * 8;
+}
+
+// FBT_MIXED_FP32_ALL on a single field refines w = Sigma^{-1} Z (see refine_w)
+bool refines(const fbt_ctx *c)
+{
+    return c->precision == FBT_MIXED_FP32_ALL && c->refine_iters > 0 && !c->batched;
+}
+
+// The copy of Sigma that refinement takes its residuals from (npad x ld).
+bool ensure_sc(fbt_ctx *c)
+{
+    const size_t bytes = (size_t)c->npad * c->ld * sizeof(double);
+    if (bytes <= c->cap_sc)
+        return true;
+    (void)hipFree(c->Sc);
+    c->Sc = nullptr;
+    c->cap_sc = 0;
+    if (hipMalloc((void **)&c->Sc, bytes) != hipSuccess) {
+        c->Sc = nullptr;
+        (void)hipGetLastError();
+        return false;
+    }
+    c->cap_sc = bytes;
+    return true;
 }
 
 // The FP32 copies for the current fields (FBT_MIXED_FP32 and FBT_MIXED_BF16).  A failed
@@ -577,6 +609,8 @@ fbt_status factorize_enqueue(fbt_ctx *c, const GenParams &gp, int mode)
     launch_init_info(s0, c->info, c->G);
     TIMED(c, s0, KC_GEN, 0.0, launch_gen(s0, gp, c->d_gpa, c->F, c->x, c->y, c->z, A, c->S2,
                                            c->S2 + npad * ld, mode));
+    if (refines(c) && c->cap_sc >= (size_t)npad * ld * sizeof(double))
+        launch_copy_sym(s0, A, ld, n, c->Sc);
     // Block columns are taken in pairs (b, b + 1), and singly in the last
     // FACT_SINGLE_TAIL blocks.  On s0: diagonal block b, panel b, update of
     // block column b + 1 by panel b, diagonal block b + 1, panel b + 1.  The
@@ -651,21 +685,20 @@ void factor_results(fbt_ctx *c)
 
 // FBT_MIXED_FP32_ALL: the factor's trailing updates ran in FP32, so w =
 // Sigma^{-1} Z (and with it q = Z^T w) is won back by iterative refinement:
-// w from the factor, then c->refine_iters steps w += Sigma~^{-1} (Z - Sigma w)
-// with the residual in FP64 and the entries of Sigma regenerated (no FP64
-// copy of Sigma is kept), Sigma~ = L L^T the factor's matrix.  The log
-// determinant keeps the factor's rounding.  Sets c->factor_out[1] = Z^T w;
-// c->wv holds w.
-fbt_status refine_w(fbt_ctx *c, const GenParams &gp)
+// w_0 = L~^{-T} y with y = L~^{-1} Z from the bordered factor's row n, then
+// c->refine_iters steps w += Sigma~^{-1} (Z - Sigma w) with the residual in
+// FP64 from the copy of Sigma taken before the factorisation (c->Sc),
+// Sigma~ = L~ L~^T the factor's matrix.  The log determinant keeps the
+// factor's rounding.  Sets c->factor_out[1] = Z^T w; c->wv holds w.
+fbt_status refine_w(fbt_ctx *c)
 {
     hipStream_t s0 = c->stream;
     const int64_t npad = c->npad, ld = c->ld, n = c->n;
     double *w = c->wv, *r = c->rv, *part = c->rv + npad;
-    constexpr int NQ = 8; // column chunks of the residual's matrix-vector product
-    HIPCHK(c, hipMemcpyAsync(w, c->z, (size_t)npad * 8, hipMemcpyDeviceToDevice, s0));
-    launch_solve_sigma(s0, w, c->A, ld, n, npad, c->Linv);
+    launch_border_row(s0, c->A, ld, n, npad, w);
+    launch_trsv(s0, w, c->A, ld, npad, c->Linv, 1);
     for (int it = 0; it < c->refine_iters; ++it) {
-        launch_residual(s0, gp, c->x, c->y, c->tab, c->z, w, NQ, part, r);
+        launch_residual(s0, c->Sc, ld, n, npad, c->z, w, REFINE_NQ, part, r);
         launch_solve_sigma(s0, r, c->A, ld, n, npad, c->Linv);
         launch_axpy_dot(s0, w, r, c->z, n, npad, nullptr);
     }
@@ -676,17 +709,14 @@ fbt_status refine_w(fbt_ctx *c, const GenParams &gp)
     return FBT_OK;
 }
 
-bool refines(const fbt_ctx *c)
-{
-    return c->precision == FBT_MIXED_FP32_ALL && c->refine_iters > 0 && !c->batched;
-}
-
 fbt_status factorize(fbt_ctx *c, const double *th, int mode)
 {
     GenParams gp;
     fbt_status st = upload_theta(c, th, &gp);
     if (st != FBT_OK)
         return st;
+    if (refines(c) && !ensure_sc(c))
+        return fail(c, FBT_ENOMEM, "cannot allocate the copy of Sigma for refinement");
     if ((st = factorize_enqueue(c, gp, mode)) != FBT_OK)
         return st;
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -701,7 +731,7 @@ fbt_status factorize(fbt_ctx *c, const double *th, int mode)
     }
     c->factor_out[0] = c->h_out[0];
     c->factor_out[1] = c->h_out[1];
-    if (refines(c) && (st = refine_w(c, gp)) != FBT_OK)
+    if (refines(c) && (st = refine_w(c)) != FBT_OK)
         return st;
     if (!std::isfinite(c->factor_out[0]) || !std::isfinite(c->factor_out[1]))
         return fail(c, FBT_ENONFINITE, "log-determinant or quadratic form is not finite");
@@ -740,6 +770,15 @@ fbt_status derivative_terms(fbt_ctx *c, const double *th, double terms[9])
         return st;
     }
     c->factor_valid = false; // reuse is for one derivative evaluation only
+    if (refines(c)) {
+        // u_i = w^T Sigma_i w with the refined w, from the derivative matrices
+        // before the W phase overwrites them (its own u_i come from the
+        // factor's y); the W phase's launches are ordered after these on s0
+        const int64_t npad = c->npad, ld = c->ld;
+        for (int i = 0; i < 2; ++i)
+            launch_quad_form(s0, c->S2 + i * npad * ld, ld, c->n, npad, c->wv, REFINE_NQ,
+                             c->rv + npad, c->out + 10 + i);
+    }
     if (use_two_sided(c)) {
         if ((st = wphase_sygst_enqueue(c)) != FBT_OK)
             return st;
@@ -752,19 +791,6 @@ fbt_status derivative_terms(fbt_ctx *c, const double *th, double terms[9])
     tcollect(c);
     if ((st = wphase_results(c, terms)) != FBT_OK || !refines(c))
         return st;
-    // u_i = w^T Sigma_i w with the refined w and Sigma_i regenerated (the W
-    // phase's u_i comes from the factor's y); pairs of 64 x 64 tiles as in the
-    // adjoint contraction
-    GenParams gp;
-    stage_theta(c, th, &gp);
-    const int64_t nt = (c->n + 63) / 64, pairs = nt * (nt + 1) / 2;
-    if (2 * pairs > (int64_t)c->T * (c->npad / 64) * 8)
-        return fail(c, FBT_EINVAL, "internal: quadratic-form partials exceed the partials buffer");
-    launch_adjoint(c->stream, gp, c->x, c->y, c->tab, nullptr, c->wv, c->partials);
-    launch_reduce_pairs(c->stream, c->partials, pairs, c->out + 10);
-    HIPCHK(c, hipMemcpyAsync(c->h_out + 10, c->out + 10, 2 * sizeof(double), hipMemcpyDeviceToHost,
-                             c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
     terms[4] = c->h_out[10];
     terms[5] = c->h_out[11];
     if (!std::isfinite(terms[4]) || !std::isfinite(terms[5]))

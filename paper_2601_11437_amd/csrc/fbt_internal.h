@@ -151,17 +151,25 @@ void launch_pack_data(hipStream_t s, const double *locs, const double *zin, int6
                       double *x, double *y, double *z, double *flag);
 // iterative refinement of w = Sigma^{-1} Z (FBT_MIXED_FP32_ALL): x <- L^{-1} x
 // (trans 0) or L^{-T} x (trans 1) on the block-lower factor with its diagonal
-// inverses; r = z - Sigma w with Sigma regenerated (part: npad x nq doubles);
-// x += d and out[0] = z^T x (d or out may be null)
+// inverses
 void launch_trsv(hipStream_t s, double *x, const double *L, int64_t ld, int64_t npad,
                  const double *Linv, int trans);
-// x <- Sigma^{-1} x for x zero past n: L^{-1} with the bordered factor, the
-// border and padding entries cleared, then L^{-T}
+// x <- Sigma^{-1} x: L^{-1} with the bordered factor, the border and padding
+// entries cleared, then L^{-T}
 void launch_solve_sigma(hipStream_t s, double *x, const double *L, int64_t ld, int64_t n,
                         int64_t npad, const double *Linv);
-void launch_residual(hipStream_t s, const GenParams &gp, const double *xs, const double *ys,
-                     const Node *tab, const double *z, const double *w, int nq, double *part,
-                     double *r);
+// Sc (n x n, both triangles, leading dimension ld) = Sigma from A's lower triangle
+void launch_copy_sym(hipStream_t s, const double *A, int64_t ld, int64_t n, double *Sc);
+// r = z - Sc w (part: npad x nq doubles of partial products)
+void launch_residual(hipStream_t s, const double *Sc, int64_t ld, int64_t n, int64_t npad,
+                     const double *z, const double *w, int nq, double *part, double *r);
+// out[0] = w^T M w (M n x n, both triangles)
+void launch_quad_form(hipStream_t s, const double *M, int64_t ld, int64_t n, int64_t npad,
+                      const double *w, int nq, double *part, double *out);
+// w = row n of the bordered factor (y = L^{-1} Z), zero from n on
+void launch_border_row(hipStream_t s, const double *A, int64_t ld, int64_t n, int64_t npad,
+                       double *w);
+// x += d and out[0] = z^T x (d or out may be null)
 void launch_axpy_dot(hipStream_t s, double *x, const double *d, const double *z, int64_t n,
                      int64_t npad, double *out);
 // adjoint gradient

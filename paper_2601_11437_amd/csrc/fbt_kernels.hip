@@ -2052,70 +2052,140 @@ void launch_pack_data(hipStream_t s, const double *locs, const double *zin, int6
 
 // ---------------------------------------------------------------------------
 // Iterative refinement of w = Sigma^{-1} Z on a factor whose trailing updates
-// ran in FP32 (FBT_MIXED_FP32_ALL): residuals r = Z - Sigma w in FP64 with the
-// entries of Sigma regenerated by the generation quadrature (no FP64 copy of
-// Sigma is kept), corrections from the factor by blocked triangular solves.
+// ran in FP32 (FBT_MIXED_FP32_ALL): residuals r = Z - Sigma w in FP64 from a
+// copy of Sigma taken before the factorisation, corrections from the factor
+// by blocked triangular solves; and the quadratic forms w^T Sigma_i w from
+// the derivative matrices.  The matrix-vector products are HBM-bound (one
+// read of the matrix), the triangular solves latency-bound (one diagonal
+// step and one update per block).
 // ---------------------------------------------------------------------------
 
-// Forward block step of x = L^{-1} x: x_k <- Linv_k x_k (one workgroup; thread
-// t owns row t of the block, fixed summation order).
-__global__ __launch_bounds__(256) void k_trsv_diag(double *x, int64_t krow, const double *Linv,
-                                                   int trans)
+// Diagonal block step of the triangular solves: x_k <- Linv_k x_k (trans 0)
+// or Linv_k^T x_k (trans 1), one workgroup of 1024 threads with x_k staged in
+// LDS.  Linv_k's strict upper triangle is zero, so every row takes all 256
+// products.  trans 0: thread (t, q) sums the 64 products of row t with j in
+// [64 q, 64 q + 64) (a column slice is read coalesced over t), the four
+// partial sums are added in order.  trans 1: output t is column t of Linv_k
+// (contiguous) dotted with x_k; a wave takes 16 outputs, eight at a time with
+// all their loads issued first, and sums each over its lanes in a fixed
+// butterfly order.
+constexpr int TRSV_DT = 1024;
+__global__ __launch_bounds__(TRSV_DT) void k_trsv_diag(double *x, int64_t krow,
+                                                       const double *__restrict__ Linv, int trans)
 {
     __shared__ double xs[NB];
-    const int t = threadIdx.x;
-    xs[t] = x[krow + t];
+    __shared__ double part[4][NB];
+    const int tid = threadIdx.x;
+    if (tid < NB)
+        xs[tid] = x[krow + tid];
     __syncthreads();
-    double v = 0.0;
-    if (!trans) { // (Linv x)_t = sum_{j <= t} Linv[t][j] x_j
-        for (int j = 0; j <= t; ++j)
-            v = fma(Linv[t + (int64_t)j * NB], xs[j], v);
-    } else { // (Linv^T x)_t = sum_{j >= t} Linv[j][t] x_j
-        for (int j = t; j < NB; ++j)
-            v = fma(Linv[j + (int64_t)t * NB], xs[j], v);
+    if (!trans) {
+        const int t = tid & (NB - 1), q = tid >> 8;
+        const double *col = Linv + t + (int64_t)(64 * q) * NB;
+        double v0 = 0.0, v1 = 0.0;
+#pragma unroll 16
+        for (int j = 0; j < 64; j += 2) {
+            v0 = fma(col[(int64_t)j * NB], xs[64 * q + j], v0);
+            v1 = fma(col[(int64_t)(j + 1) * NB], xs[64 * q + j + 1], v1);
+        }
+        part[q][t] = v0 + v1;
+        __syncthreads();
+        if (tid < NB)
+            x[krow + tid] = ((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid];
+    } else {
+        const int lane = tid & 63, wv = tid >> 6;
+        const double x0 = xs[lane], x1 = xs[lane + 64], x2 = xs[lane + 128], x3 = xs[lane + 192];
+        for (int h = 0; h < 2; ++h) {
+            const int t0 = 16 * wv + 8 * h;
+            double c[8][4];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+                    c[u][m] = Linv[lane + 64 * m + (int64_t)(t0 + u) * NB];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                double v = fma(c[u][0], x0, c[u][1] * x1);
+                v = fma(c[u][2], x2, v);
+                v = fma(c[u][3], x3, v);
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1)
+                    v += __shfl_xor(v, off, 64);
+                if (lane == 0)
+                    part[0][t0 + u] = v;
+            }
+        }
+        __syncthreads();
+        if (tid < NB)
+            x[krow + tid] = part[0][tid];
     }
-    x[krow + t] = v;
 }
 
-// Forward update: x[r] -= sum_j L[r][krow + j] x[krow + j] for rows r >= r0
-// (one thread per row; the block's 256 values staged in LDS).
-__global__ __launch_bounds__(256) void k_trsv_update(double *x, const double *L, int64_t ld,
-                                                     int64_t krow, int64_t r0, int64_t npad)
-{
-    __shared__ double xs[NB];
-    const int t = threadIdx.x;
-    xs[t] = x[krow + t];
-    __syncthreads();
-    const int64_t r = r0 + (int64_t)blockIdx.x * 256 + t;
-    if (r >= npad)
-        return;
-    double v = 0.0;
-    for (int j = 0; j < NB; ++j)
-        v = fma(L[r + (krow + j) * ld], xs[j], v);
-    x[r] -= v;
-}
-
-// Backward update of x = L^{-T} x after block k is solved: x[c] -= sum_i
-// L[krow + i][c] x[krow + i] for columns c < krow.  A workgroup takes 64
-// columns; its four waves split the block's 256 rows and the column sums are
-// added in a fixed order.
-__global__ __launch_bounds__(256) void k_trsv_update_t(double *x, const double *L, int64_t ld,
-                                                       int64_t krow)
+// Forward update: x[r] -= sum_j L[r][krow + j] x[krow + j] for rows r0 <= r <
+// npad.  A workgroup takes 64 rows; thread (r, q) sums the 64 products with j
+// in [64 q, 64 q + 64) (coalesced over r), the four partial sums are added in
+// order.
+__global__ __launch_bounds__(256) void k_trsv_update(double *x, const double *__restrict__ L,
+                                                     int64_t ld, int64_t krow, int64_t r0,
+                                                     int64_t npad)
 {
     __shared__ double xs[NB];
     __shared__ double part[4][64];
+    const int t = threadIdx.x, rl = t & 63, q = t >> 6;
+    xs[t] = x[krow + t];
+    __syncthreads();
+    const int64_t r = r0 + (int64_t)blockIdx.x * 64 + rl;
+    double v0 = 0.0, v1 = 0.0;
+    if (r < npad) {
+        const double *row = L + r + (krow + 64 * q) * ld;
+#pragma unroll 16
+        for (int j = 0; j < 64; j += 2) {
+            v0 = fma(row[(int64_t)j * ld], xs[64 * q + j], v0);
+            v1 = fma(row[(int64_t)(j + 1) * ld], xs[64 * q + j + 1], v1);
+        }
+    }
+    part[q][rl] = v0 + v1;
+    __syncthreads();
+    if (t < 64 && r < npad)
+        x[r] -= ((part[0][t] + part[1][t]) + part[2][t]) + part[3][t];
+}
+
+// Backward update of x = L^{-T} x after block k is solved: x[c] -= sum_i
+// L[krow + i][c] x[krow + i] for columns c < krow.  A wave takes TRSV_CPW
+// columns: its lanes read each column's 256 entries of the block row (four
+// coalesced loads, all columns' loads issued first), and each column's
+// products are summed in a fixed order (the four loads, then a butterfly over
+// the lanes).  Four waves per workgroup.
+constexpr int TRSV_CPW = 8;
+__global__ __launch_bounds__(256) void k_trsv_update_t(double *x, const double *__restrict__ L,
+                                                       int64_t ld, int64_t krow)
+{
+    __shared__ double xs[NB];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     xs[t] = x[krow + t];
     __syncthreads();
-    const int64_t c = (int64_t)blockIdx.x * 64 + lane;
-    double v = 0.0;
-    if (c < krow)
-        for (int i = wv * 64; i < wv * 64 + 64; ++i)
-            v = fma(L[krow + i + c * ld], xs[i], v);
-    part[wv][lane] = v;
-    __syncthreads();
-    if (t < 64 && c < krow)
-        x[c] -= ((part[0][t] + part[1][t]) + part[2][t]) + part[3][t];
+    const double x0 = xs[lane], x1 = xs[lane + 64], x2 = xs[lane + 128], x3 = xs[lane + 192];
+    const int64_t c0 = ((int64_t)blockIdx.x * 4 + wv) * TRSV_CPW;
+    double e[TRSV_CPW][4];
+#pragma unroll
+    for (int j = 0; j < TRSV_CPW; ++j) {
+        const int64_t c = c0 + j < krow ? c0 + j : krow - 1; // in bounds; not stored
+        const double *col = L + krow + c * ld;
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            e[j][m] = col[lane + 64 * m];
+    }
+#pragma unroll
+    for (int j = 0; j < TRSV_CPW; ++j) {
+        double v = fma(e[j][0], x0, e[j][1] * x1);
+        v = fma(e[j][2], x2, v);
+        v = fma(e[j][3], x3, v);
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+            v += __shfl_xor(v, off, 64);
+        if (lane == 0 && c0 + j < krow)
+            x[c0 + j] -= v;
+    }
 }
 
 void launch_trsv(hipStream_t s, double *x, const double *L, int64_t ld, int64_t npad,
@@ -2125,59 +2195,94 @@ void launch_trsv(hipStream_t s, double *x, const double *L, int64_t ld, int64_t 
     if (!trans) {
         for (int k = 0; k < T; ++k) {
             const int64_t krow = (int64_t)k * NB;
-            hipLaunchKernelGGL(k_trsv_diag, dim3(1), dim3(256), 0, s, x, krow,
+            hipLaunchKernelGGL(k_trsv_diag, dim3(1), dim3(TRSV_DT), 0, s, x, krow,
                                Linv + (int64_t)k * NB * NB, 0);
             if (krow + NB < npad)
-                hipLaunchKernelGGL(k_trsv_update, dim3((unsigned)((npad - krow - NB + 255) / 256)),
+                hipLaunchKernelGGL(k_trsv_update, dim3((unsigned)((npad - krow - NB + 63) / 64)),
                                    dim3(256), 0, s, x, L, ld, krow, krow + NB, npad);
         }
     } else {
         for (int k = T - 1; k >= 0; --k) {
             const int64_t krow = (int64_t)k * NB;
-            hipLaunchKernelGGL(k_trsv_diag, dim3(1), dim3(256), 0, s, x, krow,
+            hipLaunchKernelGGL(k_trsv_diag, dim3(1), dim3(TRSV_DT), 0, s, x, krow,
                                Linv + (int64_t)k * NB * NB, 1);
             if (krow > 0)
-                hipLaunchKernelGGL(k_trsv_update_t, dim3((unsigned)(krow / 64)), dim3(256), 0, s,
-                                   x, L, ld, krow);
+                hipLaunchKernelGGL(k_trsv_update_t,
+                                   dim3((unsigned)((krow + 4 * TRSV_CPW - 1) / (4 * TRSV_CPW))),
+                                   dim3(256), 0, s, x, L, ld, krow);
         }
     }
 }
 
-// Residual of the refinement, partial sums: part[a + npad q] = sum over the
-// q-th of `nq` column chunks of C(h_ab) w_b, for rows a < n (the entries of
-// Sigma regenerated as in k_gen; both triangles).  blockIdx.x: 64-row tile,
-// y: chunk; four waves split the chunk's columns and add in a fixed order.
-__global__ __launch_bounds__(256) void k_sigma_matvec(GenParams gp, const double *__restrict__ xs,
-                                                      const double *__restrict__ ys,
-                                                      const Node *__restrict__ gtab,
-                                                      const double *__restrict__ w, int nq,
-                                                      double *__restrict__ part)
+// Sc = Sigma on rows and columns < n, both triangles, from the generated
+// lower triangle of A (before the factorisation overwrites it).  One 64 x 64
+// tile pair (ti >= tj) per workgroup, staged in LDS so that the mirrored
+// tile is written with coalesced stores; a diagonal tile takes its upper
+// part from its lower one.
+__global__ __launch_bounds__(256) void k_copy_sym(const double *A, int64_t ld, int64_t n,
+                                                  double *Sc)
 {
-    __shared__ Node tab[TAB_MAX];
-    __shared__ double red[4][64];
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const int ntab = gp.off[NLEV - 1] + gp.len[NLEV - 1];
-    for (int i = t; i < ntab; i += 256)
-        tab[i] = gtab[i];
-    const int64_t n = gp.n;
-    const int64_t a = (int64_t)blockIdx.x * 64 + lane;
+    __shared__ double T[64][65];
+    const int64_t p = blockIdx.x;
+    int64_t ti = (int64_t)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+    while ((ti + 1) * (ti + 2) / 2 <= p)
+        ++ti;
+    while (ti * (ti + 1) / 2 > p)
+        --ti;
+    const int64_t tj = p - ti * (ti + 1) / 2;
+    const int64_t a0 = ti * 64, b0 = tj * 64;
+    const int t = threadIdx.x, r = t & 63;
+    for (int cc = t >> 6; cc < 64; cc += 4) {
+        const int64_t a = a0 + r, b = b0 + cc;
+        double v = 0.0;
+        if (a < n && b < n)
+            v = (ti == tj && r < cc) ? A[b + a * ld] : A[a + b * ld];
+        T[r][cc] = v;
+    }
+    __syncthreads();
+    for (int cc = t >> 6; cc < 64; cc += 4) {
+        const int64_t a = a0 + r, b = b0 + cc;
+        if (a < n && b < n)
+            Sc[a + b * ld] = T[r][cc];
+        // mirrored tile: row b0 + r, column a0 + cc holds T[cc][r]
+        const int64_t a2 = b0 + r, b2 = a0 + cc;
+        if (ti != tj && a2 < n && b2 < n)
+            Sc[a2 + b2 * ld] = T[cc][r];
+    }
+}
+
+void launch_copy_sym(hipStream_t s, const double *A, int64_t ld, int64_t n, double *Sc)
+{
+    const int64_t nt = (n + 63) / 64, pairs = nt * (nt + 1) / 2;
+    hipLaunchKernelGGL(k_copy_sym, dim3((unsigned)pairs), dim3(256), 0, s, A, ld, n, Sc);
+}
+
+// Partial products part[a + npad q] = sum over the q-th of nq column chunks
+// of M[a][b] w[b] (a, b < n; M column-major, both triangles stored).  One
+// thread per row; the rows of a workgroup read each column coalesced.
+__global__ __launch_bounds__(256) void k_matvec_part(const double *__restrict__ M, int64_t ld,
+                                                     int64_t n, int64_t npad,
+                                                     const double *__restrict__ w, int nq,
+                                                     double *__restrict__ part)
+{
+    const int64_t a = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t clen = (n + nq - 1) / nq, b0 = (int64_t)blockIdx.y * clen;
     const int64_t b1 = b0 + clen < n ? b0 + clen : n;
-    const double xa = a < n ? xs[a] : 0.0, ya = a < n ? ys[a] : 0.0;
-    const double inv_alpha = 1.0 / gp.alpha;
-    __syncthreads();
-    double v = 0.0;
-    if (a < n)
-        for (int64_t b = b0 + wv; b < b1; b += 4) {
-            const double dx = xa - xs[b], dy = ya - ys[b];
-            double c, ca, cn;
-            matern3(gp, tab, sqrt(dx * dx + dy * dy) * inv_alpha, GEN_SIGMA, c, ca, cn);
-            v = fma(c, w[b], v);
-        }
-    red[wv][lane] = v;
-    __syncthreads();
-    if (t < 64)
-        part[a + gp.npad * (int64_t)blockIdx.y] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
+    if (a >= n)
+        return;
+    // four accumulators (columns b mod 4), added in a fixed order
+    double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+    int64_t b = b0;
+#pragma unroll 2
+    for (; b + 3 < b1; b += 4) {
+        v0 = fma(M[a + b * ld], w[b], v0);
+        v1 = fma(M[a + (b + 1) * ld], w[b + 1], v1);
+        v2 = fma(M[a + (b + 2) * ld], w[b + 2], v2);
+        v3 = fma(M[a + (b + 3) * ld], w[b + 3], v3);
+    }
+    for (; b < b1; ++b)
+        v0 = fma(M[a + b * ld], w[b], v0);
+    part[a + npad * (int64_t)blockIdx.y] = (v0 + v1) + (v2 + v3);
 }
 
 // r[a] = z[a] - sum_q part[a + npad q] (a < n; 0 beyond), the chunks in order.
@@ -2188,20 +2293,62 @@ __global__ __launch_bounds__(256) void k_residual(const double *z, const double 
     if (a >= npad)
         return;
     double v = 0.0;
-    for (int q = 0; q < nq; ++q)
-        v += part[a + npad * q];
+    if (a < n)
+        for (int q = 0; q < nq; ++q)
+            v += part[a + npad * q];
     r[a] = a < n ? z[a] - v : 0.0;
 }
 
-void launch_residual(hipStream_t s, const GenParams &gp, const double *xs, const double *ys,
-                     const Node *tab, const double *z, const double *w, int nq, double *part,
-                     double *r)
+void launch_residual(hipStream_t s, const double *Sc, int64_t ld, int64_t n, int64_t npad,
+                     const double *z, const double *w, int nq, double *part, double *r)
 {
-    const int64_t nt = (gp.n + 63) / 64;
-    hipLaunchKernelGGL(k_sigma_matvec, dim3((unsigned)nt, (unsigned)nq), dim3(256), 0, s, gp, xs,
-                       ys, tab, w, nq, part);
-    hipLaunchKernelGGL(k_residual, dim3((unsigned)((gp.npad + 255) / 256)), dim3(256), 0, s, z, part,
-                       nq, gp.n, gp.npad, r);
+    hipLaunchKernelGGL(k_matvec_part, dim3((unsigned)((n + 255) / 256), (unsigned)nq), dim3(256),
+                       0, s, Sc, ld, n, npad, w, nq, part);
+    hipLaunchKernelGGL(k_residual, dim3((unsigned)((npad + 255) / 256)), dim3(256), 0, s, z, part,
+                       nq, n, npad, r);
+}
+
+// out[0] = sum_a w[a] (sum_q part[a + npad q]) over a < n: w^T M w from the
+// partial products (one workgroup, fixed order)
+__global__ __launch_bounds__(256) void k_quad_form(const double *w, const double *part, int nq,
+                                                   int64_t n, int64_t npad, double *out)
+{
+    __shared__ double sh[4];
+    double v = 0.0;
+    for (int64_t a = threadIdx.x; a < n; a += 256) {
+        double m = 0.0;
+        for (int q = 0; q < nq; ++q)
+            m += part[a + npad * q];
+        v = fma(w[a], m, v);
+    }
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0)
+        out[0] = v;
+}
+
+void launch_quad_form(hipStream_t s, const double *M, int64_t ld, int64_t n, int64_t npad,
+                      const double *w, int nq, double *part, double *out)
+{
+    hipLaunchKernelGGL(k_matvec_part, dim3((unsigned)((n + 255) / 256), (unsigned)nq), dim3(256),
+                       0, s, M, ld, n, npad, w, nq, part);
+    hipLaunchKernelGGL(k_quad_form, dim3(1), dim3(256), 0, s, w, part, nq, n, npad, out);
+}
+
+// w[b] = A[n + b ld] (b < n), 0 for n <= b < npad: y = L^{-1} Z from the
+// bordered factor's row n
+__global__ __launch_bounds__(256) void k_border_row(const double *A, int64_t ld, int64_t n,
+                                                    int64_t npad, double *w)
+{
+    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (b < npad)
+        w[b] = b < n ? A[n + b * ld] : 0.0;
+}
+
+void launch_border_row(hipStream_t s, const double *A, int64_t ld, int64_t n, int64_t npad,
+                       double *w)
+{
+    hipLaunchKernelGGL(k_border_row, dim3((unsigned)((npad + 255) / 256)), dim3(256), 0, s, A, ld,
+                       n, npad, w);
 }
 
 // x[a] = 0 for n <= a < npad: between the forward and the backward solve with
@@ -2372,8 +2519,7 @@ __global__ __launch_bounds__(256) void k_adjoint(GenParams gp, const double *__r
         const double dx = xa - xs[b], dy = ya - ys[b];
         double c, ca, cn;
         matern3(gp, tab, sqrt(dx * dx + dy * dy) * inv_alpha, GEN_DERIV, c, ca, cn);
-        // without P: the plain quadratic form sum_ab w_a w_b (Sigma_i)_ab
-        const double g = P ? fma(wa, w[b], -0.5 * P[a + b * ld]) : wa * w[b];
+        const double g = fma(wa, w[b], -0.5 * P[a + b * ld]);
         sa = fma(g, ca, sa);
         sn = fma(g, cn, sn);
     }

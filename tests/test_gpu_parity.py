@@ -342,7 +342,7 @@ def test_mixed_fp32_all(ctx, oracle_mod, n, theta):
 @pytest.mark.parametrize("n,theta", [(600, (1.0, 0.1, 0.5)), (1500, (1.5, 0.07, 1.0))])
 def test_fp32_all_refinement(ctx, oracle_mod, n, theta):
     """FBT_MIXED_FP32_ALL with iterative refinement of w = Sigma^{-1} Z (the
-    residual in FP64 with Sigma regenerated, corrections from the FP32-updated
+    residual in FP64 from a copy of Sigma, corrections from the FP32-updated
     factor): the quadratic forms q = Z^T Sigma^{-1} Z and u_i = w^T Sigma_i w
     against the oracle, without refinement and after the default two steps.
     Refinement leaves log det and the traces untouched (bitwise) and brings q
