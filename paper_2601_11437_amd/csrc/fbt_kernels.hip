@@ -594,6 +594,18 @@ void launch_potrf_diag(hipStream_t s, const Fields &F, double *A, int64_t lda, i
                        Linv, logdet_part, info);
 }
 
+// Workgroups are dealt to MI355X's 8 XCDs round-robin by linear index, and
+// each XCD has its own L2.  xcd_tile renumbers a launch's tiles so that each
+// XCD takes a contiguous range of them: tiles that share operand panels
+// (neighbours in the tile order) then meet in one L2.  A bijection on
+// [0, total) for any total.
+constexpr int NXCD = 8;
+__device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t total)
+{
+    const int64_t x = bid % NXCD, i = bid / NXCD, q = total / NXCD, r = total % NXCD;
+    return x * q + (x < r ? x : r) + i;
+}
+
 // ---------------------------------------------------------------------------
 // FP64 MFMA tile engine.  A workgroup of 4 waves computes a (64 WM) x (64 WN)
 // tile of A * B^T, each wave a 64 x 64 block held as 4 x 4 MFMA accumulators.
@@ -1169,8 +1181,9 @@ __global__ __launch_bounds__(256) void k_update_lower(int nmat, int64_t sC, int6
     using TF = TileF<2, 2, false>;
     using TBF = TileB<2, 2, false>;
     __shared__ double lds[MIX == 2 ? (TBF::LDS + 3) / 4 : MIX ? (TF::LDS + 1) / 2 : TL::LDS];
-    const int64_t p = blockIdx.x >> 2;
-    const int s = blockIdx.x & 3;
+    const int64_t u = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t p = u >> 2;
+    const int s = u & 3;
     int64_t I = (int64_t)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
     while ((I + 1) * (I + 2) / 2 <= p)
         ++I;
@@ -1374,9 +1387,12 @@ __global__ __launch_bounds__(256) void k_update_nn(Fields F, int64_t sS, double 
     const int f = blockIdx.z; // field
     S += f * sS;
     L += f * F.sA;
-    const int64_t ct = blockIdx.x;
+    // row-major tile order (tiles of a row share the L panel), renumbered per XCD
+    const int64_t u = xcd_tile(blockIdx.x + (int64_t)blockIdx.y * gridDim.x,
+                               (int64_t)gridDim.x * gridDim.y);
+    const int64_t ct = u % gridDim.x;
     const int64_t c0 = (ct < half_tiles) ? 128 * ct : col_shift + 128 * (ct - half_tiles);
-    const int64_t m0 = r0 + 128 * (int64_t)blockIdx.y;
+    const int64_t m0 = r0 + 128 * (u / gridDim.x);
     double *C = S + m0 + c0 * ld;
     if constexpr (MIX == 2) {
         TBF::update(C, ld, L + m0 + krow * lda, lda, S + krow + c0 * ld, ld, K,
@@ -1854,8 +1870,9 @@ __global__ __launch_bounds__(256) void k_syr2k_lower(Fields F, double *S2, int64
                                                      int64_t ymofs, int64_t sY, int64_t p0)
 {
     __shared__ double lds[Syr2kLds<MIX>::N];
-    const int64_t p = p0 + (blockIdx.x >> 2);
-    const int s = blockIdx.x & 3;
+    const int64_t u = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t p = p0 + (u >> 2);
+    const int s = u & 3;
     int64_t I = (int64_t)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
     while ((I + 1) * (I + 2) / 2 <= p)
         ++I;
