@@ -337,13 +337,13 @@ def precision_bench(args):
         log("%s: loglik %.3f s, eval %.3f s" % (name, t1 - t0, t3 - t2))
     ctx.set_refinement(2)
     if args.precision_fits:
-        # Fisher-BT from the L9 start in FP64 and in the FP32, all-FP32 and BF16
-        # mixed forms (all switch to FP64 near the optimum).  No Nelder-Mead fallback: a
+        # Fisher-BT from the L9 start in FP64 and in the FP32 and BF16 mixed forms
+        # (both switch to FP64 near the optimum).  No Nelder-Mead fallback: a
         # fit that exhausts its derivative budget reports so (the fallback's
         # hundreds of log-likelihood calls would take minutes at this size).
         lo, hi = (0.01, 0.01, 0.01), (5.0, 5.0, 2.0)
         for name, prec in (("fp64", fbt.FP64), ("mixed_fp32", fbt.MIXED_FP32),
-                           ("mixed_fp32_all", fbt.MIXED_FP32_ALL), ("mixed_bf16", fbt.MIXED_BF16)):
+                           ("mixed_bf16", fbt.MIXED_BF16)):
             ctx.set_precision(prec)
             t0 = time.perf_counter()
             r = ctx.fit(lo=lo, hi=hi, nelder_mead=0, callback=lambda it, th, ll, g, fi: log(
@@ -356,12 +356,11 @@ def precision_bench(args):
                                 "n_grad_calls": r["n_grad_calls"], "converged": r["converged"],
                                 "used_nelder_mead": r["used_nelder_mead"],
                                 "precision_switch": r["precision_switch"],
-                                "n_fp64_retries": r["n_fp64_retries"],
                                 "grad_norm": float(np.linalg.norm(r["score"]))}
             log("%s fit: %.1f s, theta %s" % (name, dt, np.round(r["theta"], 7)))
         ctx.set_precision(fbt.FP64)
         t64 = np.array(res["fp64"]["fit"]["theta"])
-        for name in ("mixed_fp32", "mixed_fp32_all", "mixed_bf16"):
+        for name in ("mixed_fp32", "mixed_bf16"):
             tm = np.array(res[name]["fit"]["theta"])
             res[name]["fit"]["theta_rel_err_vs_fp64"] = (np.abs(tm - t64) / np.abs(t64)).tolist()
     ctx.close()
@@ -420,7 +419,7 @@ def main():
     ap.add_argument("--precision-n", type=int, default=0,
                     help="with --precision, the number of points (default 50,000)")
     ap.add_argument("--precision-fits", action="store_true",
-                    help="with --precision, also one FP64 and three mixed Fisher-BT fits (minutes)")
+                    help="with --precision, also one FP64 and two mixed Fisher-BT fits (minutes)")
     args = ap.parse_args()
     if args.grid and args.gpus == 1:
         grid_bench(args)

@@ -61,9 +61,7 @@ typedef enum {
  *   fbt_set_refinement), so the quadratic forms Z^T Sigma^{-1} Z and
  *   w^T Sigma_i w are FP64-accurate; the log-determinant and the traces keep
  *   FP32 rounding amplified by the conditioning of Sigma, and the
- *   factorisation can fail for ill-conditioned Sigma.  In fbt_fit the
- *   log-likelihood calls run in this form too until the precision switch
- *   (see fbt_fit_options.mixed_switch), FP64 after it.
+ *   factorisation can fail for ill-conditioned Sigma.  fbt_fit refuses it.
  * FBT_MIXED_BF16: as FBT_MIXED_FP32, with the operands of those updates
  *   rounded to bfloat16 (8-bit significand) and the products summed in FP32
  *   (v_mfma_f32_16x16x16_bf16).  The log-likelihood is the FP64 one; score and
@@ -184,10 +182,8 @@ typedef struct {
      * scales s = ((q + n) / (2 sigma2), (|t_a| + |u_a|) / 2, (|t_nu| + |u_nu|) / 2)
      * (t_i = tr(Sigma^-1 Sigma_i), u_i = w^T Sigma_i w, q = Z^T Sigma^-1 Z), the
      * context switches to FP64 for the rest of the fit and that theta is
-     * evaluated again in FP64 (on the same factor under FBT_MIXED_FP32, after
-     * a new FP64 factorisation under FBT_MIXED_FP32_ALL, whose log-likelihood
-     * calls switch with it); the re-evaluation is not counted as a grad call.
-     * 0 never switches.  The
+     * evaluated again in FP64 (on the same factor under FBT_MIXED_FP32); the
+     * re-evaluation is not counted as a grad call.  0 never switches.  The
      * context's precision is restored when fbt_fit returns.  Ignored by
      * fbt_fit_evaluator and under FBT_FP64. */
     double mixed_switch;
@@ -198,13 +194,9 @@ typedef struct {
     int32_t n_loglik_calls, n_grad_calls, n_iter, used_nelder_mead, converged, n_nm_evals;
     /* fbt_fit: the driver's derivative evaluations whose results are FP64
      * (all of them under FBT_FP64; under a mixed precision those from the
-     * switch on, the one at the switch point included, and those repeated in
-     * FP64), and the 0-based index of the derivative evaluation at which the
-     * switch happened (-1: none). */
+     * switch on, the one at the switch point included), and the 0-based index
+     * of the derivative evaluation at which the switch happened (-1: none). */
     int32_t n_fp64_evals, precision_switch;
-    /* fbt_fit under FBT_MIXED_FP32_ALL: log-likelihood and derivative calls
-     * whose all-FP32 factorisation failed and that were repeated in FP64. */
-    int32_t n_fp64_retries;
 } fbt_fit_result;
 
 void fbt_fit_options_default(fbt_fit_options *o);
@@ -212,13 +204,10 @@ void fbt_fit_options_default(fbt_fit_options *o);
 /* Algorithm 1 (Fisher-BT): L9 start, Fisher scoring phi = I^{-1} grad with the
  * relaxed Armijo backtracking of Eq. (4), stop at ||grad|| <= grad_tol, shift
  * to Nelder-Mead when a call budget is exceeded, then one Fisher evaluation
- * at the result.  Every l and derivative evaluation runs on the GPU.  Under
- * FBT_MIXED_FP32_ALL the log-likelihood calls before the precision switch
- * take the all-FP32 factorisation too (their log-determinant carries FP32
- * rounding, far below the changes the line search compares while the score
- * is large); a call whose factorisation fails in that form is repeated in
- * FP64 (fbt_fit_result.n_fp64_retries) and the fit stays in the form.
- * Errors: FBT_EINVAL, FBT_ENODATA, FBT_ENOTPD (every L9 candidate failed),
+ * at the result.  Every l and derivative evaluation runs on the GPU.
+ * Errors: FBT_EINVAL (also for a context in FBT_MIXED_FP32_ALL: its
+ * log-likelihood is not the FP64 one that the acceptance tests of Eq. (4)
+ * take), FBT_ENODATA, FBT_ENOTPD (every L9 candidate failed),
  * FBT_EBUDGET (budget exhausted with nelder_mead = 0; *out still holds the
  * last iterate), FBT_EDEVICE. */
 fbt_status fbt_fit(fbt_ctx *ctx, const fbt_fit_options *opt, fbt_fit_result *out);

@@ -49,7 +49,7 @@ class FitResult(ctypes.Structure):
     _fields_ = [("theta", _d * 3), ("loglik", _d), ("score", _d * 3), ("fisher", _d * 9),
                 ("n_loglik_calls", _i32), ("n_grad_calls", _i32), ("n_iter", _i32),
                 ("used_nelder_mead", _i32), ("converged", _i32), ("n_nm_evals", _i32),
-                ("n_fp64_evals", _i32), ("precision_switch", _i32), ("n_fp64_retries", _i32)]
+                ("n_fp64_evals", _i32), ("precision_switch", _i32)]
 
 
 class Config(ctypes.Structure):
@@ -195,7 +195,7 @@ def _result(r: FitResult) -> dict:
             "n_grad_calls": r.n_grad_calls, "n_iter": r.n_iter,
             "used_nelder_mead": bool(r.used_nelder_mead), "converged": bool(r.converged),
             "n_nm_evals": r.n_nm_evals, "n_fp64_evals": r.n_fp64_evals,
-            "precision_switch": r.precision_switch, "n_fp64_retries": r.n_fp64_retries}
+            "precision_switch": r.precision_switch}
 
 
 def fit_with(loglik, evaluate, **opts) -> dict:

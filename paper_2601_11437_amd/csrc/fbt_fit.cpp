@@ -25,7 +25,6 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
-#include <functional>
 #include <limits>
 
 namespace {
@@ -358,34 +357,11 @@ struct GpuFit {
     double sw;         // fbt_fit_options.mixed_switch
     int state;         // 1 once the derivatives run in FP64
     int calls, n_fp64, switch_at;
-    int fp64_retries; // calls repeated in FP64 after the all-FP32 factorisation failed
 };
-
-// Under FBT_MIXED_FP32_ALL a factorisation with FP32 trailing updates can
-// fail where the FP64 one succeeds (a nearly singular Sigma, such as the long
-// ranges among the L9 candidates): that call is repeated in FP64, and the fit
-// stays in the form.  Returns the call's status; *fp64 tells whether its
-// result is FP64.
-static fbt_status fp64_if_fp32_fails(GpuFit *g, const std::function<fbt_status()> &call,
-                                     bool *fp64)
-{
-    fbt_status s = call();
-    *fp64 = fbt::ctx_precision(g->ctx) == FBT_FP64;
-    if (s == FBT_ENOTPD && fbt::ctx_precision(g->ctx) == FBT_MIXED_FP32_ALL) {
-        fbt_set_precision(g->ctx, FBT_FP64);
-        s = call();
-        fbt_set_precision(g->ctx, FBT_MIXED_FP32_ALL);
-        *fp64 = true;
-        ++g->fp64_retries;
-    }
-    return s;
-}
 
 static fbt_status gpu_loglik(void *user, const double theta[3], double *ll)
 {
-    GpuFit *g = (GpuFit *)user;
-    bool fp64;
-    return fp64_if_fp32_fails(g, [&] { return fbt_loglik(g->ctx, theta, ll); }, &fp64);
+    return fbt_loglik(((GpuFit *)user)->ctx, theta, ll);
 }
 
 static fbt_status gpu_eval(void *user, const double theta[3], double *ll, double score[3],
@@ -393,12 +369,9 @@ static fbt_status gpu_eval(void *user, const double theta[3], double *ll, double
 {
     GpuFit *g = (GpuFit *)user;
     const int before = g->state;
-    bool fp64;
-    const fbt_status s = fp64_if_fp32_fails(
-        g, [&] { return fbt::fit_eval(g->ctx, theta, g->sw, &g->state, ll, score, fisher); },
-        &fp64);
+    const fbt_status s = fbt::fit_eval(g->ctx, theta, g->sw, &g->state, ll, score, fisher);
     if (s == FBT_OK) {
-        if (g->fp64_ctx || g->state || fp64)
+        if (g->fp64_ctx || g->state)
             ++g->n_fp64;
         if (!before && g->state)
             g->switch_at = g->calls;
@@ -412,14 +385,18 @@ fbt_status fbt_fit(fbt_ctx *ctx, const fbt_fit_options *opt, fbt_fit_result *out
     if (!ctx || !opt || !(opt->mixed_switch >= 0))
         return FBT_EINVAL;
     const int32_t prec = fbt::ctx_precision(ctx);
-    GpuFit g = {ctx, prec == FBT_FP64, opt->mixed_switch, 0, 0, 0, -1, 0};
+    // The line search's acceptance tests (Eq. (4)) take FP64 log-likelihoods;
+    // under FBT_MIXED_FP32_ALL fbt_loglik carries FP32 rounding of the
+    // factorisation, which no refinement of the solves removes.
+    if (prec == FBT_MIXED_FP32_ALL)
+        return FBT_EINVAL;
+    GpuFit g = {ctx, prec == FBT_FP64, opt->mixed_switch, 0, 0, 0, -1};
     fbt_evaluator ev = {&g, gpu_loglik, gpu_eval};
     const fbt_status s = fbt_fit_evaluator(&ev, opt, out);
     fbt_set_precision(ctx, prec);
     if (out && (s == FBT_OK || s == FBT_EBUDGET)) {
         out->n_fp64_evals = g.n_fp64;
         out->precision_switch = g.switch_at;
-        out->n_fp64_retries = g.fp64_retries;
     }
     return s;
 }

@@ -310,7 +310,8 @@ def test_mixed_fp32_all(ctx, oracle_mod, n, theta):
     default two refinement steps): loglik 1.1e-7 / 2.6e-7 relative, score
     1.6e-7 / 7.0e-8 of its per-term scale (the traces), Fisher 1.2e-6 / 3.0e-6
     relative at n = 600 / 1,500 (without refinement: loglik 1.9e-8 / 1.3e-5,
-    score 1.1e-7 / 3.0e-5).  Gates: loglik 1e-4, score 3e-4, Fisher 1e-4."""
+    score 1.1e-7 / 3.0e-5).  Gates: loglik 1e-4, score 3e-4, Fisher 1e-4.  A
+    fit refuses the form."""
     say("fp32-all n=%d theta=%s" % (n, theta))
     locs, z, _ = synth.dataset(n, (1.0, 0.1, 0.5), 3000 + n)
     ctx.set_data(locs, z)
@@ -319,6 +320,9 @@ def test_mixed_fp32_all(ctx, oracle_mod, n, theta):
     try:
         ll, score, fisher = ctx.eval(theta)
         ll_only = ctx.loglik(theta)
+        with pytest.raises(fbt.FisherBTError) as e:
+            ctx.fit()
+        assert e.value.status == fbt.EINVAL
     finally:
         ctx.set_precision(fbt.FP64)
     scale = np.array([(want["quad"] + n) / (2 * theta[0]),
@@ -376,37 +380,6 @@ def test_fp32_all_refinement(ctx, oracle_mod, n, theta):
     # the log-likelihood takes the refined q: only log det keeps FP32 rounding
     ll_terms = -0.5 * n * np.log(2 * np.pi) - 0.5 * t2[0] - 0.5 * t2[1]
     assert abs(ll2 - ll_terms) <= 1e-14 * abs(ll_terms)
-
-
-def test_fp32_all_fit(ctx):
-    """Fisher-BT in the all-FP32 form: log-likelihood calls and derivative
-    evaluations on the factorisation with FP32 trailing updates (w refined)
-    while the score is large, FP64 from the precision switch on, so every
-    stopping test is taken on an FP64 score.  The fit converges, switches, and
-    reaches the FP64 fit's theta-hat within 1e-5 relative; the context's
-    precision is restored."""
-    n = 2000
-    say("fp32-all fit n=%d" % n)
-    locs, z, _ = synth.dataset(n, (1.0, 0.1, 0.5), 2024)
-    ctx.set_data(locs, z)
-    r64 = ctx.fit()
-    ctx.set_precision(fbt.MIXED_FP32_ALL)
-    try:
-        ra = ctx.fit()
-        _, g_after, _ = ctx.eval((1.0, 0.1, 0.5))     # still the all-FP32 form
-    finally:
-        ctx.set_precision(fbt.FP64)
-    _, g64, _ = ctx.eval((1.0, 0.1, 0.5))
-    rel = np.abs(ra["theta"] - r64["theta"]) / np.abs(r64["theta"])
-    say("fp64", r64["theta"], r64["n_loglik_calls"], r64["n_grad_calls"], "fp32-all", ra["theta"],
-        ra["n_loglik_calls"], ra["n_grad_calls"], "switch at", ra["precision_switch"],
-        "fp64 evals", ra["n_fp64_evals"], "fp64 retries", ra["n_fp64_retries"], "rel", rel)
-    assert not np.array_equal(g_after, g64)
-    assert ra["converged"] and not ra["used_nelder_mead"]
-    assert 0 < ra["precision_switch"] < ra["n_grad_calls"]
-    assert ra["n_fp64_evals"] >= ra["n_grad_calls"] - ra["precision_switch"]
-    assert r64["n_fp64_retries"] == 0
-    assert np.all(rel <= 1e-5)
 
 
 def test_mixed_fit_switches_to_fp64(ctx):
