@@ -22,6 +22,10 @@ sys.path.insert(0, os.path.join(ROOT, "tests"))
 
 METRIC = "loglik+score+Fisher evals/s at n=20k, FP64 vs mixed; % of MFMA peak"
 PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_MFMA_TFLOPS = 157.3   # dense FP32 matrix peak of MI355X
+PEAK_BF16_MFMA_TFLOPS = 2500.0  # dense BF16 matrix peak of MI355X
+# timing classes whose updates the mixed forms run in low precision (two-sided W phase)
+LOWP_CLASSES = ("twosided_update", "twosided_lookahead", "deferred_update")
 PEAK_HBM_GBS = 8000.0
 # timing class -> kernel that implements it (for the counter summaries)
 DOMINANT_KERNEL = {"left_update": "k_update_nn", "cholesky_update": "k_update_lower",
@@ -194,7 +198,10 @@ def batch_bench(args):
     dt, (ll, sc, fi, st) = timed()
     b.close()
     ns = np.array([z.size for _, z in fields], dtype=np.float64)
-    exec_flops = float(np.sum(3.0 * ns ** 3)) * args.steps
+    # n^3 / 3 (factorisation) + 2 n^3 (two-sided W phase of both derivative
+    # matrices) per field: the algorithmic count, which the two-sided form
+    # executes (plus the diagonal blocks' zero padding)
+    exec_flops = float(np.sum(7.0 * ns ** 3 / 3.0)) * args.steps
     nf = len(fields)
     out = {"metric": "loglik+score+Fisher field evaluations/s, %d fields n~U[500,4000]" % nf,
            "value": nf * args.steps / dt, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
@@ -207,6 +214,7 @@ def batch_bench(args):
                       "exec": args.batch_exec},
            "tuning": tune,
            "ms_per_step_workers_untuned": 1e3 * dt_workers / args.steps,
+           "algorithmic_flops_per_round": exec_flops / args.steps,
            "executed_tflops": exec_flops / dt / 1e12,
            "fp64_frac": exec_flops / dt / 1e12 / PEAK_FP64_TFLOPS,
            "failed_fields": int(np.sum(st != fbt.OK))}
@@ -573,6 +581,24 @@ def main():
                              "generation of Sigma_alpha and Sigma_nu, W phase, trace reductions",
                         algorithmic=frac(2.0 * n ** 3, 1e3 * dt_w), executed=frac(w_exec, 1e3 * dt_w)),
     }
+    def mixed_roofline(form, peak_lowp):
+        # lower bound on a mixed evaluation's time with every flop at its unit's
+        # peak: the W phase's low-precision updates at the low-precision MFMA
+        # peak, the rest at the FP64 peak (flops per class from the FP64 run's
+        # timing classes: the schedule is the same)
+        if form is None or not two_sided:
+            return None
+        lowp = sum(tim[k]["flops"] for k in LOWP_CLASSES if k in tim) / args.steps
+        f64 = total_fl / args.steps - lowp
+        bound_ms = 1e3 * (f64 / (PEAK_FP64_TFLOPS * 1e12) + lowp / (peak_lowp * 1e12))
+        return {"fp64_flops": f64, "lowp_flops": lowp, "peak_fp64": PEAK_FP64_TFLOPS,
+                "peak_lowp": peak_lowp, "unit": "TFLOP/s", "bound_ms": bound_ms,
+                "frac": bound_ms / form["ms_per_step"]}
+
+    if mixed is not None:
+        mixed["roofline"] = mixed_roofline(mixed, PEAK_FP32_MFMA_TFLOPS)
+    if mixed_bf16 is not None:
+        mixed_bf16["roofline"] = mixed_roofline(mixed_bf16, PEAK_BF16_MFMA_TFLOPS)
     out = {
         "metric": METRIC,
         "value": evals_per_s,
