@@ -414,7 +414,7 @@ def main():
                     help="only run the 1 GiB copy used to scale the HBM byte counters")
     ap.add_argument("--batch", type=int, default=0,
                     help="instead of the n=20k evaluation, time one round over this many fields")
-    ap.add_argument("--batch-workers", type=int, default=8)
+    ap.add_argument("--batch-workers", type=int, default=2)
     ap.add_argument("--batch-exec", choices=("workers", "graph", "tuned"), default="tuned",
                     help="batch execution: worker threads, one HIP graph per round, or the "
                          "autotuner's choice of execution and group limits")

@@ -385,7 +385,7 @@ class Batch:
     SKIP, LOGLIK, EVAL, GRAD = 0, 1, 2, 3
     WORKERS, GRAPH = 0, 1
 
-    def __init__(self, workers: int = 8, device: int = 0, precision: int = FP64):
+    def __init__(self, workers: int = 2, device: int = 0, precision: int = FP64):
         cfg = Config(int(device), 0, int(precision), None)
         h = _p()
         st = lib().fbt_batch_create(ctypes.byref(cfg), int(workers), ctypes.byref(h))
