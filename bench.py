@@ -134,6 +134,26 @@ def measured_traffic(kernel):
     return b, "rocprofv3 --pmc, %s" % os.path.relpath(path, ROOT)
 
 
+def measured_gen_flops():
+    """FP64 vector flops of one generation launch of Sigma, Sigma_alpha and
+    Sigma_nu at the benchmark's n and theta, from the committed counter summary
+    (rocprofv3 --pmc SQ_INSTS_VALU_{FMA,ADD,MUL}_F64: 64 (2 FMA + ADD + MUL)
+    per launch).  None when there is none or the kernel source changed."""
+    path = os.path.join(ROOT, "profiles", "k_gen_n20k_valu.md")
+    if not os.path.exists(path):
+        return None, "no counter summary for k_gen"
+    rec = None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("valu_json:"):
+                rec = json.loads(line.split(":", 1)[1])
+    if rec is None:
+        return None, "counter summary has no valu_json line"
+    if rec["source_sha256"] != kernel_source_sha256():
+        return None, "kernel source changed since the counters were taken"
+    return rec["fp64_valu_flops_per_launch"], "rocprofv3 --pmc, %s" % os.path.relpath(path, ROOT)
+
+
 def copy_calibration():
     """A plain 1 GiB device-to-device copy, three times, for scaling the HBM
     byte counters (run under rocprofv3 --pmc)."""
@@ -320,11 +340,11 @@ def precision_bench(args):
     ctx = fbt.Context(0)
     ctx.set_data(locs, z)
     res = {}
-    # MIXED_FP32_ALL with its default two refinement steps of w, and without
-    for name, prec, refine in (("fp64", fbt.FP64, 2), ("mixed_fp32", fbt.MIXED_FP32, 2),
-                               ("mixed_fp32_all", fbt.MIXED_FP32_ALL, 2),
-                               ("mixed_fp32_all_unrefined", fbt.MIXED_FP32_ALL, 0),
-                               ("mixed_bf16", fbt.MIXED_BF16, 2)):
+    # MIXED_FP32_ALL as it is by default, and with two refinement steps of w
+    for name, prec, refine in (("fp64", fbt.FP64, 0), ("mixed_fp32", fbt.MIXED_FP32, 0),
+                               ("mixed_fp32_all", fbt.MIXED_FP32_ALL, 0),
+                               ("mixed_fp32_all_refined", fbt.MIXED_FP32_ALL, 2),
+                               ("mixed_bf16", fbt.MIXED_BF16, 0)):
         ctx.set_precision(prec)
         ctx.set_refinement(refine)
         try:
@@ -343,7 +363,7 @@ def precision_bench(args):
         res[name] = {"loglik": ll, "score": sc.tolist(), "fisher": fi.tolist(), "terms": terms.tolist(),
                      "loglik_s": t1 - t0, "eval_s": t3 - t2, "w_phase_s": t2 - t1}
         log("%s: loglik %.3f s, eval %.3f s" % (name, t1 - t0, t3 - t2))
-    ctx.set_refinement(2)
+    ctx.set_refinement(0)
     if args.precision_fits:
         # Fisher-BT from the L9 start in FP64 and in the FP32 and BF16 mixed forms
         # (both switch to FP64 near the optimum).  No Nelder-Mead fallback: a
@@ -377,7 +397,7 @@ def precision_bench(args):
     scale = np.array([(t[1] + n) / (2 * theta[0]), 0.5 * (abs(t[2]) + abs(t[4])),
                       0.5 * (abs(t[3]) + abs(t[5]))])
     fd = np.diag(np.array(ref["fisher"]))
-    for name in ("mixed_fp32", "mixed_fp32_all", "mixed_fp32_all_unrefined", "mixed_bf16"):
+    for name in ("mixed_fp32", "mixed_fp32_all", "mixed_fp32_all_refined", "mixed_bf16"):
         r = res[name]
         if "loglik" not in r:
             continue
@@ -595,6 +615,18 @@ def main():
                 "peak_lowp": peak_lowp, "unit": "TFLOP/s", "bound_ms": bound_ms,
                 "frac": bound_ms / form["ms_per_step"]}
 
+    # the generation (k_gen, all three matrices) is bound by FP64 vector
+    # arithmetic (the quadrature of K_nu), not by MFMA or HBM: its counted FP64
+    # vector flops over its launch time measured here, against the FP64 vector
+    # peak (256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz = 78.6 TFLOP/s)
+    gen_fl, gen_src = measured_gen_flops()
+    if "generation" in phases and gen_fl:
+        g = tim["generation"]
+        ach = gen_fl / (g["ms"] / g["launches"] * 1e-3) / 1e12
+        phases["generation"]["roofline"] = {"bound": "alu", "achieved": ach,
+                                            "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                                            "frac": ach / PEAK_FP64_TFLOPS,
+                                            "flops_per_launch": gen_fl, "source": gen_src}
     if mixed is not None:
         mixed["roofline"] = mixed_roofline(mixed, PEAK_FP32_MFMA_TFLOPS)
     if mixed_bf16 is not None:

@@ -56,12 +56,14 @@ typedef enum {
  *   quadratic form (so the log-likelihood and every line-search test), the
  *   Bessel terms, diagonal blocks, panels and all reductions stay FP64:
  *   fbt_loglik is unchanged and fbt_eval returns the FP64 log-likelihood.
- * FBT_MIXED_FP32_ALL: the Cholesky trailing updates in FP32 as well.  The
- *   solve for w = Sigma^{-1} Z is won back by iterative refinement (see
- *   fbt_set_refinement), so the quadratic forms Z^T Sigma^{-1} Z and
- *   w^T Sigma_i w are FP64-accurate; the log-determinant and the traces keep
- *   FP32 rounding amplified by the conditioning of Sigma, and the
- *   factorisation can fail for ill-conditioned Sigma.  fbt_fit refuses it.
+ * FBT_MIXED_FP32_ALL: the Cholesky trailing updates in FP32 as well, so
+ *   every term carries FP32 rounding of the factor amplified by the
+ *   conditioning of Sigma, and the factorisation can fail for
+ *   ill-conditioned Sigma.  The solve for w = Sigma^{-1} Z can be won back by
+ *   iterative refinement (fbt_set_refinement), which makes the quadratic
+ *   forms Z^T Sigma^{-1} Z and w^T Sigma_i w FP64-accurate; the
+ *   log-determinant and the traces keep the factor's rounding.  fbt_fit
+ *   refuses the form (its line-search tests take FP64 log-likelihoods).
  * FBT_MIXED_BF16: as FBT_MIXED_FP32, with the operands of those updates
  *   rounded to bfloat16 (8-bit significand) and the products summed in FP32
  *   (v_mfma_f32_16x16x16_bf16).  The log-likelihood is the FP64 one; score and
@@ -328,14 +330,20 @@ typedef enum { FBT_SIGMA_NU_EXACT = 0, FBT_SIGMA_NU_PAPER = 1 } fbt_sigma_nu_mod
 fbt_status fbt_set_sigma_nu_mode(fbt_ctx *ctx, int32_t mode);
 
 /* Iterative refinement under FBT_MIXED_FP32_ALL (ignored otherwise and in
- * batched groups): after the factorisation, `iterations` steps (default 2)
+ * batched groups): after the factorisation, `iterations` steps (default 0)
  *   w <- w + (L L^T)^{-1} (Z - Sigma w),   w_0 = (L L^T)^{-1} Z,
  * with the residual in FP64 from a copy of Sigma taken before the
  * factorisation (8 npad^2 more bytes of device memory while the form is in
  * use), L the factor with FP32 trailing updates; then Z^T Sigma^{-1} Z =
  * Z^T w, and in fbt_eval w^T Sigma_i w from the derivative matrices.  Each
  * step costs one product with Sigma and two triangular solves with the
- * factor.  0 turns it off.
+ * factor.  The log-likelihood and score are not always closer to FP64 with
+ * it: without refinement every term is that of the factor's own matrix
+ * L L^T, and near the data's maximum-likelihood theta the first-order errors
+ * of the log-determinant / traces and of the quadratic forms cancel (the
+ * derivative of l in Sigma, (w w^T - Sigma^{-1}) / 2, averages to zero
+ * there); refinement removes the second part only.  Far from it refinement
+ * helps.  Hence the default 0.
  * Errors: FBT_EINVAL (NULL context, iterations outside [0, 16]); fbt_loglik
  * and the evaluations return FBT_ENOMEM if the copy cannot be allocated. */
 fbt_status fbt_set_refinement(fbt_ctx *ctx, int32_t iterations);

@@ -359,8 +359,8 @@ class Context:
         self._check(lib().fbt_set_wphase(self._h, int(form)))
 
     def set_refinement(self, iterations: int):
-        """Refinement steps of w = Sigma^{-1} Z under MIXED_FP32_ALL (default 2;
-        0 turns it off)."""
+        """Refinement steps of w = Sigma^{-1} Z under MIXED_FP32_ALL (default
+        0: off)."""
         self._check(lib().fbt_set_refinement(self._h, int(iterations)))
 
     def set_timing(self, enable: bool):

@@ -64,7 +64,7 @@ struct fbt_ctx {
     double *rv = nullptr; // refinement: residual / correction (npad) and matvec partials (8 npad)
     double *Sc = nullptr; // refinement: Sigma (both triangles) taken before the factorisation
     size_t cap_sc = 0;
-    int refine_iters = 2; // FBT_MIXED_FP32_ALL: refinement steps of w (fbt_set_refinement)
+    int refine_iters = 0; // FBT_MIXED_FP32_ALL: refinement steps of w (fbt_set_refinement)
     int *info = nullptr;
     Node *tab = nullptr;   // per field: node table + paper-mode coefficients (TAB_BYTES)
     Node *h_tab = nullptr; // pinned staging

@@ -304,14 +304,12 @@ def test_mixed_bf16(ctx, oracle_mod, n, theta):
 @pytest.mark.parametrize("n,theta", [(600, (1.0, 0.1, 0.5)), (1500, (1.5, 0.07, 1.0))])
 def test_mixed_fp32_all(ctx, oracle_mod, n, theta):
     """FBT_MIXED_FP32_ALL: the Cholesky trailing updates in FP32 as well, so
-    the log-likelihood carries FP32 rounding of the factorisation's
-    log-determinant (the quadratic form is refined, see
-    test_fp32_all_refinement); against the oracle (measured on MI355X with the
-    default two refinement steps): loglik 1.1e-7 / 2.6e-7 relative, score
-    1.6e-7 / 7.0e-8 of its per-term scale (the traces), Fisher 1.2e-6 / 3.0e-6
-    relative at n = 600 / 1,500 (without refinement: loglik 1.9e-8 / 1.3e-5,
-    score 1.1e-7 / 3.0e-5).  Gates: loglik 1e-4, score 3e-4, Fisher 1e-4.  A
-    fit refuses the form."""
+    every term carries FP32 rounding of the factor; against the oracle
+    (measured on MI355X, no refinement, the default): loglik 1.9e-8 / 1.3e-5
+    relative, score 1.1e-7 / 3.0e-5 of its per-term scale, Fisher 1.2e-6 /
+    3.0e-6 relative at n = 600 / 1,500 (with two refinement steps: loglik
+    1.1e-7 / 2.6e-7, score 1.6e-7 / 7.0e-8, see test_fp32_all_refinement).
+    Gates: loglik 1e-4, score 3e-4, Fisher 1e-4.  A fit refuses the form."""
     say("fp32-all n=%d theta=%s" % (n, theta))
     locs, z, _ = synth.dataset(n, (1.0, 0.1, 0.5), 3000 + n)
     ctx.set_data(locs, z)
@@ -344,12 +342,15 @@ def test_fp32_all_refinement(ctx, oracle_mod, n, theta):
     """FBT_MIXED_FP32_ALL with iterative refinement of w = Sigma^{-1} Z (the
     residual in FP64 from a copy of Sigma, corrections from the FP32-updated
     factor): the quadratic forms q = Z^T Sigma^{-1} Z and u_i = w^T Sigma_i w
-    against the oracle, without refinement and after the default two steps.
+    against the oracle, without refinement (the default) and after two steps.
     Refinement leaves log det and the traces untouched (bitwise) and brings q
     and u_i to FP64 accuracy (gate 1e-10 relative, and at least 100 times
     below the unrefined error).  Measured on MI355X: unrefined 2.3e-7 - 5.0e-7
-    (n = 600) and 1.0e-5 - 3.7e-5 (n = 1,500), refined 8e-16 - 2.8e-15 and
-    2.2e-11 - 7.2e-11."""
+    (n = 600) and 1.0e-5 - 3.7e-5 (n = 1,500), refined 8e-16 - 3.1e-15 and
+    2.2e-11 - 7.3e-11.  The log-likelihood and score assembled from either
+    set of terms are reported: refinement removes the quadratic forms' share
+    of the error but not log det's and the traces', with which it partly
+    cancels, so they need not get closer to the oracle."""
     say("fp32-all refinement n=%d theta=%s" % (n, theta))
     locs, z, _ = synth.dataset(n, (1.0, 0.1, 0.5), 3000 + n)
     ctx.set_data(locs, z)
@@ -365,9 +366,19 @@ def test_fp32_all_refinement(ctx, oracle_mod, n, theta):
         t2 = ctx.eval_terms(theta)
         ll2 = ctx.loglik(theta)
     finally:
-        ctx.set_refinement(2)
+        ctx.set_refinement(0)
         ctx.set_precision(fbt.FP64)
     ref = np.array([want["quad"], want["wSw"]["a"], want["wSw"]["n"]])
+    # the log-likelihood and score from each set of terms, against the oracle
+    # (reported: whether refinement brings them closer depends on theta)
+    for tag, t in (("unrefined", t0), ("refined", t2)):
+        ll_t = -0.5 * n * np.log(2 * np.pi) - 0.5 * t[0] - 0.5 * t[1]
+        sc_t = np.array([(t[1] - n) / (2 * theta[0]), 0.5 * (t[4] - t[2]), 0.5 * (t[5] - t[3])])
+        scale = np.array([(want["quad"] + n) / (2 * theta[0]),
+                          0.5 * (abs(want["trace"]["a"]) + abs(want["wSw"]["a"])),
+                          0.5 * (abs(want["trace"]["n"]) + abs(want["wSw"]["n"]))])
+        say("%s: loglik %.2e score/scale %s" % (tag, abs(ll_t - want["loglik"]) / abs(want["loglik"]),
+                                                 np.abs(sc_t - want["score"]) / scale))
 
     def errs(t):
         return np.abs(np.array([t[1], t[4], t[5]]) - ref) / np.abs(ref)
