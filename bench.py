@@ -468,8 +468,8 @@ def main():
         cpu_full(args)
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the single-field evaluation is not sharded "
-              "across GPUs in this build (see the design notes); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library does not shard the single-field "
+              "evaluation across GPUs (see the design notes); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

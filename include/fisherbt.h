@@ -284,8 +284,7 @@ const char *fbt_batch_last_error(const fbt_batch *b);
  *     only when the fields, the modes, the group limits or the precision
  *     change; other calls replay it with their theta (one graph launch per
  *     call).  Adjoint-mode fields run after the graph, one by one.
- * Results are bitwise the same in both.  In this build FBT_BATCH_GRAPH is
- * switched off (its first capture and replay crashed the host process with a
+ * Results are bitwise the same in both.  FBT_BATCH_GRAPH is switched off (its first capture and replay crashed the host process with a
  * segmentation fault; a host-only check of the capture sequence against a
  * recording stand-in of the runtime finds every stream joined, every waited
  * event captured, no allocation or host wait inside the capture and every

@@ -298,8 +298,8 @@ fbt_status fbt_batch_set_exec(fbt_batch *b, int32_t exec)
     if (!b || (exec != FBT_BATCH_WORKERS && exec != FBT_BATCH_GRAPH))
         return FBT_EINVAL;
     if (exec == FBT_BATCH_GRAPH && !GRAPH_EXEC_ENABLED) {
-        b->err = "batch: the graph execution is disabled in this build (its capture crashed the "
-                 "host process; cause not identified)";
+        b->err = "batch: the graph execution is disabled (its capture crashed the host process; "
+                 "cause not identified)";
         return FBT_EINVAL;
     }
     b->exec = exec;
