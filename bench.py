@@ -570,9 +570,15 @@ def main():
     d = tim[dom]
     achieved = d["flops"] / (d["ms"] * 1e-3) / 1e12
     traffic, traffic_src = measured_traffic(DOMINANT_KERNEL.get(dom, dom))
+    # the counted L2-miss bytes over the launch time: the kernel's rate against
+    # the HBM peak (an upper bound on its HBM traffic; the Infinity Cache serves
+    # part of the misses)
+    traffic_gbs = traffic / (d["ms"] / d["launches"] * 1e-3) / 1e9 if traffic else None
     roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
                 "traffic_unit": "bytes per launch", "traffic_source": traffic_src,
+                "traffic_GBps": traffic_gbs,
+                "traffic_frac_hbm_peak": traffic_gbs / PEAK_HBM_GBS if traffic_gbs else None,
                 "launches": d["launches"], "avg_launch_ms": d["ms"] / d["launches"],
                 "flops_per_launch": d["flops"] / d["launches"]}
     total_fl = sum(v["flops"] for v in tim.values())
