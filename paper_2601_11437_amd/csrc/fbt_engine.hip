@@ -123,6 +123,11 @@ constexpr int FACT_CU_RESERVE = 8;
 // trailing update, bounds each step, and a 2 NB-deep lookahead update would
 // lengthen the chain (its time is per-workgroup latency, not throughput).
 constexpr int FACT_SINGLE_TAIL = 40;
+// While more than FACT_QUAD_ABOVE blocks remain the steps take four block
+// columns: the trailing matrix is large, the chain has slack, and the bulk
+// update runs 1,024 deep per pass over its C tiles instead of 512 (bitwise
+// the same results).
+constexpr int FACT_QUAD_ABOVE = 48;
 // column chunks of the refinement's matrix-vector products (workgroups per
 // 256 rows; 79 x 8 at n = 20,000)
 constexpr int REFINE_NQ = 8;
@@ -611,16 +616,20 @@ fbt_status factorize_enqueue(fbt_ctx *c, const GenParams &gp, int mode)
                                            c->S2 + npad * ld, mode));
     if (refines(c) && c->cap_sc >= (size_t)npad * ld * sizeof(double))
         launch_copy_sym(s0, A, ld, n, c->Sc);
-    // Block columns are taken in pairs (b, b + 1), and singly in the last
-    // FACT_SINGLE_TAIL blocks.  On s0: diagonal block b, panel b, update of
-    // block column b + 1 by panel b, diagonal block b + 1, panel b + 1.  The
-    // trailing matrix is then updated by the step's panels at once (K = nb NB):
-    // s0 updates the next step's block columns (lookahead) once s1 has finished
-    // the previous bulk update; s1 updates the rest.  A K = 2 NB update is the
-    // FMA sequence of two NB-deep ones (C lives in the accumulators), so the
-    // step widths do not change the results.
+    // Block columns are taken four at a time while more than FACT_QUAD_ABOVE
+    // blocks remain, then in pairs, and singly in the last FACT_SINGLE_TAIL
+    // blocks.  On s0, for each block column b + j of a step of width nb:
+    // update of block columns b + j .. b + nb - 1 by panel b + j - 1 (j > 0),
+    // diagonal block b + j, panel b + j.  The trailing matrix is then updated
+    // by the step's panels at once (K = nb NB): s0 updates the next step's
+    // block columns (lookahead) once s1 has finished the previous bulk update;
+    // s1 updates the rest.  A K = 2 NB or 4 NB update is the FMA sequence of
+    // NB-deep ones in order (C lives in the accumulators), so the step widths
+    // do not change the results.
     auto rows_from = [&](int64_t r) { return (double)std::max<int64_t>(0, n - r); };
-    auto width = [&](int b) { return T - b <= FACT_SINGLE_TAIL ? 1 : std::min(2, T - b); };
+    auto width = [&](int b) {
+        return T - b <= FACT_SINGLE_TAIL ? 1 : T - b > FACT_QUAD_ABOVE ? 4 : std::min(2, T - b);
+    };
     HIPCHK(c, ev_record(c->evB, s0));
     for (int b = 0, nb = 1; b < T; b += nb) {
         nb = width(b);
@@ -631,16 +640,20 @@ fbt_status factorize_enqueue(fbt_ctx *c, const GenParams &gp, int mode)
         if (b + 1 < T)
             TIMED(c, s0, KC_PANEL, rows_from(r0 + NB) * dNB * dNB,
                   launch_panel(s0, c->F, A + r0 + NB + r0 * ld, ld, npad - r0 - NB, Lk(b)));
-        if (nb == 2) {
-            const int64_t r1 = r0 + NB;
-            TIMED(c, s0, KC_SYRK, 2.0 * rows_from(r1) * dNB * dNB,
-                  launch_update_rect(s0, c->F, c->F.sA, c->F.sA, 1, A + r1 + r1 * ld, nullptr, ld, A + r1 + r0 * ld, nullptr,
-                                     ld, A + r1 + r0 * ld, ld, npad - r1, NB, NB, mix));
+        // the step's further block columns: each by the panels before it in
+        // the step, then its diagonal block and panel
+        for (int j = 1; j < nb; ++j) {
+            const int64_t rj = r0 + (int64_t)j * NB, rp = rj - NB;
+            TIMED(c, s0, KC_SYRK, 2.0 * rows_from(rj) * (double)(nb - j) * dNB * dNB,
+                  launch_update_rect(s0, c->F, c->F.sA, c->F.sA, 1, A + rj + rj * ld, nullptr, ld,
+                                     A + rj + rp * ld, nullptr, ld, A + rj + rp * ld, ld, npad - rj,
+                                     (int64_t)(nb - j) * NB, NB, mix));
             TIMED(c, s0, KC_DIAG, 2.0 * dNB * dNB * dNB / 3.0,
-                  launch_potrf_diag(s0, c->F, A, ld, b + 1, n, Lk(b + 1), c->logdet, c->info));
-            if (b + 2 < T)
-                TIMED(c, s0, KC_PANEL, rows_from(rn) * dNB * dNB,
-                      launch_panel(s0, c->F, A + rn + r1 * ld, ld, npad - rn, Lk(b + 1)));
+                  launch_potrf_diag(s0, c->F, A, ld, b + j, n, Lk(b + j), c->logdet, c->info));
+            if (b + j + 1 < T)
+                TIMED(c, s0, KC_PANEL, rows_from(rj + NB) * dNB * dNB,
+                      launch_panel(s0, c->F, A + rj + NB + rj * ld, ld, npad - rj - NB,
+                                   Lk(b + j)));
         }
         HIPCHK(c, ev_record(c->evP, s0));
         if (rn >= npad)

@@ -1169,7 +1169,7 @@ template <int WM, int WN> struct TileBG {
 
 // C -= A * B^T over the block-lower tiles of a trailing matrix of nblk x nblk
 // NB-blocks (128 x 128 tiles; both 128-tiles above the diagonal inside a
-// diagonal NB-block are included), depth K (one or two panels).  blockIdx.y
+// diagonal NB-block are included), depth K (one, two or four panels).  blockIdx.y
 // selects (C0, A0) or (C1, A1).
 template <int MIX, int K = NB>
 __global__ __launch_bounds__(256) void k_update_lower(int nmat, int64_t sC, int64_t sB,
@@ -1245,7 +1245,7 @@ void launch_update_rect(hipStream_t s, const Fields &F, int64_t sC, int64_t sB, 
                         int64_t lda, const double *B, int64_t ldb, int64_t rows, int64_t ncol,
                         int K, int mixed)
 {
-    if (rows <= 0 || ncol <= 0 || (K != NB && K != 2 * NB))
+    if (rows <= 0 || ncol <= 0 || (K != NB && K != 2 * NB && K != 4 * NB))
         return;
     const dim3 g((unsigned)(rows / 128), (unsigned)(ncol / 128), (unsigned)(nmat * F.count));
     if (mixed) {
@@ -1257,7 +1257,9 @@ void launch_update_rect(hipStream_t s, const Fields &F, int64_t sC, int64_t sB, 
         }
         return;
     }
-    auto kern = K == 2 * NB ? k_update_rect<0, 2 * NB> : k_update_rect<0, NB>;
+    auto kern = K == 4 * NB   ? k_update_rect<0, 4 * NB>
+                : K == 2 * NB ? k_update_rect<0, 2 * NB>
+                              : k_update_rect<0, NB>;
     hipLaunchKernelGGL(kern, g, dim3(256), 0, s, nmat, sC, sB, C0, C1, ldc, A0, A1, lda, B, ldb);
 }
 
@@ -1266,7 +1268,7 @@ void launch_update_lower(hipStream_t s, const Fields &F, int64_t sC, int64_t sB,
                          const double *A1, int64_t lda, const double *B, int64_t ldb, int nblk,
                          int K, int mixed)
 {
-    if (nblk <= 0 || (K != NB && K != 2 * NB))
+    if (nblk <= 0 || (K != NB && K != 2 * NB && K != 4 * NB))
         return;
     const int64_t pairs = (int64_t)nblk * (nblk + 1) / 2;
     const dim3 g((unsigned)(4 * pairs), (unsigned)(nmat * F.count));
@@ -1280,7 +1282,9 @@ void launch_update_lower(hipStream_t s, const Fields &F, int64_t sC, int64_t sB,
         }
         return;
     }
-    auto kern = K == 2 * NB ? k_update_lower<0, 2 * NB> : k_update_lower<0, NB>;
+    auto kern = K == 4 * NB   ? k_update_lower<0, 4 * NB>
+                : K == 2 * NB ? k_update_lower<0, 2 * NB>
+                              : k_update_lower<0, NB>;
     hipLaunchKernelGGL(kern, g, dim3(256), 0, s, nmat, sC, sB, C0, C1, ldc, A0, A1, lda, B, ldb);
 }
 
