@@ -290,9 +290,67 @@ const char *fbt_batch_last_error(const fbt_batch *b);
  * event captured, no allocation or host wait inside the capture and every
  * copy in bounds, so the cause is not identified): asking for it returns
  * FBT_EINVAL with the reason in fbt_batch_last_error.  Errors: FBT_EINVAL. */
-typedef enum { FBT_BATCH_WORKERS = 0, FBT_BATCH_GRAPH = 1 } fbt_batch_exec;
+/*   FBT_BATCH_PERSISTENT: every log-likelihood and derivative field of the
+ *     call in ONE kernel launch (the batching of Algorithm 1's evaluations
+ *     over replicate fields): the evaluations of all fields are split into
+ *     tile tasks (generation of Sigma, Sigma_alpha, Sigma_nu tiles; left-looking
+ *     Cholesky tiles with the diagonal factor and its inverse; forward
+ *     substitution of [Sigma_alpha | Sigma_nu]; W_i = L^{-1} Sigma_i L^{-T}
+ *     tiles with their shares of the traces of Eqs. (2), (3) and (5); a
+ *     fixed-order reduction per field) that the launch's workgroups take in
+ *     an order planned on the host (a list schedule of the task graph,
+ *     checked before every launch so that no workgroup can wait on a task
+ *     that no workgroup holds), each waiting on counters of the tiles it
+ *     reads.  Tiles of 64 or 128 rows (fbt_batch_set_tile).  FP64 only
+ *     (FBT_EINVAL for a batch of another precision).  Adjoint-mode fields
+ *     run after the launch, one by one.  Results agree with the other
+ *     executions to rounding (a different blocking and summation order), not
+ *     bitwise.  A dependency wait that exceeds 5 s of wall-clock time ends the
+ *     launch and the call returns FBT_EDEVICE. */
+typedef enum {
+    FBT_BATCH_WORKERS = 0,
+    FBT_BATCH_GRAPH = 1,
+    FBT_BATCH_PERSISTENT = 2
+} fbt_batch_exec;
 fbt_status fbt_batch_set_exec(fbt_batch *b, int32_t exec);
 int32_t fbt_batch_get_exec(const fbt_batch *b); /* -1 for NULL */
+/* Tile size of the persistent execution: 64, 128, or 0 for the default (64).
+ * Errors: FBT_EINVAL. */
+fbt_status fbt_batch_set_tile(fbt_batch *b, int32_t tile);
+int32_t fbt_batch_get_tile(const fbt_batch *b); /* -1 for NULL */
+/* Persistent execution of the last call: tasks of its plan, the planner's
+ * makespan estimate (microseconds) and the kernel's time (ms; 0 before the
+ * first call).  Errors: FBT_EINVAL for NULL b. */
+fbt_status fbt_batch_round_stats(const fbt_batch *b, int64_t *ntasks, double *plan_us,
+                                 double *kernel_ms);
+/* Per-task trace of the persistent execution (off by default): with on,
+ * later calls record for every task the wall-clock ticks (the device's
+ * constant-rate counter, hipDeviceAttributeWallClockRate kHz) at which a
+ * workgroup took its ticket, finished its waits and finished the task.
+ * fbt_batch_round_trace copies the last call's record, 5 int64 per task in
+ * ticket order (the two task words as in fbt_round_plan, then the three
+ * times), for at most cap tasks, and returns the task count (0: none).
+ * Errors: FBT_EINVAL, FBT_EDEVICE. */
+fbt_status fbt_batch_set_round_trace(fbt_batch *b, int32_t on);
+int64_t fbt_batch_round_trace(const fbt_batch *b, int64_t *out, int64_t cap);
+/* Host-only inspection of the persistent execution's plan (no device
+ * needed): the ticket order of the tasks of nf fields with n[f]
+ * observations and mode[f] (1, 2; other values: no tasks) for tiles of
+ * `tile` rows and `slots` workgroups.  *ntasks receives the task count;
+ * tasks (NULL: not written) receives two int32 per task, (field << 3 | type,
+ * i << 16 | j) with type 0 generation of tile (i, j), 1 Cholesky tile (i, j),
+ * 2 forward-substitution tile (i, j) of [Sigma_alpha | Sigma_nu] (j < 2T),
+ * 3 W tile (i, j), 4 the field's reduction; *est_us the planner's makespan
+ * estimate.  Returns FBT_EINVAL for bad arguments or an order that fails
+ * the check of the kernel's waits. */
+fbt_status fbt_round_plan(int32_t nf, const int64_t *n, const int32_t *mode, int32_t tile,
+                          int32_t slots, int64_t *ntasks, int32_t *tasks, double *est_us);
+/* The kernel's waits for task (ft, ij) of a field with T tiles and mode 1 or
+ * 2: counters off[k] >= need[k], k < the return value (at most 4), and the
+ * counters pub[k], k < *npub (at most 4), it advances by one when done. */
+int32_t fbt_round_task_deps(int32_t T, int32_t mode, int32_t ft, int32_t ij, int32_t *off,
+                            int32_t *need, int32_t *pub, int32_t *npub);
+
 /* At most max_fields fields of padded order npad (a multiple of 256) per group
  * (0: only the 8 GB cap).  Errors: FBT_EINVAL. */
 fbt_status fbt_batch_set_group_limit(fbt_batch *b, int64_t npad, int32_t max_fields);

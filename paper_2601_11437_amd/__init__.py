@@ -101,6 +101,13 @@ SIGNATURES = {
     "fbt_batch_group_limit": (_i32, [_p, _i64]),
     "fbt_batch_autotune": (ctypes.c_int, [_p, _p, _p, ctypes.c_char_p]),
     "fbt_batch_load_tuning": (ctypes.c_int, [_p, ctypes.c_char_p]),
+    "fbt_batch_set_tile": (ctypes.c_int, [_p, _i32]),
+    "fbt_batch_get_tile": (_i32, [_p]),
+    "fbt_batch_round_stats": (ctypes.c_int, [_p, ctypes.POINTER(_i64), _dp, _dp]),
+    "fbt_batch_set_round_trace": (ctypes.c_int, [_p, _i32]),
+    "fbt_batch_round_trace": (_i64, [_p, _p, _i64]),
+    "fbt_round_plan": (ctypes.c_int, [_i32, _p, _p, _i32, _i32, ctypes.POINTER(_i64), _p, _dp]),
+    "fbt_round_task_deps": (_i32, [_i32, _i32, _i32, _i32, _p, _p, _p, ctypes.POINTER(_i32)]),
     "fbt_set_timing": (ctypes.c_int, [_p, _i32]),
     "fbt_get_timing": (ctypes.c_int, [_p, _i32, ctypes.POINTER(_i64), _dp, _dp]),
 }
@@ -383,7 +390,7 @@ class Batch:
     set_group_limit or the autotuner."""
 
     SKIP, LOGLIK, EVAL, GRAD = 0, 1, 2, 3
-    WORKERS, GRAPH = 0, 1
+    WORKERS, GRAPH, PERSISTENT = 0, 1, 2
 
     def __init__(self, workers: int = 2, device: int = 0, precision: int = FP64):
         cfg = Config(int(device), 0, int(precision), None)
@@ -432,7 +439,7 @@ class Batch:
         return ll, sc, fi.reshape(self.nf, 3, 3), status
 
     def set_exec(self, exec_: int):
-        """WORKERS (0) or GRAPH (1) for the following calls."""
+        """WORKERS (0), GRAPH (1) or PERSISTENT (2) for the following calls."""
         st = lib().fbt_batch_set_exec(self._h, int(exec_))
         if st != OK:
             raise FisherBTError(st, "fbt_batch_set_exec: " +
@@ -441,6 +448,48 @@ class Batch:
     @property
     def exec(self) -> int:
         return int(lib().fbt_batch_get_exec(self._h))
+
+    def set_tile(self, tile: int):
+        """Tile rows of the persistent execution: 64, 128 or 0 (default)."""
+        st = lib().fbt_batch_set_tile(self._h, int(tile))
+        if st != OK:
+            raise FisherBTError(st, "fbt_batch_set_tile(%d)" % tile)
+
+    @property
+    def tile(self) -> int:
+        return int(lib().fbt_batch_get_tile(self._h))
+
+    def round_stats(self):
+        """(tasks, planner's makespan estimate in us, kernel ms) of the last
+        persistent call."""
+        nt, est, ms = _i64(0), ctypes.c_double(0), ctypes.c_double(0)
+        st = lib().fbt_batch_round_stats(self._h, ctypes.byref(nt), ctypes.byref(est),
+                                         ctypes.byref(ms))
+        if st != OK:
+            raise FisherBTError(st, "fbt_batch_round_stats")
+        return int(nt.value), float(est.value), float(ms.value)
+
+    def set_round_trace(self, on: bool = True):
+        """Record a per-task trace in later persistent calls."""
+        st = lib().fbt_batch_set_round_trace(self._h, int(bool(on)))
+        if st != OK:
+            raise FisherBTError(st, "fbt_batch_set_round_trace")
+
+    def round_trace(self):
+        """Trace of the last persistent call: (ntasks, 7) int64 array of
+        (field, type, i, j, ticket time, ready time, end time) in wall-clock
+        ticks, ticket order; None without a trace."""
+        n = int(self.round_stats()[0])
+        if n <= 0:
+            return None
+        raw = np.zeros(5 * n, dtype=np.int64)
+        got = int(lib().fbt_batch_round_trace(self._h, raw.ctypes.data, n))
+        if got <= 0:
+            return None
+        raw = raw.reshape(n, 5)
+        ft, ij = raw[:, 0], raw[:, 1]
+        return np.stack([ft >> 3, ft & 7, ij >> 16, ij & 0xFFFF, raw[:, 2], raw[:, 3], raw[:, 4]],
+                        axis=1)
 
     def set_group_limit(self, npad: int, max_fields: int):
         st = lib().fbt_batch_set_group_limit(self._h, int(npad), int(max_fields))
@@ -465,3 +514,37 @@ class Batch:
         st = lib().fbt_batch_load_tuning(self._h, str(path).encode())
         if st != OK:
             raise FisherBTError(st, "fbt_batch_load_tuning(%s)" % path)
+
+
+def round_plan(n, mode, tile: int = 64, slots: int = 512):
+    """Ticket order of the persistent execution's tasks (host only): an
+    (ntasks, 4) int array of (field, type, i, j) and the planner's makespan
+    estimate in microseconds."""
+    n = np.ascontiguousarray(n, dtype=np.int64)
+    md = np.ascontiguousarray(np.broadcast_to(np.asarray(mode, dtype=np.int32), n.shape))
+    cnt, est = _i64(0), ctypes.c_double(0)
+    st = lib().fbt_round_plan(n.size, n.ctypes.data, md.ctypes.data, int(tile), int(slots),
+                              ctypes.byref(cnt), None, ctypes.byref(est))
+    if st != OK:
+        raise FisherBTError(st, "fbt_round_plan")
+    raw = np.zeros(2 * cnt.value, dtype=np.int32)
+    st = lib().fbt_round_plan(n.size, n.ctypes.data, md.ctypes.data, int(tile), int(slots),
+                              ctypes.byref(cnt), raw.ctypes.data, None)
+    if st != OK:
+        raise FisherBTError(st, "fbt_round_plan")
+    ft, ij = raw[0::2], raw[1::2]
+    out = np.stack([ft >> 3, ft & 7, ij >> 16, ij & 0xFFFF], axis=1)
+    return out, float(est.value)
+
+
+def round_task_deps(T: int, mode: int, field: int, type_: int, i: int, j: int):
+    """The persistent kernel's waits [(counter, value)] and advanced counters
+    for one task of a field with T tiles (host only)."""
+    off = np.zeros(4, dtype=np.int32)
+    need = np.zeros(4, dtype=np.int32)
+    pub = np.zeros(4, dtype=np.int32)
+    npub = _i32(0)
+    k = lib().fbt_round_task_deps(int(T), int(mode), (field << 3) | type_, (i << 16) | j,
+                                  off.ctypes.data, need.ctypes.data, pub.ctypes.data,
+                                  ctypes.byref(npub))
+    return list(zip(off[:k].tolist(), need[:k].tolist())), pub[:npub.value].tolist()

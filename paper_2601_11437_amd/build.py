@@ -11,7 +11,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libfisherbt.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["fbt_kernels.hip", "fbt_engine.hip", "fbt_fit.cpp", "fbt_batch.cpp"]
+SOURCES = ["fbt_kernels.hip", "fbt_engine.hip", "fbt_fit.cpp", "fbt_batch.cpp", "fbt_round.hip",
+           "fbt_plan.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

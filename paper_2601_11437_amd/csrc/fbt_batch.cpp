@@ -30,6 +30,8 @@
 
 // device memory one batched group may hold (its three matrices per field)
 constexpr size_t GROUP_BYTES = (size_t)8 << 30;
+// tile size of the persistent execution when none is set or tuned
+constexpr int DEFAULT_TILE = 64;
 
 namespace {
 
@@ -61,6 +63,9 @@ struct fbt_batch {
     std::vector<hipEvent_t> join;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+    // persistent execution: one launch per call (fbt_round.hip)
+    fbt::RoundExec *round = nullptr;
+    int tile = 0; // 0: default (DEFAULT_TILE)
 };
 
 namespace {
@@ -133,6 +138,58 @@ void scatter(const Task &t, const double *gll, const double *gsc, const double *
 fbt_status graph_eval(fbt_batch *b, const double *thetas, const int32_t *mode, double *loglik,
                       double *score, double *fisher, int32_t *status);
 
+// Persistent execution: the log-likelihood and derivative fields of the call
+// in one launch of the round kernel; adjoint-mode fields after it, one by
+// one on the first worker context.
+fbt_status persistent_eval(fbt_batch *b, const double *thetas, const int32_t *mode,
+                           double *loglik, double *score, double *fisher, int32_t *status)
+{
+    const int32_t nf = (int32_t)b->n.size();
+    if (!b->round) {
+        b->round = fbt::round_create(b->cfg.device);
+        if (!b->round) {
+            b->err = "batch: cannot create the persistent execution's stream";
+            return FBT_EDEVICE;
+        }
+    }
+    std::vector<const double *> lp(nf), zp(nf);
+    for (int32_t f = 0; f < nf; ++f) {
+        lp[f] = b->locs[f].data();
+        zp[f] = b->z[f].data();
+    }
+    std::vector<int32_t> m12(nf);
+    bool any = false;
+    for (int32_t f = 0; f < nf; ++f) {
+        m12[f] = (mode[f] == 1 || mode[f] == 2) ? mode[f] : 0;
+        any = any || m12[f] != 0;
+    }
+    if (any) {
+        std::string err;
+        const fbt_status st = fbt::round_eval(b->round, b->tile ? b->tile : DEFAULT_TILE, nf,
+                                              b->n.data(), lp.data(), zp.data(),
+                                              b->fields_version, thetas, m12.data(), loglik,
+                                              score, fisher, status, &err);
+        if (st != FBT_OK) {
+            b->err = "batch: " + err;
+            return st;
+        }
+    }
+    for (int32_t f : b->order) {
+        if (mode[f] != 3)
+            continue;
+        fbt_ctx *c = b->ctx[0];
+        fbt_status st = fbt_set_data(c, b->n[f], b->locs[f].data(), b->z[f].data());
+        if (st == FBT_OK)
+            st = fbt_grad(c, thetas + 3 * f, loglik + f, score + 3 * f, nullptr);
+        status[f] = st;
+        if (st == FBT_EDEVICE || st == FBT_ENOMEM) {
+            b->err = std::string("batch: ") + fbt_last_error(c);
+            return st;
+        }
+    }
+    return FBT_OK;
+}
+
 } // namespace
 
 extern "C" {
@@ -165,6 +222,7 @@ void fbt_batch_destroy(fbt_batch *b)
     if (!b)
         return;
     drop_graph(b);
+    fbt::round_destroy(b->round);
     for (fbt_ctx *c : b->ctx)
         fbt_destroy(c);
     for (fbt_ctx *c : b->gctx)
@@ -221,6 +279,8 @@ fbt_status fbt_batch_eval(fbt_batch *b, const double *thetas, const int32_t *mod
         status[f] = FBT_OK;
     if (b->exec == FBT_BATCH_GRAPH)
         return graph_eval(b, thetas, mode, loglik, score, fisher, status);
+    if (b->exec == FBT_BATCH_PERSISTENT)
+        return persistent_eval(b, thetas, mode, loglik, score, fisher, status);
     const std::vector<Task> tasks = make_tasks(b, mode);
     std::atomic<size_t> next(0);
     std::mutex mu;
@@ -295,8 +355,13 @@ constexpr bool GRAPH_EXEC_ENABLED = FBT_GRAPH_EXEC != 0;
 
 fbt_status fbt_batch_set_exec(fbt_batch *b, int32_t exec)
 {
-    if (!b || (exec != FBT_BATCH_WORKERS && exec != FBT_BATCH_GRAPH))
+    if (!b || (exec != FBT_BATCH_WORKERS && exec != FBT_BATCH_GRAPH &&
+               exec != FBT_BATCH_PERSISTENT))
         return FBT_EINVAL;
+    if (exec == FBT_BATCH_PERSISTENT && b->cfg.precision != FBT_FP64) {
+        b->err = "batch: the persistent execution computes in FP64 only";
+        return FBT_EINVAL;
+    }
     if (exec == FBT_BATCH_GRAPH && !GRAPH_EXEC_ENABLED) {
         b->err = "batch: the graph execution is disabled (its capture crashed the host process; "
                  "cause not identified)";
@@ -327,6 +392,48 @@ int32_t fbt_batch_group_limit(const fbt_batch *b, int64_t npad)
 }
 
 int32_t fbt_batch_get_exec(const fbt_batch *b) { return b ? b->exec : -1; }
+
+fbt_status fbt_batch_set_tile(fbt_batch *b, int32_t tile)
+{
+    if (!b || (tile != 0 && tile != 64 && tile != 128))
+        return FBT_EINVAL;
+    b->tile = tile;
+    return FBT_OK;
+}
+
+int32_t fbt_batch_get_tile(const fbt_batch *b) { return b ? (b->tile ? b->tile : DEFAULT_TILE) : -1; }
+
+fbt_status fbt_batch_set_round_trace(fbt_batch *b, int32_t on)
+{
+    if (!b)
+        return FBT_EINVAL;
+    if (!b->round) {
+        b->round = fbt::round_create(b->cfg.device);
+        if (!b->round)
+            return FBT_EDEVICE;
+    }
+    fbt::round_set_trace(b->round, on != 0);
+    return FBT_OK;
+}
+
+int64_t fbt_batch_round_trace(const fbt_batch *b, int64_t *out, int64_t cap)
+{
+    return (b && out && cap > 0) ? fbt::round_trace(b->round, out, cap) : 0;
+}
+
+fbt_status fbt_batch_round_stats(const fbt_batch *b, int64_t *ntasks, double *plan_us,
+                                 double *kernel_ms)
+{
+    if (!b)
+        return FBT_EINVAL;
+    if (ntasks)
+        *ntasks = fbt::round_task_count(b->round);
+    if (plan_us)
+        *plan_us = fbt::round_plan_estimate_us(b->round);
+    if (kernel_ms)
+        *kernel_ms = fbt::round_last_ms(b->round);
+    return FBT_OK;
+}
 
 fbt_status fbt_batch_autotune(fbt_batch *b, const double *thetas, const int32_t *mode,
                               const char *path)
@@ -437,6 +544,8 @@ fbt_status fbt_batch_autotune(fbt_batch *b, const double *thetas, const int32_t 
     }
     js += "\n  },\n  \"chosen\": \"" + chosen + "\",";
     double tg = -1;
+    double best_t = tw;
+    b->exec = FBT_BATCH_WORKERS;
     if (GRAPH_EXEC_ENABLED) {
         b->exec = FBT_BATCH_GRAPH;
         if ((r = time_call(mode, &tg)) != FBT_OK) {
@@ -444,12 +553,38 @@ fbt_status fbt_batch_autotune(fbt_batch *b, const double *thetas, const int32_t 
             return r;
         }
         b->exec = tg < tw ? FBT_BATCH_GRAPH : FBT_BATCH_WORKERS;
+        best_t = std::min(tw, tg);
     }
-    char buf[256];
+    // the persistent execution (FP64 only) with each tile size
+    double tp[2] = {-1.0, -1.0};
+    const int keep_tile = b->tile;
+    int best_tile = keep_tile;
+    if (b->cfg.precision == FBT_FP64) {
+        const int exec_now = b->exec;
+        b->exec = FBT_BATCH_PERSISTENT;
+        bool won = false;
+        for (int q = 0; q < 2; ++q) {
+            b->tile = q == 0 ? 64 : 128;
+            if ((r = time_call(mode, &tp[q])) != FBT_OK) {
+                b->exec = keep;
+                b->tile = keep_tile;
+                return r;
+            }
+            if (tp[q] < best_t) {
+                best_t = tp[q];
+                best_tile = b->tile;
+                won = true;
+            }
+        }
+        b->exec = won ? FBT_BATCH_PERSISTENT : exec_now;
+        b->tile = won ? best_tile : keep_tile;
+    }
+    char buf[384];
     std::snprintf(buf, sizeof(buf),
-                  "\n  \"exec\": %d,\n  \"seconds_workers\": %.6f,\n  \"seconds_graph\": "
-                  "%.6f,\n  \"precision\": %d\n}\n",
-                  b->exec, tw, tg, (int)b->cfg.precision);
+                  "\n  \"exec\": %d,\n  \"tile\": %d,\n  \"seconds_workers\": %.6f,\n  "
+                  "\"seconds_graph\": %.6f,\n  \"seconds_persistent_64\": %.6f,\n  "
+                  "\"seconds_persistent_128\": %.6f,\n  \"precision\": %d\n}\n",
+                  b->exec, b->tile, tw, tg, tp[0], tp[1], (int)b->cfg.precision);
     js += buf;
     if (path) {
         FILE *fp = std::fopen(path, "w");
@@ -503,8 +638,17 @@ fbt_status fbt_batch_load_tuning(fbt_batch *b, const char *path)
         pos = (comma == std::string::npos || comma > close) ? close : comma + 1;
     }
     const int e = std::atoi(txt.c_str() + txt.find(':', ep) + 1);
-    if (e != FBT_BATCH_WORKERS && !(e == FBT_BATCH_GRAPH && GRAPH_EXEC_ENABLED))
+    if (e != FBT_BATCH_WORKERS && !(e == FBT_BATCH_GRAPH && GRAPH_EXEC_ENABLED) &&
+        !(e == FBT_BATCH_PERSISTENT && b->cfg.precision == FBT_FP64))
         return FBT_EINVAL;
+    int tile = 0;
+    const size_t tp = txt.find("\"tile\"");
+    if (tp != std::string::npos) {
+        tile = std::atoi(txt.c_str() + txt.find(':', tp) + 1);
+        if (tile != 0 && tile != 64 && tile != 128)
+            return FBT_EINVAL;
+    }
+    b->tile = tile;
     b->limit.clear();
     for (const auto &kv : lim)
         if (kv.second > 0)

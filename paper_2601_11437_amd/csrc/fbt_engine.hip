@@ -132,8 +132,6 @@ constexpr int FACT_QUAD_ABOVE = 48;
 // 256 rows; 79 x 8 at n = 20,000)
 constexpr int REFINE_NQ = 8;
 
-// node table followed by the paper-mode coefficient table (one upload)
-constexpr size_t TAB_BYTES = TAB_MAX * sizeof(Node) + PC_SIZE * sizeof(double);
 
 fbt_status fail(fbt_ctx *c, fbt_status s, const std::string &m)
 {
@@ -251,14 +249,16 @@ void paper_coefficients(const GenParams &gp, double *pc)
     pc[PC_SQPI] = std::sqrt(M_PI / (2.0 * nu));
 }
 
+} // namespace
+
 // Quadrature tables and prefactors for theta (see the generation kernel).
-GenParams setup_theta(fbt_ctx *c, const double *th, int f, int64_t n)
+GenParams fbt::theta_params(const double *th, int paper_mode, int64_t n, int64_t npad, int64_t ld,
+                            void *host_tab, const void *dev_tab)
 {
     GenParams gp;
     std::memset(&gp, 0, sizeof(gp));
-    Node *htab = reinterpret_cast<Node *>(reinterpret_cast<char *>(c->h_tab) + f * TAB_BYTES);
-    const Node *dtab =
-        reinterpret_cast<const Node *>(reinterpret_cast<const char *>(c->tab) + f * TAB_BYTES);
+    Node *htab = reinterpret_cast<Node *>(host_tab);
+    const Node *dtab = reinterpret_cast<const Node *>(dev_tab);
     gp.sigma2 = th[0];
     gp.alpha = th[1];
     gp.nu = th[2];
@@ -266,10 +266,10 @@ GenParams setup_theta(fbt_ctx *c, const double *th, int f, int64_t n)
     gp.cnu = std::exp((1.0 - gp.nu) * std::log(2.0) - std::lgamma(gp.nu));
     gp.log2_psi = std::log(2.0) + digamma(gp.nu);
     gp.n = n;
-    gp.npad = c->npad;
-    gp.ld = c->ld;
+    gp.npad = npad;
+    gp.ld = ld;
     gp.tab = dtab;
-    const bool paper = c->sigma_nu_mode == FBT_SIGMA_NU_PAPER;
+    const bool paper = paper_mode != 0;
     gp.paper = paper ? 1 : 0;
     gp.fd_small = std::fabs(gp.nu - std::nearbyint(gp.nu)) > 1e-6 ? 0 : 1;
     gp.fd_large = std::fabs((gp.nu + 0.5) - std::nearbyint(gp.nu + 0.5)) > 1e-6 ? 0 : 1;
@@ -300,6 +300,15 @@ GenParams setup_theta(fbt_ctx *c, const double *th, int f, int64_t n)
     if (paper)
         paper_coefficients(gp, reinterpret_cast<double *>(htab + TAB_MAX));
     return gp;
+}
+
+namespace {
+
+GenParams setup_theta(fbt_ctx *c, const double *th, int f, int64_t n)
+{
+    return theta_params(th, c->sigma_nu_mode == FBT_SIGMA_NU_PAPER ? 1 : 0, n, c->npad, c->ld,
+                        reinterpret_cast<char *>(c->h_tab) + f * TAB_BYTES,
+                        reinterpret_cast<const char *>(c->tab) + f * TAB_BYTES);
 }
 
 // ---- ordering between the critical-path and bulk streams ----
@@ -1196,6 +1205,18 @@ void assemble(int64_t nobs, const double *theta, const double *t, double *loglik
     const double F[9] = {I00, I01, I02, I01, I11, I12, I02, I12, I22};
     std::memcpy(fisher, F, sizeof(F));
 }
+
+} // namespace
+
+double fbt::loglik_terms(int64_t n, double logdet, double quad) { return loglik_from(n, logdet, quad); }
+
+void fbt::assemble_terms(int64_t nobs, const double *theta, const double *t, double *loglik,
+                         double *score, double *fisher)
+{
+    assemble(nobs, theta, t, loglik, score, fisher);
+}
+
+namespace {
 
 fbt_status check_call(fbt_ctx *c, const double *th)
 {

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "fisherbt.h"
 
 namespace fbt {
@@ -56,6 +58,15 @@ struct GenParams {
 };
 
 enum GenMode { GEN_SIGMA = 1, GEN_DERIV = 2, GEN_ALL = 3 };
+
+// node table followed by the paper-mode coefficient table (one upload per theta)
+constexpr size_t TAB_BYTES = TAB_MAX * sizeof(Node) + PC_SIZE * sizeof(double);
+
+// Generation parameters for theta = (sigma2, alpha, nu): prefactors, and the
+// quadrature node table (plus, with paper_mode, the coefficient table of the
+// paper's scheme) written to host_tab (TAB_BYTES) for upload to dev_tab.
+GenParams theta_params(const double *th, int paper_mode, int64_t n, int64_t npad, int64_t ld,
+                       void *host_tab, const void *dev_tab);
 
 // Field batching.  One launch can cover `count` independent fields of the same
 // padded order whose buffers are laid out one after another with uniform
@@ -196,6 +207,35 @@ fbt_status group_results(fbt_ctx *c, int mode, const double *thetas, const int *
 hipStream_t ctx_stream(fbt_ctx *c);
 // Restrict the context to streams a HIP graph capture accepts (no CU-masked stream).
 void ctx_set_capturable(fbt_ctx *c, bool on);
+
+// Persistent round execution of batched fields (fbt_round.hip): one launch
+// evaluates every field of a call (mode 1: Algorithm 2, 2: Algorithm 3; other
+// modes are left out) with BT x BT tiles (bt = 64 or 128).  The device arena
+// and the task order are rebuilt when the field set (version), the modes or
+// bt change.  Per-field status as fbt_batch_eval; returns FBT_EDEVICE /
+// FBT_ENOMEM / FBT_EINVAL with *err on failure of the whole call.
+struct RoundExec;
+RoundExec *round_create(int device);
+void round_destroy(RoundExec *r);
+fbt_status round_eval(RoundExec *r, int bt, int nf, const int64_t *n, const double *const *locs,
+                      const double *const *z, uint64_t version, const double *thetas,
+                      const int32_t *mode, double *loglik, double *score, double *fisher,
+                      int32_t *status, std::string *err);
+float round_last_ms(const RoundExec *r);          // kernel time of the last call
+double round_plan_estimate_us(const RoundExec *r); // planner's makespan estimate
+int round_task_count(const RoundExec *r);
+// per-task trace of later calls (wall-clock ticks at ticket, waits done, end);
+// round_trace copies the last call's: 5 int64 per task (ft, ij, times), up
+// to cap tasks; returns the task count (0: no trace)
+void round_set_trace(RoundExec *r, bool on);
+int64_t round_trace(const RoundExec *r, int64_t *out, int64_t cap);
+
+// Eq. (1) from log det and the quadratic form; Eqs. (1)-(3) from the nine
+// terms (log det, q, tr W_a, tr W_n, y'W_a y, y'W_n y, <W_a,W_a>, <W_a,W_n>,
+// <W_n,W_n>).
+double loglik_terms(int64_t n, double logdet, double quad);
+void assemble_terms(int64_t nobs, const double *theta, const double *t, double *loglik,
+                    double *score, double *fisher);
 
 // Derivative evaluation of the Fisher-BT driver with the switch from a mixed
 // precision to FP64 near the optimum (fbt_fit_options.mixed_switch);

@@ -29,7 +29,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(ROOT, "paper_2601_11437_amd", "csrc")
 CHECK = os.path.join(HERE, "capture_check")
-SOURCES = ["fbt_kernels.hip", "fbt_engine.hip", "fbt_fit.cpp", "fbt_batch.cpp"]
+SOURCES = ["fbt_kernels.hip", "fbt_engine.hip", "fbt_fit.cpp", "fbt_batch.cpp", "fbt_round.hip",
+           "fbt_plan.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ROCM_INC = "/opt/rocm/include"
 
