@@ -205,6 +205,10 @@ def batch_bench(args):
     tune = None
     if args.batch_exec == "graph":
         b.set_exec(fbt.Batch.GRAPH)
+    elif args.batch_exec == "persistent":
+        b.set_exec(fbt.Batch.PERSISTENT)
+        if args.batch_tile:
+            b.set_tile(args.batch_tile)
     elif args.batch_exec == "tuned":
         t0 = time.perf_counter()
         path = os.path.join(tempfile.gettempdir(), "fisherbt_batch_tuning.json")
@@ -212,10 +216,19 @@ def batch_bench(args):
         with open(path) as f:
             tune = json.load(f)
         tune["tuning_seconds"] = time.perf_counter() - t0
-        log("autotune: %.1f s, exec %s, limits %s" % (tune["tuning_seconds"],
-                                                      ("workers", "graph")[tune["exec"]],
-                                                      tune["limits"]))
+        log("autotune: %.1f s, exec %s, tile %s, limits %s"
+            % (tune["tuning_seconds"], ("workers", "graph", "persistent")[tune["exec"]],
+               tune.get("tile"), tune["limits"]))
     dt, (ll, sc, fi, st) = timed()
+    b_exec = b.exec
+    persistent = b_exec == fbt.Batch.PERSISTENT
+    round_info = None
+    if persistent:
+        ntasks, plan_us, kernel_ms = b.round_stats()
+        round_info = {"tile": b.tile, "tasks": ntasks, "planner_estimate_ms": plan_us / 1e3,
+                      "kernel_ms_last_round": kernel_ms,
+                      "launches_per_round": 1}
+        log("persistent round: tile %d, %d tasks, kernel %.1f ms" % (b.tile, ntasks, kernel_ms))
     b.close()
     ns = np.array([z.size for _, z in fields], dtype=np.float64)
     # n^3 / 3 (factorisation) + 2 n^3 (two-sided W phase of both derivative
@@ -231,8 +244,10 @@ def batch_bench(args):
                                   "theta_f uniform in [0.5,2]x[0.02,0.3]x[0.3,2.5], one full "
                                   "evaluation per field per step" % nf,
                       "workers": args.batch_workers, "theta_redraws": redraws,
-                      "exec": args.batch_exec},
+                      "exec": args.batch_exec,
+                      "exec_used": ("workers", "graph", "persistent")[b_exec]},
            "tuning": tune,
+           "persistent_round": round_info,
            "ms_per_step_workers_untuned": 1e3 * dt_workers / args.steps,
            "algorithmic_flops_per_round": exec_flops / args.steps,
            "executed_tflops": exec_flops / dt / 1e12,
@@ -435,9 +450,13 @@ def main():
     ap.add_argument("--batch", type=int, default=0,
                     help="instead of the n=20k evaluation, time one round over this many fields")
     ap.add_argument("--batch-workers", type=int, default=2)
-    ap.add_argument("--batch-exec", choices=("workers", "graph", "tuned"), default="tuned",
-                    help="batch execution: worker threads, one HIP graph per round, or the "
-                         "autotuner's choice of execution and group limits")
+    ap.add_argument("--batch-tile", type=int, default=0,
+                    help="tile rows of the persistent execution (64, 128; 0: default)")
+    ap.add_argument("--batch-exec", choices=("workers", "graph", "tuned", "persistent"),
+                    default="tuned",
+                    help="batch execution: worker threads, one HIP graph per round, the "
+                         "autotuner's choice of execution, tile and group limits, or one "
+                         "persistent launch per round")
     ap.add_argument("--fit", action="store_true",
                     help="instead of the evaluation rate, time one full Fisher-BT fit (FP64 and mixed)")
     ap.add_argument("--grid", action="store_true",

@@ -314,7 +314,7 @@ typedef enum {
 } fbt_batch_exec;
 fbt_status fbt_batch_set_exec(fbt_batch *b, int32_t exec);
 int32_t fbt_batch_get_exec(const fbt_batch *b); /* -1 for NULL */
-/* Tile size of the persistent execution: 64, 128, or 0 for the default (64).
+/* Tile size of the persistent execution: 64, 128, or 0 for the default (128).
  * Errors: FBT_EINVAL. */
 fbt_status fbt_batch_set_tile(fbt_batch *b, int32_t tile);
 int32_t fbt_batch_get_tile(const fbt_batch *b); /* -1 for NULL */
@@ -333,18 +333,26 @@ fbt_status fbt_batch_round_stats(const fbt_batch *b, int64_t *ntasks, double *pl
  * Errors: FBT_EINVAL, FBT_EDEVICE. */
 fbt_status fbt_batch_set_round_trace(fbt_batch *b, int32_t on);
 int64_t fbt_batch_round_trace(const fbt_batch *b, int64_t *out, int64_t cap);
+/* Task queues of the persistent execution: the fields are split over
+ * `queues` queues (1, 2, 4 or 8; 0: the default, 8, one per XCD of MI355X),
+ * each drained by the workgroups of one XCD.  Errors: FBT_EINVAL. */
+fbt_status fbt_batch_set_queues(fbt_batch *b, int32_t queues);
+int32_t fbt_batch_get_queues(const fbt_batch *b); /* -1 for NULL */
 /* Host-only inspection of the persistent execution's plan (no device
  * needed): the ticket order of the tasks of nf fields with n[f]
  * observations and mode[f] (1, 2; other values: no tasks) for tiles of
- * `tile` rows and `slots` workgroups.  *ntasks receives the task count;
- * tasks (NULL: not written) receives two int32 per task, (field << 3 | type,
- * i << 16 | j) with type 0 generation of tile (i, j), 1 Cholesky tile (i, j),
- * 2 forward-substitution tile (i, j) of [Sigma_alpha | Sigma_nu] (j < 2T),
- * 3 W tile (i, j), 4 the field's reduction; *est_us the planner's makespan
+ * `tile` rows, `slots` workgroups and `queues` queues (1..8).  *ntasks
+ * receives the task count; tasks (NULL: not written) receives two int32 per
+ * task, (field << 3 | type, i << 16 | j) with type 0 generation of tile
+ * (i, j), 1 Cholesky tile (i, j), 2 forward-substitution tile (i, j) of
+ * [Sigma_alpha | Sigma_nu] (j < 2T), 3 W tile (i, j), 4 the field's
+ * reduction; qoff (NULL: not written) receives queues + 1 offsets, queue q
+ * holding tasks [qoff[q], qoff[q + 1]); *est_us the planner's makespan
  * estimate.  Returns FBT_EINVAL for bad arguments or an order that fails
  * the check of the kernel's waits. */
 fbt_status fbt_round_plan(int32_t nf, const int64_t *n, const int32_t *mode, int32_t tile,
-                          int32_t slots, int64_t *ntasks, int32_t *tasks, double *est_us);
+                          int32_t slots, int32_t queues, int64_t *ntasks, int32_t *tasks,
+                          int64_t *qoff, double *est_us);
 /* The kernel's waits for task (ft, ij) of a field with T tiles and mode 1 or
  * 2: counters off[k] >= need[k], k < the return value (at most 4), and the
  * counters pub[k], k < *npub (at most 4), it advances by one when done. */

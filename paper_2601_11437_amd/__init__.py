@@ -106,7 +106,10 @@ SIGNATURES = {
     "fbt_batch_round_stats": (ctypes.c_int, [_p, ctypes.POINTER(_i64), _dp, _dp]),
     "fbt_batch_set_round_trace": (ctypes.c_int, [_p, _i32]),
     "fbt_batch_round_trace": (_i64, [_p, _p, _i64]),
-    "fbt_round_plan": (ctypes.c_int, [_i32, _p, _p, _i32, _i32, ctypes.POINTER(_i64), _p, _dp]),
+    "fbt_round_plan": (ctypes.c_int, [_i32, _p, _p, _i32, _i32, _i32, ctypes.POINTER(_i64), _p,
+                                      _p, _dp]),
+    "fbt_batch_set_queues": (ctypes.c_int, [_p, _i32]),
+    "fbt_batch_get_queues": (_i32, [_p]),
     "fbt_round_task_deps": (_i32, [_i32, _i32, _i32, _i32, _p, _p, _p, ctypes.POINTER(_i32)]),
     "fbt_set_timing": (ctypes.c_int, [_p, _i32]),
     "fbt_get_timing": (ctypes.c_int, [_p, _i32, ctypes.POINTER(_i64), _dp, _dp]),
@@ -469,6 +472,12 @@ class Batch:
             raise FisherBTError(st, "fbt_batch_round_stats")
         return int(nt.value), float(est.value), float(ms.value)
 
+    def set_queues(self, queues: int):
+        """Task queues of the persistent execution (1, 2, 4, 8; 0 default)."""
+        st = lib().fbt_batch_set_queues(self._h, int(queues))
+        if st != OK:
+            raise FisherBTError(st, "fbt_batch_set_queues(%d)" % queues)
+
     def set_round_trace(self, on: bool = True):
         """Record a per-task trace in later persistent calls."""
         st = lib().fbt_batch_set_round_trace(self._h, int(bool(on)))
@@ -516,25 +525,28 @@ class Batch:
             raise FisherBTError(st, "fbt_batch_load_tuning(%s)" % path)
 
 
-def round_plan(n, mode, tile: int = 64, slots: int = 512):
+def round_plan(n, mode, tile: int = 64, slots: int = 512, queues: int = 1):
     """Ticket order of the persistent execution's tasks (host only): an
-    (ntasks, 4) int array of (field, type, i, j) and the planner's makespan
-    estimate in microseconds."""
+    (ntasks, 4) int array of (field, type, i, j), the queue offsets (queue q
+    holds rows qoff[q]:qoff[q+1]) and the planner's makespan estimate in
+    microseconds."""
     n = np.ascontiguousarray(n, dtype=np.int64)
     md = np.ascontiguousarray(np.broadcast_to(np.asarray(mode, dtype=np.int32), n.shape))
     cnt, est = _i64(0), ctypes.c_double(0)
     st = lib().fbt_round_plan(n.size, n.ctypes.data, md.ctypes.data, int(tile), int(slots),
-                              ctypes.byref(cnt), None, ctypes.byref(est))
+                              int(queues), ctypes.byref(cnt), None, None, ctypes.byref(est))
     if st != OK:
         raise FisherBTError(st, "fbt_round_plan")
     raw = np.zeros(2 * cnt.value, dtype=np.int32)
+    qoff = np.zeros(int(queues) + 1, dtype=np.int64)
     st = lib().fbt_round_plan(n.size, n.ctypes.data, md.ctypes.data, int(tile), int(slots),
-                              ctypes.byref(cnt), raw.ctypes.data, None)
+                              int(queues), ctypes.byref(cnt), raw.ctypes.data, qoff.ctypes.data,
+                              None)
     if st != OK:
         raise FisherBTError(st, "fbt_round_plan")
     ft, ij = raw[0::2], raw[1::2]
     out = np.stack([ft >> 3, ft & 7, ij >> 16, ij & 0xFFFF], axis=1)
-    return out, float(est.value)
+    return out, qoff, float(est.value)
 
 
 def round_task_deps(T: int, mode: int, field: int, type_: int, i: int, j: int):

@@ -31,7 +31,7 @@
 // device memory one batched group may hold (its three matrices per field)
 constexpr size_t GROUP_BYTES = (size_t)8 << 30;
 // tile size of the persistent execution when none is set or tuned
-constexpr int DEFAULT_TILE = 64;
+constexpr int DEFAULT_TILE = 128;
 
 namespace {
 
@@ -65,7 +65,8 @@ struct fbt_batch {
     hipGraphExec_t graph_exec = nullptr;
     // persistent execution: one launch per call (fbt_round.hip)
     fbt::RoundExec *round = nullptr;
-    int tile = 0; // 0: default (DEFAULT_TILE)
+    int tile = 0;   // 0: default (DEFAULT_TILE)
+    int queues = 0; // 0: default (8)
 };
 
 namespace {
@@ -164,6 +165,7 @@ fbt_status persistent_eval(fbt_batch *b, const double *thetas, const int32_t *mo
         any = any || m12[f] != 0;
     }
     if (any) {
+        fbt::round_set_queues(b->round, b->queues ? b->queues : 8);
         std::string err;
         const fbt_status st = fbt::round_eval(b->round, b->tile ? b->tile : DEFAULT_TILE, nf,
                                               b->n.data(), lp.data(), zp.data(),
@@ -402,6 +404,16 @@ fbt_status fbt_batch_set_tile(fbt_batch *b, int32_t tile)
 }
 
 int32_t fbt_batch_get_tile(const fbt_batch *b) { return b ? (b->tile ? b->tile : DEFAULT_TILE) : -1; }
+
+fbt_status fbt_batch_set_queues(fbt_batch *b, int32_t queues)
+{
+    if (!b || (queues != 0 && queues != 1 && queues != 2 && queues != 4 && queues != 8))
+        return FBT_EINVAL;
+    b->queues = queues;
+    return FBT_OK;
+}
+
+int32_t fbt_batch_get_queues(const fbt_batch *b) { return b ? (b->queues ? b->queues : 8) : -1; }
 
 fbt_status fbt_batch_set_round_trace(fbt_batch *b, int32_t on)
 {

@@ -103,7 +103,17 @@ __device__ __forceinline__ void matern3(const GenParams &gp, const Node *tab, do
 #pragma unroll
     for (int l = 0; l < NLEV - 1; ++l)
         L += (x > gp.xtop[l]);
-    const double h = gp.h[L];
+    // the level's step, first node and node count, selected with constant
+    // indices (a copy of gp then stays in registers)
+    double h = gp.h[0];
+    int lev_len = gp.len[0], lev_off = gp.off[0];
+#pragma unroll
+    for (int l = 1; l < NLEV; ++l)
+        if (L == l) {
+            h = gp.h[l];
+            lev_len = gp.len[l];
+            lev_off = gp.off[l];
+        }
     // truncation point: the root t* of F(t) = x (cosh t - 1) - g t - 45.  The
     // iterates t1 = acosh(1 + 45 / x), t2 = acosh(1 + (45 + g t1) / x) rise
     // towards it with F(t2) = -g (t2 - t1), and beyond t2 the slope of F is at
@@ -115,8 +125,8 @@ __device__ __forceinline__ void matern3(const GenParams &gp, const Node *tab, do
     double t = g < 44.0 ? t2 + g * (t2 - t1) / (45.0 - g) : 1.0e4;
     t = fmin(t, 1.0e4); // x below ~1e-300: every node of the level
     int J = (int)(t / h) + 2;
-    J = J < gp.len[L] ? J : gp.len[L];
-    const Node *nd = tab + gp.off[L];
+    J = J < lev_len ? J : lev_len;
+    const Node *nd = tab + lev_off;
     double sk = 0.0, sk1 = 0.0, sd = 0.0, skp = 0.0, skm = 0.0;
     if (mode == GEN_SIGMA) {
         for (int j = 0; j < J; ++j) {

@@ -252,11 +252,61 @@ RPlan rplan(const std::vector<RPlanField> &fields, int bt, int slots, std::strin
                 release(adj[e]);
     }
     plan.est_us = now;
+    plan.qoff = {0, (int64_t)plan.order.size()};
     const std::string chk = rplan_check(plan.order, fields);
     if (!chk.empty()) {
         if (err)
             *err = "round plan: " + chk;
         return RPlan();
+    }
+    return plan;
+}
+
+RPlan rplan_queues(const std::vector<RPlanField> &fields, int bt, int slots, int nq,
+                   std::string *err)
+{
+    const int nf = (int)fields.size();
+    nq = std::max(1, std::min(nq, std::max(1, slots)));
+    // estimated work of each field: its tasks under the cost model
+    const Cost cm{(double)bt};
+    std::vector<double> work(nf, 0.0);
+    for (int f = 0; f < nf; ++f) {
+        const int m = fields[f].mode;
+        if (m != 1 && m != 2)
+            continue;
+        const Ids d(fields[f].T, m);
+        for (int64_t id = 0; id < d.coln; ++id)
+            work[f] += cm.task(task_of(d, f, id), m);
+    }
+    std::vector<int> byw(nf);
+    for (int f = 0; f < nf; ++f)
+        byw[f] = f;
+    std::stable_sort(byw.begin(), byw.end(), [&](int a, int b) { return work[a] > work[b]; });
+    std::vector<double> load(nq, 0.0);
+    std::vector<int> queue_of(nf, 0);
+    for (int f : byw) {
+        const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        queue_of[f] = q;
+        load[q] += work[f];
+    }
+    RPlan plan;
+    plan.qoff.assign(1, 0);
+    for (int q = 0; q < nq; ++q) {
+        std::vector<RPlanField> sub(fields);
+        for (int f = 0; f < nf; ++f)
+            if (queue_of[f] != q)
+                sub[f].mode = 0;
+        std::string e;
+        const RPlan p = rplan(sub, bt, std::max(1, slots / nq), &e);
+        if (!e.empty()) {
+            if (err)
+                *err = e;
+            return RPlan();
+        }
+        plan.order.insert(plan.order.end(), p.order.begin(), p.order.end());
+        plan.qoff.push_back((int64_t)plan.order.size());
+        plan.est_us = std::max(plan.est_us, p.est_us);
+        plan.busy_us += p.busy_us;
     }
     return plan;
 }
@@ -333,10 +383,11 @@ std::string rplan_check(const std::vector<RTask> &order, const std::vector<RPlan
 extern "C" {
 
 fbt_status fbt_round_plan(int32_t nf, const int64_t *n, const int32_t *mode, int32_t tile,
-                          int32_t slots, int64_t *ntasks, int32_t *tasks, double *est_us)
+                          int32_t slots, int32_t queues, int64_t *ntasks, int32_t *tasks,
+                          int64_t *qoff, double *est_us)
 {
     if (nf < 0 || (nf > 0 && (!n || !mode)) || (tile != 64 && tile != 128) || slots < 1 ||
-        !ntasks)
+        queues < 1 || queues > 8 || !ntasks)
         return FBT_EINVAL;
     std::vector<fbt::RPlanField> pf(nf);
     for (int32_t f = 0; f < nf; ++f) {
@@ -346,10 +397,13 @@ fbt_status fbt_round_plan(int32_t nf, const int64_t *n, const int32_t *mode, int
                  (mode[f] == 1 || mode[f] == 2) ? mode[f] : 0};
     }
     std::string err;
-    const fbt::RPlan plan = fbt::rplan(pf, tile, slots, &err);
+    const fbt::RPlan plan = fbt::rplan_queues(pf, tile, slots, queues, &err);
     if (!err.empty())
         return FBT_EINVAL;
     *ntasks = (int64_t)plan.order.size();
+    if (qoff)
+        for (size_t q = 0; q < plan.qoff.size(); ++q)
+            qoff[q] = plan.qoff[q];
     if (tasks)
         for (size_t q = 0; q < plan.order.size(); ++q) {
             tasks[2 * q] = plan.order[q].ft;

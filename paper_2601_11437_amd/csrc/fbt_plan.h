@@ -17,9 +17,10 @@ struct RPlanField {
 };
 
 struct RPlan {
-    std::vector<RTask> order; // ticket order
-    double est_us = 0.0;      // makespan of the list schedule under the cost model
-    double busy_us = 0.0;     // sum of the task costs
+    std::vector<RTask> order;  // ticket order (queue after queue)
+    std::vector<int64_t> qoff; // queue q holds order[qoff[q], qoff[q + 1])
+    double est_us = 0.0;       // makespan of the list schedule under the cost model
+    double busy_us = 0.0;      // sum of the task costs
 };
 
 // Ticket order of every task of the fields for `slots` workgroups taking
@@ -28,6 +29,13 @@ struct RPlan {
 // size bt.  The order is checked with rplan_check before it is returned;
 // on a failed check the result is empty and *err says why.
 RPlan rplan(const std::vector<RPlanField> &fields, int bt, int slots, std::string *err);
+
+// The fields split over nq queues (largest estimated work first, each to
+// the queue with the least work so far), each queue planned by rplan for
+// slots / nq workgroups: a queue's workgroups (one XCD's, in the kernel) then
+// work on few fields at a time, whose tiles share that XCD's L2.
+RPlan rplan_queues(const std::vector<RPlanField> &fields, int bt, int slots, int nq,
+                   std::string *err);
 
 // Executes `order` one task at a time on the counters (rdeps / rpublish):
 // "" if every task finds its waits satisfied when its turn comes (so that

@@ -40,18 +40,19 @@ struct RField {
 
 namespace {
 
-// Threads per workgroup: 4 waves for 64-row tiles (two workgroups per CU),
-// 8 waves for 128-row tiles (one workgroup per CU; two waves per SIMD either
-// way, with at most 256 registers per lane).
-constexpr int rthreads(int bt) { return bt == 64 ? 256 : 512; }
+// Threads per workgroup: 4 waves, two workgroups per CU (two waves per SIMD,
+// at most 256 registers per lane).  The tasks other than the tile products
+// are separate functions (not inlined), so that the kernel's register
+// allocation at the product is that of the product alone.
+constexpr int rthreads(int) { return 256; }
 
 // ---------------------------------------------------------------------------
 // MFMA product of one BT x BT tile: acc -= A (BT x K) B^T with A M-contiguous
 // (element (m, k) at A[m + k lda]) and B N-contiguous (element (n, k) at
-// B[n + k ldb]) or, with bkc, K-contiguous (at B[k + n ldb]).  The waves of
-// the workgroup (four for BT = 64, eight for BT = 128) in 2 x (waves / 2),
-// each a block of 16 x 16 accumulators; K in chunks of 16 through
-// double-buffered LDS (A is negated when staged).  With the B
+// B[n + k ldb]) or, with bkc, K-contiguous (at B[k + n ldb]).  The four
+// waves of the workgroup in 2 x 2, each a (BT/2)^2 block of 16 x 16
+// accumulators; K in chunks of 16 through double-buffered LDS (A is negated
+// when staged).  With the B
 // fragment as the MFMA's first operand, lane l holds in accumulator (i, j),
 // element r, the entry (16 i + l % 16, 16 j + l / 16 + 4 r) of the wave's
 // block.  The kernel has one call site of run (every product of every task
@@ -215,7 +216,10 @@ template <int BT> struct RAcc {
 };
 
 // ---- waits and releases ---------------------------------------------------
-// ctl[0]: ticket counter; ctl[1]: abort flag (a wait ran out of time).
+// ctl[1]: abort flag (a wait ran out of time); ctl[RQ_CTL + RQ_STRIDE q]:
+// ticket counter of queue q (one 128-byte line each).
+constexpr int RQ_CTL = 32, RQ_STRIDE = 32, RQ_MAX = 8;
+constexpr int R_CTL_WORDS = RQ_CTL + RQ_STRIDE * RQ_MAX;
 
 // thread 0: wait until *p >= v (acquire), at most `limit` ticks of the
 // 100 MHz wall clock; false on timeout or abort.
@@ -384,7 +388,7 @@ __device__ bool mul64(FX X, FY Y, double (&o)[4][4], int &r0, int &c0)
 //   L00 = chol(A00), L10 = A10 L00^{-T}, L11 = chol(A11 - L10 L10^T),
 //   Li = [[L00^{-1}, 0], [-L11^{-1} L10 L00^{-1}, L11^{-1}]].
 template <int BT, int NT>
-__device__ void diag_factor(double *D, int64_t ld, double *Li, int64_t g0, int64_t n, double *lds,
+__device__ __attribute__((noinline)) void diag_factor(double *D, int64_t ld, double *Li, int64_t g0, int64_t n, double *lds,
                             double *logsum, int64_t *bad)
 {
     const int t = threadIdx.x;
@@ -470,37 +474,43 @@ __device__ void diag_factor(double *D, int64_t ld, double *Li, int64_t g0, int64
 // GEN(i, j): entries of Sigma' (lower part of the tile) and, for Algorithm 3,
 // of Sigma_alpha' and Sigma_nu' at (a, b) and (b, a).
 template <int BT>
-__device__ void task_gen(const RField &F, int ti, int tj, double *lds)
+__device__ __attribute__((noinline)) void task_gen(const RField &F, int ti, int tj, double *lds)
 {
     Node *tab = reinterpret_cast<Node *>(lds);
+    // the stores go through restrict pointers, so the descriptor's loads
+    // are not repeated for every entry
     const GenParams &gp = F.gp;
+    const double *xs = F.x, *ys = F.y, *zs = F.z;
+    double *__restrict__ A = F.A;
+    const int fmode = F.mode;
     const int t = threadIdx.x;
     const int ntab = gp.off[NLEV - 1] + gp.len[NLEV - 1];
     constexpr int NT = rthreads(BT);
     for (int i = t; i < ntab; i += NT)
         tab[i] = gp.tab[i];
     __syncthreads();
-    const int mode = F.mode == 2 ? GEN_ALL : GEN_SIGMA;
+    const int mode = fmode == 2 ? GEN_ALL : GEN_SIGMA;
     const int64_t n = F.n, ld = F.ld;
     const int r = t % BT;
     const int64_t a = (int64_t)ti * BT + r;
-    const double xa = a < n ? F.x[a] : 0.0, ya = a < n ? F.y[a] : 0.0;
+    const double xa = a < n ? xs[a] : 0.0, ya = a < n ? ys[a] : 0.0;
     const double inv_alpha = 1.0 / gp.alpha;
-    double *Sa = F.S, *Sn = F.S + ld * ld;
+    double *__restrict__ Sa = F.S;
+    double *__restrict__ Sn = F.S + ld * ld;
     for (int c = t / BT; c < BT; c += NT / BT) {
         if (ti == tj && c > r)
             continue;
         const int64_t b = (int64_t)tj * BT + c;
         double cv = 0.0, ca = 0.0, cn = 0.0;
         if (a < n) {
-            const double dx = xa - F.x[b], dy = ya - F.y[b];
+            const double dx = xa - xs[b], dy = ya - ys[b];
             matern3(gp, tab, sqrt(dx * dx + dy * dy) * inv_alpha, mode, cv, ca, cn);
         } else if (a == n) {
-            cv = (b < n) ? F.z[b] : 1.0;
+            cv = (b < n) ? zs[b] : 1.0;
         } else {
             cv = (a == b) ? 1.0 : 0.0;
         }
-        F.A[a + b * ld] = cv;
+        A[a + b * ld] = cv;
         if (mode == GEN_ALL) {
             Sa[a + b * ld] = ca;
             Sn[a + b * ld] = cn;
@@ -568,7 +578,7 @@ __device__ __forceinline__ Step make_step(const RField &F, int ty, int i, int j,
 // the strictly lower part of a diagonal tile counts twice, its upper part not
 // at all.  The workgroup sums go to red[] (thread 0, fixed order).
 template <int BT>
-__device__ void rsolve_shares(const RField &F, int i, int j, int h, double *sh, double *red)
+__device__ __attribute__((noinline)) void rsolve_shares(const RField &F, int i, int j, int h, double *sh, double *red)
 {
     constexpr int NT = rthreads(BT);
     const int64_t n = F.n, ld = F.ld;
@@ -602,7 +612,7 @@ __device__ void rsolve_shares(const RField &F, int i, int j, int h, double *sh, 
 }
 
 template <int BT>
-__device__ void task_reduce(const RField &F, double *lds, bool work)
+__device__ __attribute__((noinline)) void task_reduce(const RField &F, double *lds, bool work)
 {
     const int64_t n = F.n, ld = F.ld;
     const int T = F.T;
@@ -638,9 +648,15 @@ constexpr int R_LDS = 2 * 16 * (128 + 4) * 2; // doubles: the BT = 128 product s
 
 template <int BT>
 __global__ __launch_bounds__(rthreads(BT)) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_round(const RField *__restrict__ fields,
-                                               const RTask *__restrict__ tasks, int ntasks,
+                                               const RTask *__restrict__ tasks,
+                                               const int64_t *__restrict__ qoff, int nq,
                                                int *ctl, int64_t limit, long long *trace)
 {
+    // queue of this workgroup: workgroups are dealt to the XCDs round-robin,
+    // so with nq = 8 a queue's workgroups share one XCD (and its L2)
+    const int q = blockIdx.x % nq;
+    const int64_t q0 = qoff[q], qn = qoff[q + 1] - q0;
+    int *qctl = ctl + RQ_CTL + RQ_STRIDE * q;
     __shared__ __attribute__((aligned(16))) double lds[R_LDS];
     __shared__ int s_ticket, s_flag;
     __shared__ double s_red[8];
@@ -648,13 +664,13 @@ __global__ __launch_bounds__(rthreads(BT)) __attribute__((amdgpu_waves_per_eu(2,
     static_assert(TAB_MAX * sizeof(Node) <= R_LDS * sizeof(double), "node table exceeds the LDS");
     for (;;) {
         if (threadIdx.x == 0)
-            s_ticket = atomicAdd(ctl, 1);
+            s_ticket = atomicAdd(qctl, 1);
         __syncthreads();
         // the ticket, and all task data read with it, are uniform: keep them in
         // scalar registers
-        const int tk = __builtin_amdgcn_readfirstlane(s_ticket);
+        const int64_t tk = q0 + __builtin_amdgcn_readfirstlane(s_ticket);
         __syncthreads();
-        if (tk >= ntasks)
+        if (tk >= q0 + qn)
             break;
         long long t_take = 0;
         if (trace && threadIdx.x == 0)
@@ -734,9 +750,9 @@ __global__ __launch_bounds__(rthreads(BT)) __attribute__((amdgpu_waves_per_eu(2,
         const int np = rpublish(task, F.T, off);
         release(F.cnt, off, np);
         if (trace && threadIdx.x == 0) {
-            trace[3 * (int64_t)tk] = t_take;
-            trace[3 * (int64_t)tk + 1] = t_ready;
-            trace[3 * (int64_t)tk + 2] = wall_clock64();
+            trace[3 * tk] = t_take;
+            trace[3 * tk + 1] = t_ready;
+            trace[3 * tk + 2] = wall_clock64();
         }
     }
 }
@@ -790,6 +806,11 @@ struct RoundExec {
     long long *d_trace = nullptr;
     std::vector<long long> h_trace;
     std::vector<RTask> order;
+    // task queues (one per XCD by default)
+    int queues = 8;
+    int nq = 1;
+    std::vector<int64_t> qoff;
+    int64_t *d_qoff = nullptr;
 };
 
 namespace {
@@ -805,6 +826,7 @@ void free_arena(RoundExec *r)
     if (r->d_trace)
         (void)hipFree(r->d_trace);
     r->d_trace = nullptr;
+    r->d_qoff = nullptr; // inside the task allocation
     r->h_trace.clear();
     if (r->h_tab)
         (void)hipHostFree(r->h_tab);
@@ -868,7 +890,7 @@ fbt_status build(RoundExec *r, int bt, int nf, const int64_t *n, const double *c
         if (m)
             ci += rcount(T).size;
     }
-    r->cnt_ints = ci + 64;
+    r->cnt_ints = ci + R_CTL_WORDS;
     const size_t cnt_off = bytes;
     bytes = up256(bytes + r->cnt_ints * sizeof(int));
     for (int f = 0; f < nf; ++f) {
@@ -944,7 +966,8 @@ fbt_status build(RoundExec *r, int bt, int nf, const int64_t *n, const double *c
     }
     const int slots = per_cu * prop.multiProcessorCount;
     std::string perr;
-    const RPlan plan = rplan(pf, bt, slots, &perr);
+    const int nq = (r->queues > 0 && slots % r->queues == 0) ? r->queues : 1;
+    const RPlan plan = rplan_queues(pf, bt, slots, nq, &perr);
     if (!perr.empty()) {
         if (err)
             *err = perr;
@@ -952,11 +975,18 @@ fbt_status build(RoundExec *r, int bt, int nf, const int64_t *n, const double *c
     }
     r->ntasks = (int)plan.order.size();
     r->order = plan.order;
+    r->nq = nq;
+    r->qoff = plan.qoff;
     r->est_us = plan.est_us;
-    r->grid = std::min(slots, std::max(r->ntasks, 1));
+    // every queue gets slots / nq workgroups (all resident at once)
+    r->grid = slots;
     if (r->ntasks > 0) {
-        RCHK(hipMalloc((void **)&r->d_tasks, plan.order.size() * sizeof(RTask)));
+        RCHK(hipMalloc((void **)&r->d_tasks, plan.order.size() * sizeof(RTask) +
+                                                 (nq + 1) * sizeof(int64_t)));
         RCHK(hipMemcpy(r->d_tasks, plan.order.data(), plan.order.size() * sizeof(RTask),
+                       hipMemcpyHostToDevice));
+        r->d_qoff = reinterpret_cast<int64_t *>(r->d_tasks + plan.order.size());
+        RCHK(hipMemcpy(r->d_qoff, plan.qoff.data(), (nq + 1) * sizeof(int64_t),
                        hipMemcpyHostToDevice));
     }
     r->bt = bt;
@@ -1005,6 +1035,16 @@ void round_destroy(RoundExec *r)
 }
 
 float round_last_ms(const RoundExec *r) { return r ? r->last_ms : 0.0f; }
+
+void round_set_queues(RoundExec *r, int queues)
+{
+    if (r && queues != r->queues) {
+        r->queues = queues;
+        r->version = ~(uint64_t)0; // new plan at the next call
+    }
+}
+
+int round_queues(const RoundExec *r) { return r ? r->queues : 0; }
 
 void round_set_trace(RoundExec *r, bool on)
 {
@@ -1073,7 +1113,7 @@ fbt_status round_eval(RoundExec *r, int bt, int nf, const int64_t *n, const doub
     RCHK(hipMemcpyAsync(r->d_fields, r->h_fields, (size_t)nf * sizeof(RField),
                         hipMemcpyHostToDevice, r->stream));
     RCHK(hipMemsetAsync(r->d_cnt, 0, r->cnt_ints * sizeof(int), r->stream));
-    int *ctl = r->d_cnt + (r->cnt_ints - 64);
+    int *ctl = r->d_cnt + (r->cnt_ints - R_CTL_WORDS);
     const int64_t limit = (int64_t)5000 * r->tick_khz; // 5 s of waiting for one counter
     if (r->trace_on && !r->d_trace)
         RCHK(hipMalloc((void **)&r->d_trace, (size_t)r->ntasks * 3 * sizeof(long long)));
@@ -1081,10 +1121,10 @@ fbt_status round_eval(RoundExec *r, int bt, int nf, const int64_t *n, const doub
     RCHK(hipEventRecord(r->e0, r->stream));
     if (bt == 64)
         hipLaunchKernelGGL(k_round<64>, dim3(r->grid), dim3(rthreads(64)), 0, r->stream, r->d_fields,
-                           r->d_tasks, r->ntasks, ctl, limit, trace);
+                           r->d_tasks, r->d_qoff, r->nq, ctl, limit, trace);
     else
         hipLaunchKernelGGL(k_round<128>, dim3(r->grid), dim3(rthreads(128)), 0, r->stream, r->d_fields,
-                           r->d_tasks, r->ntasks, ctl, limit, trace);
+                           r->d_tasks, r->d_qoff, r->nq, ctl, limit, trace);
     RCHK(hipGetLastError());
     RCHK(hipEventRecord(r->e1, r->stream));
     RCHK(hipMemcpyAsync(r->h_out, r->d_out, (size_t)nf * 16 * sizeof(double),
@@ -1098,8 +1138,11 @@ fbt_status round_eval(RoundExec *r, int bt, int nf, const int64_t *n, const doub
     }
     RCHK(hipStreamSynchronize(r->stream));
     RCHK(hipEventElapsedTime(&r->last_ms, r->e0, r->e1));
-    const int *hctl = r->h_cnt + (r->cnt_ints - 64);
-    if (hctl[1] != 0 || hctl[0] < r->ntasks) {
+    const int *hctl = r->h_cnt + (r->cnt_ints - R_CTL_WORDS);
+    bool drained = hctl[1] == 0;
+    for (int q = 0; q < r->nq; ++q)
+        drained = drained && hctl[RQ_CTL + RQ_STRIDE * q] >= r->qoff[q + 1] - r->qoff[q];
+    if (!drained) {
         if (err)
             *err = "round: a dependency wait of the persistent kernel ran out of time";
         return FBT_EDEVICE;

@@ -189,7 +189,11 @@ def test_group_limits_and_autotune(fields, tmp_path):
     bt.autotune(calls[0][small], 2, path)
     rec = json.loads(path.read_text())
     say("autotune", rec)
-    assert rec["exec"] == 0 and rec["chosen"] in ("per_order", "none", "all_4", "all_16", "all_64")
+    assert rec["exec"] in (0, 2) and rec["chosen"] in ("per_order", "none", "all_4", "all_16",
+                                                       "all_64")
+    assert rec["seconds_persistent_64"] > 0 and rec["seconds_persistent_128"] > 0
+    if rec["exec"] == 2:
+        assert rec["tile"] in (64, 128)
     # "none" stores no limit, "all_N" stores N for every order; "per_order"
     # may store none either, when no limit was fastest for every order
     if rec["chosen"] == "none":
@@ -201,14 +205,23 @@ def test_group_limits_and_autotune(fields, tmp_path):
     bt2.set_fields([data[i] for i in small])
     bt2.load_tuning(path)
     assert bt2.exec == rec["exec"]
+    if rec["exec"] == 2:
+        assert bt2.tile == rec["tile"]
     for k, v in rec["limits"].items():
         assert bt2.group_limit(int(k)) == v
     a = bt2.eval(calls[0][small], 2)
     mode_s = np.zeros(nf, dtype=np.int32)
     mode_s[small] = 2
     b = bw.eval(calls[0], mode_s)
-    for x, y in zip(a, b):
-        np.testing.assert_array_equal(x, y[small])
+    if rec["exec"] == 0:
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(x, y[small])
+    else:
+        # the persistent execution: the same statuses, log-likelihoods to
+        # rounding (its blocking differs)
+        np.testing.assert_array_equal(a[3], b[3][small])
+        ok = a[3] == fbt.OK
+        np.testing.assert_allclose(a[0][ok], b[0][small][ok], rtol=1e-9)
     for bb in (bw, bl, bt, bt2):
         bb.close()
 

@@ -94,16 +94,18 @@ CASES = [
 
 
 @pytest.mark.parametrize("ns,modes,bt", CASES)
-@pytest.mark.parametrize("slots", [1, 7, 512])
-def test_ticket_order_complete_and_ordered(ns, modes, bt, slots):
-    order, est = fbt.round_plan(ns, modes, tile=bt, slots=slots)
-    assert est > 0
+@pytest.mark.parametrize("slots,queues", [(1, 1), (7, 1), (512, 1), (16, 2), (512, 8)])
+def test_ticket_order_complete_and_ordered(ns, modes, bt, slots, queues):
+    order, qoff, est = fbt.round_plan(ns, modes, tile=bt, slots=slots, queues=queues)
+    assert est > 0 and qoff[0] == 0 and qoff[-1] == len(order) and np.all(np.diff(qoff) >= 0)
     fl = _fields(ns, modes, bt)
-    seen = {}
+    seen, queue = {}, {}
     for q, (f, ty, i, j) in enumerate(order.tolist()):
         key = (f, ty, i, j)
         assert key not in seen, key
         seen[key] = q
+        qq = int(np.searchsorted(qoff, q, side="right")) - 1
+        assert queue.setdefault(f, qq) == qq, "a field's tasks span two queues"
     for f, (T, m) in enumerate(fl):
         got = {(ty, i, j) for (ff, ty, i, j) in seen if ff == f}
         assert got == expected_tasks(T, m), f
@@ -114,10 +116,15 @@ def test_ticket_order_complete_and_ordered(ns, modes, bt, slots):
             assert seen[(f,) + p] < q, ((f, ty, i, j), p)
 
 
-def _simulate(order, fl, workers, rng):
+def _simulate(order, fl, workers, rng, qoff=None):
     """Random interleaving of `workers` workgroups taking tickets in order and
-    waiting on the kernel's counters; checks the true predecessors at every
-    start of a phase.  Returns the number of finished tasks."""
+    waiting on the kernel's counters (with queues: worker w takes tickets of
+    queue w % len(queues) only); checks the true predecessors at every start
+    of a phase.  Returns the number of finished tasks."""
+    if qoff is None:
+        qoff = [0, len(order)]
+    nq = len(qoff) - 1
+    nxt_q = list(qoff[:-1])
     cnt = [dict() for _ in fl]
     deps = {}
 
@@ -129,7 +136,6 @@ def _simulate(order, fl, workers, rng):
         return deps[key]
 
     done = set()
-    nxt = 0
     state = [None] * workers      # None idle, else [task, stage]
     # stages: 0 waiting (first waits), 1 running phase 0, 2 waiting (last wait), 3 running phase 1
     while True:
@@ -137,7 +143,7 @@ def _simulate(order, fl, workers, rng):
         for w in range(workers):
             st = state[w]
             if st is None:
-                if nxt < len(order):
+                if nxt_q[w % nq] < qoff[w % nq + 1]:
                     actions.append((w, "take"))
                 continue
             (f, ty, i, j), stage = st
@@ -154,8 +160,8 @@ def _simulate(order, fl, workers, rng):
             break
         w, act = rng.choice(actions)
         if act == "take":
-            state[w] = [tuple(order[nxt]), 0]
-            nxt += 1
+            state[w] = [tuple(order[nxt_q[w % nq]]), 0]
+            nxt_q[w % nq] += 1
             continue
         (f, ty, i, j), stage = state[w]
         T, m = fl[f]
@@ -184,11 +190,12 @@ def _simulate(order, fl, workers, rng):
 def test_counter_waits_imply_data_order(ns, modes, bt):
     rng = random.Random(1234)
     fl = _fields(ns, modes, bt)
-    for slots, workers in ((1, 1), (7, 3), (512, 8), (512, 600)):
-        order, _ = fbt.round_plan(ns, modes, tile=bt, slots=slots)
+    for slots, workers, queues in ((1, 1, 1), (7, 3, 1), (512, 8, 1), (512, 600, 1),
+                                   (16, 4, 2), (512, 16, 8), (512, 64, 8)):
+        order, qoff, _ = fbt.round_plan(ns, modes, tile=bt, slots=slots, queues=queues)
         for rep in range(3):
-            finished = _simulate(order.tolist(), fl, workers, rng)
-            assert finished == len(order), (slots, workers, rep)
+            finished = _simulate(order.tolist(), fl, workers, rng, qoff.tolist())
+            assert finished == len(order), (slots, workers, queues, rep)
 
 
 def test_plan_rejects_bad_arguments():
@@ -196,18 +203,20 @@ def test_plan_rejects_bad_arguments():
         fbt.round_plan([100], [2], tile=96)
     with pytest.raises(fbt.FisherBTError):
         fbt.round_plan([0], [2], tile=64)
-    order, _ = fbt.round_plan([100, 50], [0, 3], tile=64)
+    with pytest.raises(fbt.FisherBTError):
+        fbt.round_plan([10], [2], tile=64, queues=9)
+    order, _, _ = fbt.round_plan([100, 50], [0, 3], tile=64)
     assert len(order) == 0
 
 
 def test_plan_of_the_many_field_round():
     """256 fields, n ~ U[500, 4000] (the batched workload): the plan is built
-    and checked on the host, and the list schedule's makespan is within a few
-    percent of the bound that the critical path and the total work set."""
+    and checked on the host for one queue and for one per XCD."""
     rng = np.random.default_rng(5)
     ns = rng.integers(500, 4001, size=256)
-    for bt in (64, 128):
-        order, est = fbt.round_plan(ns, [2] * 256, tile=bt, slots=512)
+    for bt, slots in ((64, 512), (128, 256)):
         T = [(n + 1 + bt - 1) // bt for n in ns]
-        assert len(order) == sum(3 * t * (t + 1) // 2 + 2 * t * t + 1 for t in T)
-        assert est > 0
+        for queues in (1, 8):
+            order, qoff, est = fbt.round_plan(ns, [2] * 256, tile=bt, slots=slots, queues=queues)
+            assert len(order) == sum(3 * t * (t + 1) // 2 + 2 * t * t + 1 for t in T)
+            assert est > 0
