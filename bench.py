@@ -169,6 +169,39 @@ def copy_calibration():
                       "repeats": 3}), flush=True)
 
 
+def round_trace_summary(tr, bt, kernel_ms):
+    """Per-task-type breakdown of a persistent round's trace: workgroup time
+    busy and waiting, task counts, the products' executed FP64 rate per
+    workgroup, and the share of busy workgroup time per type."""
+    import numpy as np
+
+    f, ty, i, j, t_take, t_ready, t_end = tr.T
+    tick_ms = 1e-5  # the device wall clock runs at 100 MHz
+    busy = (t_end - t_ready) * tick_ms
+    wait = (t_ready - t_take) * tick_ms
+    fl = np.zeros(len(ty))
+    b3 = 2.0 * bt ** 3
+    m = ty == 1
+    fl[m] = 2.0 * bt * bt * (j[m] * bt) + np.where(i[m] > j[m], b3, 0.0)
+    m = ty == 2
+    fl[m] = 2.0 * bt * bt * (i[m] * bt) + b3
+    m = ty == 3
+    fl[m] = 2.0 * (2.0 * bt * bt * (j[m] * bt) + b3)
+    span_ms = (t_end.max() - t_take.min()) * tick_ms
+    out = {"kernel_ms": kernel_ms, "trace_span_ms": span_ms,
+           "workgroup_busy_ms": float(busy.sum()), "workgroup_wait_ms": float(wait.sum()),
+           "executed_flops": float(fl.sum()), "types": {}}
+    for k, name in enumerate(("generation", "cholesky", "forward_subst", "w_tiles", "reduce")):
+        m = ty == k
+        bsum = float(busy[m].sum())
+        out["types"][name] = {
+            "tasks": int(m.sum()), "busy_ms": bsum, "wait_ms": float(wait[m].sum()),
+            "busy_share": bsum / float(busy.sum()),
+            "mean_busy_us": 1e3 * bsum / max(1, int(m.sum())),
+            "tflops_per_workgroup": (float(fl[m].sum()) / (bsum * 1e-3) / 1e12) if fl[m].sum() else None}
+    return out
+
+
 def batch_bench(args):
     """One Fisher-BT round over many independent fields (loglik + score +
     Fisher for every field), through the batch executor."""
@@ -229,6 +262,13 @@ def batch_bench(args):
                       "kernel_ms_last_round": kernel_ms,
                       "launches_per_round": 1}
         log("persistent round: tile %d, %d tasks, kernel %.1f ms" % (b.tile, ntasks, kernel_ms))
+        if args.round_trace:
+            # one more round with the per-task trace on (outside the timed rounds)
+            b.set_round_trace(True)
+            b.eval(thetas, fbt.Batch.EVAL)
+            round_info["trace"] = round_trace_summary(b.round_trace(), b.tile,
+                                                      b.round_stats()[2])
+            b.set_round_trace(False)
     b.close()
     ns = np.array([z.size for _, z in fields], dtype=np.float64)
     # n^3 / 3 (factorisation) + 2 n^3 (two-sided W phase of both derivative
@@ -450,6 +490,9 @@ def main():
     ap.add_argument("--batch", type=int, default=0,
                     help="instead of the n=20k evaluation, time one round over this many fields")
     ap.add_argument("--batch-workers", type=int, default=2)
+    ap.add_argument("--round-trace", action="store_true",
+                    help="persistent execution: one extra traced round, its per-task-type "
+                         "breakdown in the JSON line")
     ap.add_argument("--batch-tile", type=int, default=0,
                     help="tile rows of the persistent execution (64, 128; 0: default)")
     ap.add_argument("--batch-exec", choices=("workers", "graph", "tuned", "persistent"),
