@@ -296,6 +296,51 @@ def batch_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def batch_fit_bench(args):
+    """Fisher-BT for many replicate fields at once (fbt_batch_fit): every
+    field's fit from the L9 start, all fits' evaluations of one iteration in
+    one round (one persistent launch)."""
+    import numpy as np
+
+    import paper_2601_11437_amd as fbt
+    import synth
+
+    t0 = time.perf_counter()
+    fields, theta_true = synth.batch_fit_workload(args.batch_fit)
+    log("batch-fit data: %d fields generated in %.1f s" % (len(fields), time.perf_counter() - t0))
+    b = fbt.Batch(args.batch_workers)
+    b.set_fields(fields)
+    b.set_exec(fbt.Batch.PERSISTENT)
+    if args.batch_tile:
+        b.set_tile(args.batch_tile)
+    # one untimed round builds the plan and the device arena
+    b.eval(theta_true, fbt.Batch.EVAL)
+    t0 = time.perf_counter()
+    fits, st, rounds = b.fit()
+    dt = time.perf_counter() - t0
+    b.close()
+    nf = len(fields)
+    ok = [f for f in fits if f is not None and f["status"] == fbt.OK]
+    conv = sum(1 for f in ok if f["converged"] and not f["used_nelder_mead"])
+    nm = sum(1 for f in ok if f["used_nelder_mead"])
+    ns = np.array([z.size for _, z in fields], dtype=np.float64)
+    th = np.array([f["theta"] for f in fits])
+    out = {"metric": "Fisher-BT fits of %d replicate fields, n~U[500,4000]: wall time" % nf,
+           "value": dt, "unit": "s", "n_gpus": 1, "higher_is_better": False, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "%d fields, n_f ~ U[500, 4000] uniform points, true theta_f "
+                                  "uniform in [0.5,2]x[0.02,0.3]x[0.3,2.5], one realisation "
+                                  "each; Algorithm 1 from the L9 start" % nf,
+                      "exec": "persistent", "tile": args.batch_tile or 128},
+           "rounds": rounds, "ms_per_round": 1e3 * dt / max(1, rounds),
+           "fits_ok": len(ok), "converged_by_scoring": conv, "nelder_mead": nm,
+           "loglik_calls_total": int(sum(f["n_loglik_calls"] for f in ok)),
+           "grad_calls_total": int(sum(f["n_grad_calls"] for f in ok)),
+           "median_rel_err_vs_true": float(np.median(np.abs(th - theta_true) / theta_true)),
+           "sum_n_cubed": float(np.sum(ns ** 3))}
+    print(json.dumps(out), flush=True)
+
+
 def fit_bench(args):
     """Algorithm 1 end to end at the benchmark size: Fisher-BT from the L9
     start within the paper's simulation bounds, in FP64 and in the mixed form;
@@ -490,6 +535,9 @@ def main():
     ap.add_argument("--batch", type=int, default=0,
                     help="instead of the n=20k evaluation, time one round over this many fields")
     ap.add_argument("--batch-workers", type=int, default=2)
+    ap.add_argument("--batch-fit", type=int, default=0,
+                    help="Fisher-BT fits of this many replicate fields at once "
+                         "(persistent execution, one round per iteration)")
     ap.add_argument("--round-trace", action="store_true",
                     help="persistent execution: one extra traced round, its per-task-type "
                          "breakdown in the JSON line")
@@ -519,6 +567,9 @@ def main():
         return
     if args.fit and args.gpus == 1:
         fit_bench(args)
+        return
+    if args.batch_fit and args.gpus == 1:
+        batch_fit_bench(args)
         return
     if args.batch and args.gpus == 1:
         batch_bench(args)

@@ -271,6 +271,24 @@ fbt_status fbt_batch_set_fields(fbt_batch *b, int32_t nf, const int64_t *n,
 fbt_status fbt_batch_eval(fbt_batch *b, const double *thetas, const int32_t *mode,
                           double *loglik, double *score, double *fisher, int32_t *status);
 const char *fbt_batch_last_error(const fbt_batch *b);
+/* Algorithm 1 (Fisher-BT) for every field of the batch at once: each field's
+ * fit is fbt_fit_evaluator's driver with options *opt (its theta0 is
+ * ignored; theta0 here is nf x 3 row-major starts, or NULL for the L9 start
+ * of Table 1 from [opt->lo, opt->hi]), and all the evaluations the running
+ * fits ask for next (log-likelihood trials, derivative evaluations,
+ * Nelder-Mead points) are made together in one fbt_batch_eval call per
+ * round - one launch of the round kernel in the persistent execution.  A
+ * field's fit is the one fbt_fit_evaluator gives over the batch's evaluation
+ * of that field.  active (NULL: all) selects fields; res[nf] and status[nf]
+ * receive each selected field's result and fbt_fit_evaluator's status
+ * (FBT_EBUDGET with nelder_mead = 0 included); *rounds (may be NULL) the
+ * number of evaluation rounds.  opt->cb runs on the fields' host threads
+ * (one per selected field; cb_user is shared).  Returns FBT_OK unless a
+ * round failed as a whole (FBT_EDEVICE, FBT_ENOMEM; the fits then stop with
+ * that status), or FBT_EINVAL for bad arguments. */
+fbt_status fbt_batch_fit(fbt_batch *b, const fbt_fit_options *opt, const double *theta0,
+                         const int32_t *active, fbt_fit_result *res, int32_t *status,
+                         int32_t *rounds);
 
 /* Execution of fbt_batch_eval (batched evaluations of one Fisher-BT
  * iteration over many fields, the batching of Section 2's estimator across

@@ -101,6 +101,8 @@ SIGNATURES = {
     "fbt_batch_group_limit": (_i32, [_p, _i64]),
     "fbt_batch_autotune": (ctypes.c_int, [_p, _p, _p, ctypes.c_char_p]),
     "fbt_batch_load_tuning": (ctypes.c_int, [_p, ctypes.c_char_p]),
+    "fbt_batch_fit": (ctypes.c_int, [_p, ctypes.POINTER(FitOptions), _p, _p, _p, _p,
+                                     ctypes.POINTER(_i32)]),
     "fbt_batch_set_tile": (ctypes.c_int, [_p, _i32]),
     "fbt_batch_get_tile": (_i32, [_p]),
     "fbt_batch_round_stats": (ctypes.c_int, [_p, ctypes.POINTER(_i64), _dp, _dp]),
@@ -451,6 +453,36 @@ class Batch:
     @property
     def exec(self) -> int:
         return int(lib().fbt_batch_get_exec(self._h))
+
+    def fit(self, theta0=None, active=None, **opts):
+        """Algorithm 1 for every field at once, one evaluation round per
+        iteration of the fits (fbt_batch_fit).  theta0: (nf, 3) starts or
+        None (L9); active: (nf,) flags or None (all).  Returns (list of result
+        dicts, None for unselected fields; status (nf,); rounds)."""
+        o, keep = _options(**opts)
+        t0 = None
+        if theta0 is not None:
+            t0 = np.ascontiguousarray(theta0, dtype=np.float64).reshape(self.nf, 3)
+        act = None
+        if active is not None:
+            act = np.ascontiguousarray(np.asarray(active, dtype=bool).astype(np.int32))
+        res = (FitResult * max(1, self.nf))()
+        status = np.zeros(self.nf, dtype=np.int32)
+        rounds = _i32(0)
+        st = lib().fbt_batch_fit(self._h, ctypes.byref(o), None if t0 is None else t0.ctypes.data,
+                                 None if act is None else act.ctypes.data, res,
+                                 status.ctypes.data, ctypes.byref(rounds))
+        if st != OK:
+            raise FisherBTError(st, lib().fbt_batch_last_error(self._h).decode())
+        out = []
+        for f in range(self.nf):
+            if act is not None and not act[f]:
+                out.append(None)
+                continue
+            d = _result(res[f])
+            d["status"] = int(status[f])
+            out.append(d)
+        return out, status, int(rounds.value)
 
     def set_tile(self, tile: int):
         """Tile rows of the persistent execution: 64, 128 or 0 (default)."""

@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
 #include <cstdio>
 #include <map>
 #include <atomic>
@@ -343,6 +344,141 @@ fbt_status fbt_batch_eval(fbt_batch *b, const double *thetas, const int32_t *mod
 }
 
 const char *fbt_batch_last_error(const fbt_batch *b) { return b ? b->err.c_str() : ""; }
+
+} // extern "C"
+
+namespace {
+
+// Batched Fisher-BT: every field runs the library's driver (fbt_fit_evaluator,
+// Algorithm 1) on a host thread of its own, with an evaluator that posts the
+// request and sleeps; once every running driver has posted (or finished), the
+// calling thread evaluates all posted requests in one fbt_batch_eval call (a
+// round: one launch of the round kernel in the persistent execution) and
+// wakes the drivers with their results.  Each driver sees exactly the
+// evaluations a single-field fit over the batch's evaluator would see.
+struct FitShared {
+    std::mutex mu;
+    std::condition_variable coord, field;
+    int posted = 0, finished = 0;
+};
+
+struct FitSlot {
+    FitShared *S = nullptr;
+    int mode = 0; // 1 log-likelihood, 2 derivatives
+    double th[3] = {0, 0, 0};
+    double ll = 0, sc[3] = {0, 0, 0}, fi[9] = {0};
+    fbt_status st = FBT_OK;
+    bool posted = false, ready = false;
+};
+
+fbt_status fit_post(FitSlot *sl, int mode, const double *th, double *ll, double *sc, double *fi)
+{
+    FitShared &S = *sl->S;
+    std::unique_lock<std::mutex> lk(S.mu);
+    sl->mode = mode;
+    std::memcpy(sl->th, th, 3 * sizeof(double));
+    sl->ready = false;
+    sl->posted = true;
+    ++S.posted;
+    S.coord.notify_one();
+    S.field.wait(lk, [&] { return sl->ready; });
+    if (sl->st == FBT_OK) {
+        *ll = sl->ll;
+        if (mode == 2) {
+            std::memcpy(sc, sl->sc, 3 * sizeof(double));
+            std::memcpy(fi, sl->fi, 9 * sizeof(double));
+        }
+    }
+    return sl->st;
+}
+
+fbt_status fit_loglik(void *user, const double theta[3], double *ll)
+{
+    return fit_post(static_cast<FitSlot *>(user), 1, theta, ll, nullptr, nullptr);
+}
+
+fbt_status fit_eval(void *user, const double theta[3], double *ll, double score[3],
+                    double fisher[9])
+{
+    return fit_post(static_cast<FitSlot *>(user), 2, theta, ll, score, fisher);
+}
+
+} // namespace
+
+extern "C" {
+
+fbt_status fbt_batch_fit(fbt_batch *b, const fbt_fit_options *opt, const double *theta0,
+                         const int32_t *active, fbt_fit_result *res, int32_t *status,
+                         int32_t *rounds)
+{
+    if (!b || !opt || !res || !status)
+        return FBT_EINVAL;
+    const int32_t nf = (int32_t)b->n.size();
+    FitShared S;
+    std::vector<FitSlot> slot(nf);
+    std::vector<fbt_fit_options> o(nf, *opt);
+    std::vector<int32_t> run;
+    for (int32_t f = 0; f < nf; ++f) {
+        slot[f].S = &S;
+        o[f].theta0 = theta0 ? theta0 + 3 * f : nullptr;
+        status[f] = FBT_OK;
+        if (!active || active[f])
+            run.push_back(f);
+    }
+    if (rounds)
+        *rounds = 0;
+    const int nrun = (int)run.size();
+    std::vector<std::thread> th;
+    th.reserve(nrun);
+    for (int32_t f : run)
+        th.emplace_back([&, f] {
+            fbt_evaluator ev{&slot[f], fit_loglik, fit_eval};
+            std::memset(&res[f], 0, sizeof(fbt_fit_result));
+            status[f] = fbt_fit_evaluator(&ev, &o[f], &res[f]);
+            std::lock_guard<std::mutex> g(S.mu);
+            ++S.finished;
+            S.coord.notify_one();
+        });
+    std::vector<double> thetas(3 * (size_t)nf, 1.0), ll(nf), sc(3 * (size_t)nf), fi(9 * (size_t)nf);
+    std::vector<int32_t> mode(nf), st(nf);
+    fbt_status fatal = FBT_OK;
+    std::unique_lock<std::mutex> lk(S.mu);
+    for (;;) {
+        S.coord.wait(lk, [&] { return S.posted + S.finished == nrun; });
+        if (S.finished == nrun)
+            break;
+        for (int32_t f = 0; f < nf; ++f) {
+            mode[f] = slot[f].posted ? slot[f].mode : 0;
+            if (slot[f].posted)
+                std::memcpy(&thetas[3 * f], slot[f].th, 3 * sizeof(double));
+        }
+        lk.unlock();
+        const fbt_status r = fbt_batch_eval(b, thetas.data(), mode.data(), ll.data(), sc.data(),
+                                            fi.data(), st.data());
+        lk.lock();
+        if (r != FBT_OK && fatal == FBT_OK)
+            fatal = r;
+        for (int32_t f = 0; f < nf; ++f) {
+            FitSlot &sl = slot[f];
+            if (!sl.posted)
+                continue;
+            sl.st = r != FBT_OK ? r : (fbt_status)st[f];
+            sl.ll = ll[f];
+            std::memcpy(sl.sc, &sc[3 * f], 3 * sizeof(double));
+            std::memcpy(sl.fi, &fi[9 * f], 9 * sizeof(double));
+            sl.posted = false;
+            sl.ready = true;
+        }
+        S.posted = 0;
+        if (rounds)
+            ++*rounds;
+        S.field.notify_all();
+    }
+    lk.unlock();
+    for (std::thread &t : th)
+        t.join();
+    return fatal;
+}
 
 // The graph execution is switched off: its first capture and replay ended the
 // host process with a segmentation fault inside the capture / instantiate /

@@ -156,6 +156,18 @@ def batch_workload(nf: int = 256, seed: int = 5000, n_range=(500, 4000),
     return fields, batch_redraw_thetas(np.zeros((nf, 3)), np.ones(nf, bool), gen)
 
 
+def batch_fit_workload(nf: int = 256, seed: int = 6000, n_range=(500, 4000)):
+    """Replicate fields for batched fits: n_f ~ U[n_range] uniform points
+    each, a true theta_f uniform in sigma2 in [0.5, 2], alpha in [0.02, 0.3],
+    nu in [0.3, 2.5], and one realisation at theta_f (seed seed + 1 + f).
+    Returns (fields [(locs, z)], true thetas (nf x 3))."""
+    gen = rng(seed)
+    ns = gen.integers(n_range[0], n_range[1] + 1, nf)
+    thetas = batch_redraw_thetas(np.zeros((nf, 3)), np.ones(nf, bool), gen)
+    fields = [dataset(int(n), tuple(thetas[f]), seed + 1 + f)[:2] for f, n in enumerate(ns)]
+    return fields, thetas
+
+
 def batch_redraw_thetas(thetas, which, gen):
     """Redraw the evaluation points of the fields flagged in `which`."""
     thetas = np.array(thetas, dtype=np.float64)
