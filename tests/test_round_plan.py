@@ -116,13 +116,14 @@ def test_ticket_order_complete_and_ordered(ns, modes, bt, slots, queues):
             assert seen[(f,) + p] < q, ((f, ty, i, j), p)
 
 
-def _simulate(order, fl, workers, rng, qoff=None):
+def _simulate(order, fl, workers, rng, qoff=None, task_deps=None):
     """Random interleaving of `workers` workgroups taking tickets in order and
     waiting on the kernel's counters (with queues: worker w takes tickets of
     queue w % len(queues) only); checks the true predecessors at every start
     of a phase.  Returns the number of finished tasks."""
     if qoff is None:
         qoff = [0, len(order)]
+    task_deps = task_deps or fbt.round_task_deps
     nq = len(qoff) - 1
     nxt_q = list(qoff[:-1])
     cnt = [dict() for _ in fl]
@@ -132,7 +133,7 @@ def _simulate(order, fl, workers, rng, qoff=None):
         key = (f, ty, i, j)
         if key not in deps:
             T, m = fl[f]
-            deps[key] = fbt.round_task_deps(T, m, f, ty, i, j)
+            deps[key] = task_deps(T, m, f, ty, i, j)
         return deps[key]
 
     done = set()
@@ -220,3 +221,76 @@ def test_plan_of_the_many_field_round():
             order, qoff, est = fbt.round_plan(ns, [2] * 256, tile=bt, slots=slots, queues=queues)
             assert len(order) == sum(3 * t * (t + 1) // 2 + 2 * t * t + 1 for t in T)
             assert est > 0
+
+
+MUTATIONS = {
+    # a forward-substitution tile waits for one X tile too few above it
+    "lsolve_one_short": ("off[k] = c.xd + j, need[k++] = i; // X tiles above",
+                         "off[k] = c.xd + j, need[k++] = i - 1; // X tiles above"),
+    # a W tile does not wait for the nu-matrix column of X
+    "rsolve_no_nu_column": ("        off[k] = c.xd + T + j, need[k++] = T;\n", ""),
+    # a Cholesky tile takes the previous block column as finished one tile early
+    "chol_column_early": ("need[k++] = T - j + 1; // block columns",
+                          "need[k++] = T - j; // block columns"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_planted_counter_mistakes_are_caught(name, tmp_path):
+    """The counter waits of the kernel with one mistake planted (a copy of
+    the header, compiled on the host with the planner): the random
+    interleavings must then run some task before its data are ready."""
+    import ctypes
+    import os
+    import shutil
+    import subprocess
+
+    if not shutil.which("g++"):
+        pytest.skip("g++ not available")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    csrc = os.path.join(root, "paper_2601_11437_amd", "csrc")
+    hdr = open(os.path.join(csrc, "fbt_round.h")).read()
+    old, new = MUTATIONS[name]
+    assert old in hdr
+    (tmp_path / "fbt_round.h").write_text(hdr.replace(old, new))
+    # the planner's sources beside the planted header, so that their quoted
+    # includes find it
+    for src in ("fbt_plan.h", "fbt_plan.cpp"):
+        shutil.copy(os.path.join(csrc, src), tmp_path / src)
+    so = str(tmp_path / "libplan.so")
+    subprocess.run(["g++", "-O1", "-std=c++17", "-shared", "-fPIC", "-I",
+                    os.path.join(root, "include"), str(tmp_path / "fbt_plan.cpp"), "-o", so],
+                   check=True, capture_output=True)
+    L = ctypes.CDLL(so)
+    f = L.fbt_round_task_deps
+    f.restype, f.argtypes = fbt.SIGNATURES["fbt_round_task_deps"]
+    # the planted copy differs from the library's waits
+    probe = {"lsolve_one_short": (8, 2, 2, 5, 3), "rsolve_no_nu_column": (8, 2, 3, 5, 3),
+             "chol_column_early": (8, 2, 1, 5, 3)}[name]
+
+    def deps(T, mode, field, type_, i, j):
+        off, need, pub = (np.zeros(4, dtype=np.int32) for _ in range(3))
+        npub = ctypes.c_int32(0)
+        k = f(T, mode, (field << 3) | type_, (i << 16) | j, off.ctypes.data, need.ctypes.data,
+              pub.ctypes.data, ctypes.byref(npub))
+        return list(zip(off[:k].tolist(), need[:k].tolist())), pub[:npub.value].tolist()
+
+    T_, m_, ty_, i_, j_ = probe
+    assert deps(T_, m_, 0, ty_, i_, j_) != fbt.round_task_deps(T_, m_, 0, ty_, i_, j_)
+    rng = random.Random(7)
+    caught = False
+    for ns, modes, bt in CASES:
+        fl = _fields(ns, modes, bt)
+        for slots, workers in ((7, 3), (512, 8), (512, 600)):
+            order, qoff, _ = fbt.round_plan(ns, modes, tile=bt, slots=slots, queues=1)
+            for rep in range(3):
+                try:
+                    _simulate(order.tolist(), fl, workers, rng, qoff.tolist(), task_deps=deps)
+                except AssertionError:
+                    caught = True
+                    break
+            if caught:
+                break
+        if caught:
+            break
+    assert caught, name
