@@ -306,8 +306,12 @@ def batch_fit_bench(args):
     import synth
 
     t0 = time.perf_counter()
-    fields, theta_true = synth.batch_fit_workload(args.batch_fit)
-    log("batch-fit data: %d fields generated in %.1f s" % (len(fields), time.perf_counter() - t0))
+    approx = []
+    fields, theta_true = synth.batch_fit_workload(
+        args.batch_fit, approx=approx, draw="rff",
+        progress=lambda f: (f + 1) % 32 == 0 and log("batch-fit data: %d fields" % (f + 1)))
+    log("batch-fit data: %d fields generated in %.1f s (%d by the approximate draw)"
+        % (len(fields), time.perf_counter() - t0, len(approx)))
     b = fbt.Batch(args.batch_workers)
     b.set_fields(fields)
     b.set_exec(fbt.Batch.PERSISTENT)
@@ -330,8 +334,10 @@ def batch_fit_bench(args):
            "data": "synthetic",
            "config": {"workload": "%d fields, n_f ~ U[500, 4000] uniform points, true theta_f "
                                   "uniform in [0.5,2]x[0.02,0.3]x[0.3,2.5], one realisation "
-                                  "each; Algorithm 1 from the L9 start" % nf,
+                                  "each (random-Fourier-feature draw, 4096 features); "
+                                  "Algorithm 1 from the L9 start" % nf,
                       "exec": "persistent", "tile": args.batch_tile or 128},
+           "fields_approximate_draw": len(approx),
            "rounds": rounds, "ms_per_round": 1e3 * dt / max(1, rounds),
            "fits_ok": len(ok), "converged_by_scoring": conv, "nelder_mead": nm,
            "loglik_calls_total": int(sum(f["n_loglik_calls"] for f in ok)),

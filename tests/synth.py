@@ -156,15 +156,34 @@ def batch_workload(nf: int = 256, seed: int = 5000, n_range=(500, 4000),
     return fields, batch_redraw_thetas(np.zeros((nf, 3)), np.ones(nf, bool), gen)
 
 
-def batch_fit_workload(nf: int = 256, seed: int = 6000, n_range=(500, 4000)):
+def batch_fit_workload(nf: int = 256, seed: int = 6000, n_range=(500, 4000), approx=None,
+                       progress=None, draw: str = "exact"):
     """Replicate fields for batched fits: n_f ~ U[n_range] uniform points
     each, a true theta_f uniform in sigma2 in [0.5, 2], alpha in [0.02, 0.3],
-    nu in [0.3, 2.5], and one realisation at theta_f (seed seed + 1 + f).
+    nu in [0.3, 2.5], and one realisation at theta_f (seed seed + 1 + f):
+    the exact draw (draw="exact"; where Sigma(theta_f) is numerically
+    indefinite it is replaced by the random-Fourier-feature draw on the same
+    locations, and f is appended to `approx` when given), or the
+    random-Fourier-feature draw for every field (draw="rff": the exact draw
+    costs a dense host Cholesky and n^2 Bessel values per field).
     Returns (fields [(locs, z)], true thetas (nf x 3))."""
     gen = rng(seed)
     ns = gen.integers(n_range[0], n_range[1] + 1, nf)
     thetas = batch_redraw_thetas(np.zeros((nf, 3)), np.ones(nf, bool), gen)
-    fields = [dataset(int(n), tuple(thetas[f]), seed + 1 + f)[:2] for f, n in enumerate(ns)]
+    fields = []
+    for f, n in enumerate(ns):
+        try:
+            if draw != "exact":
+                raise RuntimeError("approximate draw requested")
+            fields.append(dataset(int(n), tuple(thetas[f]), seed + 1 + f, max_redraws=0)[:2])
+        except RuntimeError:
+            g = rng(seed + 1 + f)
+            locs = uniform_locations(int(n), g)
+            fields.append((locs, rff_field(locs, thetas[f], g)))
+            if approx is not None:
+                approx.append(f)
+        if progress is not None:
+            progress(f)
     return fields, thetas
 
 
