@@ -105,11 +105,15 @@ def cpu_full(args):
 
 
 def kernel_source_sha256():
+    """SHA-256 of the evaluation kernels' source: fbt_kernels.hip followed by
+    fbt_device.h (the MFMA wrapper and the Matern entries it includes)."""
     import hashlib
 
-    path = os.path.join(ROOT, "paper_2601_11437_amd", "csrc", "fbt_kernels.hip")
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for name in ("fbt_kernels.hip", "fbt_device.h"):
+        with open(os.path.join(ROOT, "paper_2601_11437_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_traffic(kernel):
