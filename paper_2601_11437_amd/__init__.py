@@ -107,6 +107,7 @@ SIGNATURES = {
     "fbt_batch_get_tile": (_i32, [_p]),
     "fbt_batch_round_stats": (ctypes.c_int, [_p, ctypes.POINTER(_i64), _dp, _dp]),
     "fbt_batch_set_round_trace": (ctypes.c_int, [_p, _i32]),
+    "fbt_batch_set_round_graph": (ctypes.c_int, [_p, _i32]),
     "fbt_batch_round_trace": (_i64, [_p, _p, _i64]),
     "fbt_round_plan": (ctypes.c_int, [_i32, _p, _p, _i32, _i32, _i32, ctypes.POINTER(_i64), _p,
                                       _p, _dp]),
@@ -509,6 +510,12 @@ class Batch:
         st = lib().fbt_batch_set_queues(self._h, int(queues))
         if st != OK:
             raise FisherBTError(st, "fbt_batch_set_queues(%d)" % queues)
+
+    def set_round_graph(self, on: bool = True):
+        """Replay a HIP graph of the persistent round in later calls."""
+        st = lib().fbt_batch_set_round_graph(self._h, int(bool(on)))
+        if st != OK:
+            raise FisherBTError(st, "fbt_batch_set_round_graph")
 
     def set_round_trace(self, on: bool = True):
         """Record a per-task trace in later persistent calls."""

@@ -551,6 +551,19 @@ fbt_status fbt_batch_set_queues(fbt_batch *b, int32_t queues)
 
 int32_t fbt_batch_get_queues(const fbt_batch *b) { return b ? (b->queues ? b->queues : 8) : -1; }
 
+fbt_status fbt_batch_set_round_graph(fbt_batch *b, int32_t on)
+{
+    if (!b)
+        return FBT_EINVAL;
+    if (!b->round) {
+        b->round = fbt::round_create(b->cfg.device);
+        if (!b->round)
+            return FBT_EDEVICE;
+    }
+    fbt::round_set_graph(b->round, on != 0);
+    return FBT_OK;
+}
+
 fbt_status fbt_batch_set_round_trace(fbt_batch *b, int32_t on)
 {
     if (!b)

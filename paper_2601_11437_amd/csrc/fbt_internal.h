@@ -228,6 +228,9 @@ int round_task_count(const RoundExec *r);
 // round_trace copies the last call's: 5 int64 per task (ft, ij, times), up
 // to cap tasks; returns the task count (0: no trace)
 void round_set_trace(RoundExec *r, bool on);
+// later calls (without trace) replay a HIP graph of the round, captured once
+// per arena
+void round_set_graph(RoundExec *r, bool on);
 // task queues (1..8; a new plan at the next call when it changes)
 void round_set_queues(RoundExec *r, int queues);
 int round_queues(const RoundExec *r);

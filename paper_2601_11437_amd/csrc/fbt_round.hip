@@ -757,6 +757,14 @@ __global__ __launch_bounds__(rthreads(BT)) __attribute__((amdgpu_waves_per_eu(2,
     }
 }
 
+// counters to zero before a round (a kernel, not a memset: it may be
+// recorded into a HIP graph)
+__global__ __launch_bounds__(256) void k_zero_ints(int *p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        p[i] = 0;
+}
+
 } // namespace fbt
 
 // ===========================================================================
@@ -811,14 +819,30 @@ struct RoundExec {
     int nq = 1;
     std::vector<int64_t> qoff;
     int64_t *d_qoff = nullptr;
+    // HIP graph of the round (uploads, counter clearing, the kernel, result
+    // copies), captured once per arena when graph_on
+    bool graph_on = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
 };
 
 namespace {
 
 size_t up256(size_t b) { return (b + 255) / 256 * 256; }
 
+void drop_graph(RoundExec *r)
+{
+    if (r->gexec)
+        (void)hipGraphExecDestroy(r->gexec);
+    if (r->graph)
+        (void)hipGraphDestroy(r->graph);
+    r->gexec = nullptr;
+    r->graph = nullptr;
+}
+
 void free_arena(RoundExec *r)
 {
+    drop_graph(r);
     if (r->arena)
         (void)hipFree(r->arena);
     if (r->d_tasks)
@@ -1001,6 +1025,51 @@ fbt_status build(RoundExec *r, int bt, int nf, const int64_t *n, const double *c
 
 } // namespace
 
+// The device work of one round on r->stream: theta tables and field
+// descriptors up, counters cleared, the kernel (between r->e0 and r->e1 with
+// timing), results and counters down.  No allocation and no host wait, so it
+// can be captured.
+static hipError_t round_enqueue(RoundExec *r, int bt, int nf, long long *trace, bool timing)
+{
+    hipError_t e;
+    if ((e = hipMemcpyAsync(r->d_tab, r->h_tab, (size_t)nf * TAB_BYTES, hipMemcpyHostToDevice,
+                            r->stream)) != hipSuccess)
+        return e;
+    if ((e = hipMemcpyAsync(r->d_fields, r->h_fields, (size_t)nf * sizeof(RField),
+                            hipMemcpyHostToDevice, r->stream)) != hipSuccess)
+        return e;
+    const int64_t nz = (int64_t)r->cnt_ints;
+    hipLaunchKernelGGL(k_zero_ints, dim3((unsigned)std::min<int64_t>(1024, (nz + 255) / 256)),
+                       dim3(256), 0, r->stream, r->d_cnt, nz);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
+    int *ctl = r->d_cnt + (r->cnt_ints - R_CTL_WORDS);
+    const int64_t limit = (int64_t)5000 * r->tick_khz; // 5 s of waiting for one counter
+    if (timing && (e = hipEventRecord(r->e0, r->stream)) != hipSuccess)
+        return e;
+    if (bt == 64)
+        hipLaunchKernelGGL(k_round<64>, dim3(r->grid), dim3(rthreads(64)), 0, r->stream,
+                           r->d_fields, r->d_tasks, r->d_qoff, r->nq, ctl, limit, trace);
+    else
+        hipLaunchKernelGGL(k_round<128>, dim3(r->grid), dim3(rthreads(128)), 0, r->stream,
+                           r->d_fields, r->d_tasks, r->d_qoff, r->nq, ctl, limit, trace);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
+    if (timing && (e = hipEventRecord(r->e1, r->stream)) != hipSuccess)
+        return e;
+    if ((e = hipMemcpyAsync(r->h_out, r->d_out, (size_t)nf * 16 * sizeof(double),
+                            hipMemcpyDeviceToHost, r->stream)) != hipSuccess)
+        return e;
+    return hipMemcpyAsync(r->h_cnt, r->d_cnt, r->cnt_ints * sizeof(int), hipMemcpyDeviceToHost,
+                          r->stream);
+}
+
+void round_set_graph(RoundExec *r, bool on)
+{
+    if (r)
+        r->graph_on = on;
+}
+
 RoundExec *round_create(int device)
 {
     RoundExec *r = new RoundExec();
@@ -1108,29 +1177,28 @@ fbt_status round_eval(RoundExec *r, int bt, int nf, const int64_t *n, const doub
         F.gp = theta_params(th, 0, F.n, F.ld, F.ld, r->h_tab + (size_t)f * TAB_BYTES,
                             r->d_tab + (size_t)f * TAB_BYTES);
     }
-    RCHK(hipMemcpyAsync(r->d_tab, r->h_tab, (size_t)nf * TAB_BYTES, hipMemcpyHostToDevice,
-                        r->stream));
-    RCHK(hipMemcpyAsync(r->d_fields, r->h_fields, (size_t)nf * sizeof(RField),
-                        hipMemcpyHostToDevice, r->stream));
-    RCHK(hipMemsetAsync(r->d_cnt, 0, r->cnt_ints * sizeof(int), r->stream));
-    int *ctl = r->d_cnt + (r->cnt_ints - R_CTL_WORDS);
-    const int64_t limit = (int64_t)5000 * r->tick_khz; // 5 s of waiting for one counter
     if (r->trace_on && !r->d_trace)
         RCHK(hipMalloc((void **)&r->d_trace, (size_t)r->ntasks * 3 * sizeof(long long)));
     long long *trace = r->trace_on ? r->d_trace : nullptr;
-    RCHK(hipEventRecord(r->e0, r->stream));
-    if (bt == 64)
-        hipLaunchKernelGGL(k_round<64>, dim3(r->grid), dim3(rthreads(64)), 0, r->stream, r->d_fields,
-                           r->d_tasks, r->d_qoff, r->nq, ctl, limit, trace);
-    else
-        hipLaunchKernelGGL(k_round<128>, dim3(r->grid), dim3(rthreads(128)), 0, r->stream, r->d_fields,
-                           r->d_tasks, r->d_qoff, r->nq, ctl, limit, trace);
-    RCHK(hipGetLastError());
-    RCHK(hipEventRecord(r->e1, r->stream));
-    RCHK(hipMemcpyAsync(r->h_out, r->d_out, (size_t)nf * 16 * sizeof(double),
-                        hipMemcpyDeviceToHost, r->stream));
-    RCHK(hipMemcpyAsync(r->h_cnt, r->d_cnt, r->cnt_ints * sizeof(int), hipMemcpyDeviceToHost,
-                        r->stream));
+    if (r->graph_on && !trace) {
+        if (!r->gexec) {
+            // the round's work on the stream, captured once per arena: the
+            // copies read the pinned staging buffers at every replay
+            RCHK(hipStreamBeginCapture(r->stream, hipStreamCaptureModeThreadLocal));
+            const hipError_t e = round_enqueue(r, bt, nf, nullptr, false);
+            hipGraph_t g = nullptr;
+            const hipError_t e2 = hipStreamEndCapture(r->stream, &g);
+            r->graph = g;
+            RCHK(e);
+            RCHK(e2);
+            RCHK(hipGraphInstantiate(&r->gexec, r->graph, nullptr, nullptr, 0));
+        }
+        RCHK(hipEventRecord(r->e0, r->stream));
+        RCHK(hipGraphLaunch(r->gexec, r->stream));
+        RCHK(hipEventRecord(r->e1, r->stream));
+    } else {
+        RCHK(round_enqueue(r, bt, nf, trace, true));
+    }
     if (trace) {
         r->h_trace.resize((size_t)r->ntasks * 3);
         RCHK(hipMemcpyAsync(r->h_trace.data(), trace, r->h_trace.size() * sizeof(long long),

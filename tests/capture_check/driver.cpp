@@ -148,6 +148,46 @@ static int context()
     return 0;
 }
 
+// The persistent execution with its round graph: captured at the first call
+// for a field set and modes, replayed by the next, captured again for new
+// modes.  The round kernel does not run under the stand-in, so the calls
+// report the undrained round (FBT_EDEVICE); the calls themselves are checked.
+static int persistent()
+{
+    const int nf = 6;
+    std::vector<int64_t> n;
+    std::vector<std::vector<double>> locs, z;
+    fields(nf, n, locs, z);
+    std::vector<const double *> pl(nf), pz(nf);
+    for (int f = 0; f < nf; ++f) {
+        pl[f] = locs[f].data();
+        pz[f] = z[f].data();
+    }
+    fbt_config cfg;
+    std::memset(&cfg, 0, sizeof(cfg));
+    fbt_batch *b = nullptr;
+    CALL(30, fbt_batch_create(&cfg, 1, &b));
+    CALL(31, fbt_batch_set_fields(b, nf, n.data(), pl.data(), pz.data()));
+    CALL(32, fbt_batch_set_exec(b, FBT_BATCH_PERSISTENT));
+    CALL(33, fbt_batch_set_round_graph(b, 1));
+    std::vector<double> th(3 * nf), ll(nf), sc(3 * nf), fi(9 * nf);
+    std::vector<int32_t> mode(nf), st(nf);
+    for (int call = 0; call < 3; ++call) {
+        for (int f = 0; f < nf; ++f) {
+            th[3 * f] = 1.0 + 0.1 * call;
+            th[3 * f + 1] = 0.05 + 0.01 * f;
+            th[3 * f + 2] = 0.5;
+            mode[f] = call < 2 ? 1 + (f % 2) : 2;
+        }
+        const fbt_status r =
+            fbt_batch_eval(b, th.data(), mode.data(), ll.data(), sc.data(), fi.data(), st.data());
+        if (r != FBT_OK && r != FBT_EDEVICE)
+            return 34;
+    }
+    fbt_batch_destroy(b);
+    return 0;
+}
+
 int main()
 {
     int r;
@@ -161,6 +201,10 @@ int main()
     }
     if ((r = batch(FBT_BATCH_WORKERS)) != 0)
         return r;
+    if ((r = persistent()) != 0)
+        return r;
+    std::printf("persistent round graph: %ld captures, %ld graph launches\n",
+                hiprec_captures() - captures, hiprec_graph_launches() - launches);
     if ((r = context()) != 0)
         return r;
     const int v = hiprec_report(stdout);

@@ -91,4 +91,8 @@ def test_library_capture_sequence_is_legal(built):
     assert r.returncode == 0, r.stdout + r.stderr
     m = re.search(r"batch graph: (\d+) captures, (\d+) graph launches", r.stdout)
     assert m and int(m.group(1)) == 3 and int(m.group(2)) == 5
+    # the persistent round's graph: captured for the first modes, replayed,
+    # captured again for new modes
+    m = re.search(r"persistent round graph: (\d+) captures, (\d+) graph launches", r.stdout)
+    assert m and int(m.group(1)) == 2 and int(m.group(2)) == 3
     assert "no violations" in r.stdout

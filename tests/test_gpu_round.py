@@ -186,3 +186,30 @@ def test_round_many_field_workload():
         say("  loglik relative difference: median %.1e, max %.1e" % (np.median(rel), rel.max()))
         assert np.median(rel) <= 1e-10
     b.close()
+
+
+def test_round_graph_replays(small_fields):
+    """The persistent round replayed from a HIP graph: every replay, with other
+    eager work and synchronisations between the replays, gives bitwise the
+    direct launch's results for the same theta."""
+    data, thetas = small_fields
+    nf = len(data)
+    mode = np.array([2, 1] * nf)[:nf]
+    calls = [thetas * (1.0 + 0.03 * k) for k in range(3)]
+    direct = fbt.Batch(1)
+    direct.set_fields(data)
+    direct.set_exec(fbt.Batch.PERSISTENT)
+    want = [direct.eval(th, mode) for th in calls]
+    g = fbt.Batch(1)
+    g.set_fields(data)
+    g.set_exec(fbt.Batch.PERSISTENT)
+    g.set_round_graph(True)
+    for rep in range(2):
+        for k, th in enumerate(calls):
+            say("graph replay %d, theta set %d" % (rep, k))
+            got = g.eval(th, mode)
+            direct.eval(calls[(k + 1) % 3], mode)   # eager work between replays
+            for a, b in zip(got, want[k]):
+                np.testing.assert_array_equal(a, b)
+    g.close()
+    direct.close()
