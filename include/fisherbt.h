@@ -341,7 +341,7 @@ int32_t fbt_batch_get_tile(const fbt_batch *b); /* -1 for NULL */
  * first call).  Errors: FBT_EINVAL for NULL b. */
 fbt_status fbt_batch_round_stats(const fbt_batch *b, int64_t *ntasks, double *plan_us,
                                  double *kernel_ms);
-/* HIP graph of the persistent execution's round (off by default): with on,
+/* HIP graph of the persistent execution's round (on by default): with on,
  * later calls without a trace replay one graph - the uploads of the theta
  * tables and field descriptors from pinned staging, a kernel that clears the
  * counters, the round kernel, and the result copies - captured on the first

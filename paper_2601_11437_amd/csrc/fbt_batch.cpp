@@ -68,6 +68,7 @@ struct fbt_batch {
     fbt::RoundExec *round = nullptr;
     int tile = 0;   // 0: default (DEFAULT_TILE)
     int queues = 0; // 0: default (8)
+    int round_graph = 1; // the persistent round replayed from a HIP graph
 };
 
 namespace {
@@ -167,6 +168,7 @@ fbt_status persistent_eval(fbt_batch *b, const double *thetas, const int32_t *mo
     }
     if (any) {
         fbt::round_set_queues(b->round, b->queues ? b->queues : 8);
+        fbt::round_set_graph(b->round, b->round_graph != 0);
         std::string err;
         const fbt_status st = fbt::round_eval(b->round, b->tile ? b->tile : DEFAULT_TILE, nf,
                                               b->n.data(), lp.data(), zp.data(),
@@ -555,12 +557,7 @@ fbt_status fbt_batch_set_round_graph(fbt_batch *b, int32_t on)
 {
     if (!b)
         return FBT_EINVAL;
-    if (!b->round) {
-        b->round = fbt::round_create(b->cfg.device);
-        if (!b->round)
-            return FBT_EDEVICE;
-    }
-    fbt::round_set_graph(b->round, on != 0);
+    b->round_graph = on != 0;
     return FBT_OK;
 }
 

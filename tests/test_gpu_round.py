@@ -199,6 +199,7 @@ def test_round_graph_replays(small_fields):
     direct = fbt.Batch(1)
     direct.set_fields(data)
     direct.set_exec(fbt.Batch.PERSISTENT)
+    direct.set_round_graph(False)
     want = [direct.eval(th, mode) for th in calls]
     g = fbt.Batch(1)
     g.set_fields(data)
