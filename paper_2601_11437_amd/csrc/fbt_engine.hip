@@ -1035,6 +1035,8 @@ fbt_status wphase_sygst_enqueue(fbt_ctx *c)
         TIMED(c, sd, KC_DUPD, 2.0 * 2.0 * real(rn, la) * K * real(0, cols),
               launch_update_nn(sd, c->F, c->F.sS2, 2, S2, ld, A, ld, rn, r0, la, cols, npad, K, mix));
         HIPCHK(c, ev_wait(sdb, c->evP2));
+        // the two bulk updates alternate: this one after the pair's rank-2k update
+        HIPCHK(c, ev_wait(sdb, c->evB));
         if (rn + la < npad)
             TIMED(c, sdb, KC_DUPD, 2.0 * 2.0 * real(rn + la, npad) * K * real(0, cols),
                   launch_update_nn(sdb, c->F, c->F.sS2, 2, S2, ld, A, ld, rn + la, r0,
@@ -1065,6 +1067,9 @@ fbt_status wphase_sygst_enqueue(fbt_ctx *c)
             HIPCHK(c, ev_wait(s0, c->evB));
             rect(rn, rn, la, b, KS, Y);
             HIPCHK(c, ev_wait(s1, c->evP));
+            // after the previous pair's deferred bulk update (the two bulk
+            // updates alternate)
+            HIPCHK(c, ev_wait(s1, c->evB2));
             const int64_t t0 = rn + la;
             if (t0 < npad)
                 TIMED(c, s1, KC_SUPD, 2.0 * 2.0 * real(t0, npad) * real(t0, npad) * KS,
