@@ -282,13 +282,18 @@ const char *fbt_batch_last_error(const fbt_batch *b);
  * of that field.  active (NULL: all) selects fields; res[nf] and status[nf]
  * receive each selected field's result and fbt_fit_evaluator's status
  * (FBT_EBUDGET with nelder_mead = 0 included); *rounds (may be NULL) the
- * number of evaluation rounds.  opt->cb runs on the fields' host threads
- * (one per selected field; cb_user is shared).  Returns FBT_OK unless a
+ * number of evaluation rounds.  opt->cb runs on the fits' host threads
+ * (cb_user is shared).  Returns FBT_OK unless a
  * round failed as a whole (FBT_EDEVICE, FBT_ENOMEM; the fits then stop with
  * that status), or FBT_EINVAL for bad arguments. */
 fbt_status fbt_batch_fit(fbt_batch *b, const fbt_fit_options *opt, const double *theta0,
                          const int32_t *active, fbt_fit_result *res, int32_t *status,
                          int32_t *rounds);
+/* Fits of fbt_batch_fit that run at once (one host thread each; 0: the
+ * default, 512): the other fields' fits start as running ones end.  The
+ * results of every fit do not depend on it.  threads in [0, 4096].
+ * Errors: FBT_EINVAL. */
+fbt_status fbt_batch_set_fit_threads(fbt_batch *b, int32_t threads);
 
 /* Execution of fbt_batch_eval (batched evaluations of one Fisher-BT
  * iteration over many fields, the batching of Section 2's estimator across

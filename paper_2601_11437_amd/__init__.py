@@ -103,6 +103,7 @@ SIGNATURES = {
     "fbt_batch_load_tuning": (ctypes.c_int, [_p, ctypes.c_char_p]),
     "fbt_batch_fit": (ctypes.c_int, [_p, ctypes.POINTER(FitOptions), _p, _p, _p, _p,
                                      ctypes.POINTER(_i32)]),
+    "fbt_batch_set_fit_threads": (ctypes.c_int, [_p, _i32]),
     "fbt_batch_set_tile": (ctypes.c_int, [_p, _i32]),
     "fbt_batch_get_tile": (_i32, [_p]),
     "fbt_batch_round_stats": (ctypes.c_int, [_p, ctypes.POINTER(_i64), _dp, _dp]),
@@ -484,6 +485,12 @@ class Batch:
             d["status"] = int(status[f])
             out.append(d)
         return out, status, int(rounds.value)
+
+    def set_fit_threads(self, threads: int):
+        """Fits of Batch.fit running at once (0: default)."""
+        st = lib().fbt_batch_set_fit_threads(self._h, int(threads))
+        if st != OK:
+            raise FisherBTError(st, "fbt_batch_set_fit_threads(%d)" % threads)
 
     def set_tile(self, tile: int):
         """Tile rows of the persistent execution: 64, 128 or 0 (default)."""

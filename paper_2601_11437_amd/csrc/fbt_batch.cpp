@@ -69,6 +69,7 @@ struct fbt_batch {
     int tile = 0;   // 0: default (DEFAULT_TILE)
     int queues = 0; // 0: default (8)
     int round_graph = 1; // the persistent round replayed from a HIP graph
+    int fit_threads = 0; // fbt_batch_fit: fits running at once (0: FIT_THREADS)
 };
 
 namespace {
@@ -352,16 +353,22 @@ const char *fbt_batch_last_error(const fbt_batch *b) { return b ? b->err.c_str()
 namespace {
 
 // Batched Fisher-BT: every field runs the library's driver (fbt_fit_evaluator,
-// Algorithm 1) on a host thread of its own, with an evaluator that posts the
-// request and sleeps; once every running driver has posted (or finished), the
-// calling thread evaluates all posted requests in one fbt_batch_eval call (a
-// round: one launch of the round kernel in the persistent execution) and
-// wakes the drivers with their results.  Each driver sees exactly the
+// Algorithm 1) on a host thread, with an evaluator that posts the request and
+// sleeps; once every running driver has posted, the calling thread evaluates
+// all posted requests in one fbt_batch_eval call (a round: one launch of the
+// round kernel in the persistent execution) and wakes the drivers with their
+// results.  At most FIT_THREADS fits run at once: a thread whose fit ends
+// takes the next field (counted as running throughout, so that no round
+// starts in between with fewer fields).  Each driver sees exactly the
 // evaluations a single-field fit over the batch's evaluator would see.
+constexpr int FIT_THREADS = 512; // default of fbt_batch_set_fit_threads
+
 struct FitShared {
     std::mutex mu;
     std::condition_variable coord, field;
-    int posted = 0, finished = 0;
+    int posted = 0;  // drivers waiting for their request's result
+    int running = 0; // drivers inside a fit
+    size_t next = 0; // next field of the run list
 };
 
 struct FitSlot {
@@ -430,24 +437,36 @@ fbt_status fbt_batch_fit(fbt_batch *b, const fbt_fit_options *opt, const double 
     if (rounds)
         *rounds = 0;
     const int nrun = (int)run.size();
+    const int nthreads = std::min(nrun, b->fit_threads > 0 ? b->fit_threads : FIT_THREADS);
+    S.running = nthreads; // each thread starts inside its first fit
+    S.next = (size_t)nthreads;
     std::vector<std::thread> th;
-    th.reserve(nrun);
-    for (int32_t f : run)
-        th.emplace_back([&, f] {
-            fbt_evaluator ev{&slot[f], fit_loglik, fit_eval};
-            std::memset(&res[f], 0, sizeof(fbt_fit_result));
-            status[f] = fbt_fit_evaluator(&ev, &o[f], &res[f]);
-            std::lock_guard<std::mutex> g(S.mu);
-            ++S.finished;
-            S.coord.notify_one();
+    th.reserve(nthreads);
+    for (int w = 0; w < nthreads; ++w)
+        th.emplace_back([&, w] {
+            size_t k = (size_t)w;
+            for (;;) {
+                const int32_t f = run[k];
+                fbt_evaluator ev{&slot[f], fit_loglik, fit_eval};
+                std::memset(&res[f], 0, sizeof(fbt_fit_result));
+                status[f] = fbt_fit_evaluator(&ev, &o[f], &res[f]);
+                std::lock_guard<std::mutex> g(S.mu);
+                if (S.next < run.size()) {
+                    k = S.next++; // stays running: the next field's fit starts at once
+                    continue;
+                }
+                --S.running;
+                S.coord.notify_one();
+                return;
+            }
         });
     std::vector<double> thetas(3 * (size_t)nf, 1.0), ll(nf), sc(3 * (size_t)nf), fi(9 * (size_t)nf);
     std::vector<int32_t> mode(nf), st(nf);
     fbt_status fatal = FBT_OK;
     std::unique_lock<std::mutex> lk(S.mu);
     for (;;) {
-        S.coord.wait(lk, [&] { return S.posted + S.finished == nrun; });
-        if (S.finished == nrun)
+        S.coord.wait(lk, [&] { return S.posted == S.running; });
+        if (S.running == 0)
             break;
         for (int32_t f = 0; f < nf; ++f) {
             mode[f] = slot[f].posted ? slot[f].mode : 0;
@@ -542,6 +561,14 @@ fbt_status fbt_batch_set_tile(fbt_batch *b, int32_t tile)
 }
 
 int32_t fbt_batch_get_tile(const fbt_batch *b) { return b ? (b->tile ? b->tile : DEFAULT_TILE) : -1; }
+
+fbt_status fbt_batch_set_fit_threads(fbt_batch *b, int32_t threads)
+{
+    if (!b || threads < 0 || threads > 4096)
+        return FBT_EINVAL;
+    b->fit_threads = threads;
+    return FBT_OK;
+}
 
 fbt_status fbt_batch_set_queues(fbt_batch *b, int32_t queues)
 {

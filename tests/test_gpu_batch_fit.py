@@ -87,3 +87,25 @@ def test_batch_fit_matches_single_field_fits(fields):
         assert (got["n_loglik_calls"], got["n_grad_calls"]) == (ref["n_loglik_calls"],
                                                                ref["n_grad_calls"])
         assert rel.max() <= 1e-8
+
+
+def test_batch_fit_with_few_threads(fields):
+    """Two fits at a time (the others start as those end): every field's
+    result bitwise the one of the run with all fits at once."""
+    data, theta_true = fields
+    out = []
+    for threads in (0, 2):
+        b = fbt.Batch(1)
+        b.set_fields(data)
+        b.set_exec(fbt.Batch.PERSISTENT)
+        b.set_fit_threads(threads)
+        say("batched fit, %d fits at once" % (threads or len(data)))
+        out.append(b.fit())
+        b.close()
+    (a, sa, ra), (c, sc, rc) = out
+    say("  rounds %d and %d" % (ra, rc))
+    assert rc > ra
+    np.testing.assert_array_equal(sa, sc)
+    for x, y in zip(a, c):
+        for k in ("theta", "loglik", "score", "fisher", "n_loglik_calls", "n_grad_calls"):
+            np.testing.assert_array_equal(x[k], y[k])
