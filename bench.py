@@ -450,11 +450,13 @@ def precision_bench(args):
     ctx = fbt.Context(0)
     ctx.set_data(locs, z)
     res = {}
-    # MIXED_FP32_ALL as it is by default, and with two refinement steps of w
+    # the _ALL forms as they are by default, and with two refinement steps of w
     for name, prec, refine in (("fp64", fbt.FP64, 0), ("mixed_fp32", fbt.MIXED_FP32, 0),
                                ("mixed_fp32_all", fbt.MIXED_FP32_ALL, 0),
                                ("mixed_fp32_all_refined", fbt.MIXED_FP32_ALL, 2),
-                               ("mixed_bf16", fbt.MIXED_BF16, 0)):
+                               ("mixed_bf16", fbt.MIXED_BF16, 0),
+                               ("mixed_bf16_all", fbt.MIXED_BF16_ALL, 0),
+                               ("mixed_bf16_all_refined", fbt.MIXED_BF16_ALL, 2)):
         ctx.set_precision(prec)
         ctx.set_refinement(refine)
         try:
@@ -507,7 +509,8 @@ def precision_bench(args):
     scale = np.array([(t[1] + n) / (2 * theta[0]), 0.5 * (abs(t[2]) + abs(t[4])),
                       0.5 * (abs(t[3]) + abs(t[5]))])
     fd = np.diag(np.array(ref["fisher"]))
-    for name in ("mixed_fp32", "mixed_fp32_all", "mixed_fp32_all_refined", "mixed_bf16"):
+    for name in ("mixed_fp32", "mixed_fp32_all", "mixed_fp32_all_refined", "mixed_bf16",
+                 "mixed_bf16_all", "mixed_bf16_all_refined"):
         r = res[name]
         if "loglik" not in r:
             continue

@@ -68,12 +68,19 @@ typedef enum {
  *   rounded to bfloat16 (8-bit significand) and the products summed in FP32
  *   (v_mfma_f32_16x16x16_bf16).  The log-likelihood is the FP64 one; score and
  *   Fisher carry bfloat16 rounding of the W phase's updates, amplified by the
- *   conditioning of Sigma (errors of order 1e-3 relative or worse). */
+ *   conditioning of Sigma (errors of order 1e-3 relative or worse).
+ * FBT_MIXED_BF16_ALL: the Cholesky trailing updates with bfloat16 operands
+ *   and FP32 sums as well (the W phase as FBT_MIXED_BF16): the factor carries
+ *   bfloat16 rounding, so the form suits well-conditioned Sigma only (short
+ *   range); the factorisation fails (FBT_ENOTPD) once that rounding exceeds
+ *   Sigma's smallest eigenvalues.  Refinement of w (fbt_set_refinement) and
+ *   the fit's refusal as under FBT_MIXED_FP32_ALL. */
 typedef enum {
     FBT_FP64 = 0,
     FBT_MIXED_FP32 = 1,
     FBT_MIXED_FP32_ALL = 2,
-    FBT_MIXED_BF16 = 3
+    FBT_MIXED_BF16 = 3,
+    FBT_MIXED_BF16_ALL = 4
 } fbt_precision;
 
 typedef struct {
@@ -424,12 +431,12 @@ fbt_status fbt_batch_load_tuning(fbt_batch *b, const char *path);
 typedef enum { FBT_SIGMA_NU_EXACT = 0, FBT_SIGMA_NU_PAPER = 1 } fbt_sigma_nu_mode;
 fbt_status fbt_set_sigma_nu_mode(fbt_ctx *ctx, int32_t mode);
 
-/* Iterative refinement under FBT_MIXED_FP32_ALL (ignored otherwise and in
+/* Iterative refinement under FBT_MIXED_FP32_ALL and FBT_MIXED_BF16_ALL (ignored otherwise and in
  * batched groups): after the factorisation, `iterations` steps (default 0)
  *   w <- w + (L L^T)^{-1} (Z - Sigma w),   w_0 = (L L^T)^{-1} Z,
  * with the residual in FP64 from a copy of Sigma taken before the
  * factorisation (8 npad^2 more bytes of device memory while the form is in
- * use), L the factor with FP32 trailing updates; then Z^T Sigma^{-1} Z =
+ * use), L the factor with FP32 or bfloat16 trailing updates; then Z^T Sigma^{-1} Z =
  * Z^T w, and in fbt_eval w^T Sigma_i w from the derivative matrices.  Each
  * step costs one product with Sigma and two triangular solves with the
  * factor.  The log-likelihood and score are not always closer to FP64 with

@@ -56,7 +56,7 @@ class Config(ctypes.Structure):
     _fields_ = [("device", _i32), ("tile", _i32), ("precision", _i32), ("hip_stream", _p)]
 
 
-FP64, MIXED_FP32, MIXED_FP32_ALL, MIXED_BF16 = 0, 1, 2, 3
+FP64, MIXED_FP32, MIXED_FP32_ALL, MIXED_BF16, MIXED_BF16_ALL = 0, 1, 2, 3, 4
 SIGMA_NU_EXACT, SIGMA_NU_PAPER = 0, 1
 WPHASE_TWO_SIDED, WPHASE_SOLVES = 0, 1
 
@@ -356,8 +356,9 @@ class Context:
 
     def set_precision(self, precision: int):
         """FP64 (0), MIXED_FP32 (1: solve updates in FP32), MIXED_FP32_ALL
-        (2: Cholesky updates too) or MIXED_BF16 (3: solve updates with
-        bfloat16 operands and FP32 sums) for the following evaluations."""
+        (2: Cholesky updates too), MIXED_BF16 (3: solve updates with
+        bfloat16 operands and FP32 sums) or MIXED_BF16_ALL (4: Cholesky
+        updates too) for the following evaluations."""
         self._check(lib().fbt_set_precision(self._h, int(precision)))
 
     def set_sigma_nu_mode(self, mode: int):

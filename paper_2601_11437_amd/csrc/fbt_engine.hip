@@ -442,10 +442,16 @@ bool use_two_sided(fbt_ctx *c, bool may_alloc = true)
            c->cap_vd >= (size_t)c->G * vd_stride(c) * 8 && c->cap_pd >= (size_t)c->G * pd_stride() * 8;
 }
 
-// FBT_MIXED_FP32_ALL on a single field refines w = Sigma^{-1} Z (see refine_w)
+// the forms whose Cholesky trailing updates are low precision
+bool low_factor(int precision)
+{
+    return precision == FBT_MIXED_FP32_ALL || precision == FBT_MIXED_BF16_ALL;
+}
+
+// FBT_MIXED_FP32_ALL / _BF16_ALL on a single field refine w = Sigma^{-1} Z (see refine_w)
 bool refines(const fbt_ctx *c)
 {
-    return c->precision == FBT_MIXED_FP32_ALL && c->refine_iters > 0 && !c->batched;
+    return low_factor(c->precision) && c->refine_iters > 0 && !c->batched;
 }
 
 // The copy of Sigma that refinement takes its residuals from (npad x ld).
@@ -618,7 +624,8 @@ fbt_status factorize_enqueue(fbt_ctx *c, const GenParams &gp, int mode)
     hipStream_t s0 = c->stream, s1 = c->capturable ? c->stream2 : c->stream3;
     double *A = c->A;
     const double dNB = NB;
-    const int mix = c->precision == FBT_MIXED_FP32_ALL; // Cholesky updates in FP32
+    // Cholesky updates in FP32 (1) or with BF16 operands and FP32 sums (2)
+    const int mix = c->precision == FBT_MIXED_FP32_ALL ? 1 : c->precision == FBT_MIXED_BF16_ALL ? 2 : 0;
     auto Lk = [&](int k) { return c->Linv + (size_t)k * NB * NB; };
     launch_init_info(s0, c->info, c->G);
     TIMED(c, s0, KC_GEN, 0.0, launch_gen(s0, gp, c->d_gpa, c->F, c->x, c->y, c->z, A, c->S2,
@@ -831,7 +838,9 @@ fbt_status wphase_enqueue(fbt_ctx *c)
     double *Sa = c->S2, *Sn = c->S2 + npad * ld, *A = c->A;
     const double dn = (double)n, dNB = NB;
     // solve updates: FP32 (1) or BF16 operands with FP32 sums (2)
-    const int mix = c->precision == FBT_FP64 ? 0 : c->precision == FBT_MIXED_BF16 ? 2 : 1;
+    const int mix = c->precision == FBT_FP64 ? 0
+                    : (c->precision == FBT_MIXED_BF16 || c->precision == FBT_MIXED_BF16_ALL) ? 2
+                                                                                           : 1;
     auto Lk = [&](int k) { return c->Linv + (size_t)k * NB * NB; };
     // mixed forms with their operand copies: the factor once, each solved pair of
     // block rows as the diagonal apply writes it (slot by pair parity, so the
@@ -972,7 +981,9 @@ fbt_status wphase_sygst_enqueue(fbt_ctx *c)
     const double dNB = NB;
     // the rank-2k updates and the deferred solve's updates: FP32 (1) or BF16
     // operands (2) with FP32 sums in the mixed precisions; everything else FP64
-    const int mix = c->precision == FBT_FP64 ? 0 : c->precision == FBT_MIXED_BF16 ? 2 : 1;
+    const int mix = c->precision == FBT_FP64 ? 0
+                    : (c->precision == FBT_MIXED_BF16 || c->precision == FBT_MIXED_BF16_ALL) ? 2
+                                                                                           : 1;
     auto Lk = [&](int k) { return c->Linv + (size_t)k * NB * NB; };
     auto Vk = [&](int k) { return c->Vd + (size_t)k * NB * NB; };
     auto slot = [&](int b) { return c->Ysl + (size_t)((b / 2) & 1) * (2 * npad * (2 * NB)); };
@@ -1434,7 +1445,7 @@ fbt_status fbt::fit_eval(fbt_ctx *c, const double *th, double mixed_switch, int 
     *state = 1;
     // derivative_terms leaves the factor of th in place; it is the FP64 one
     // unless the Cholesky updates were FP32 as well
-    c->factor_valid = c->precision != FBT_MIXED_FP32_ALL;
+    c->factor_valid = !low_factor(c->precision);
     std::memcpy(c->factor_theta, th, sizeof(c->factor_theta));
     c->precision = FBT_FP64;
     if ((st = derivative_terms(c, th, t)) != FBT_OK)
@@ -1631,7 +1642,7 @@ fbt_status fbt_create(const fbt_config *cfg, fbt_ctx **out)
         return FBT_EINVAL;
     *out = nullptr;
     if (!(cfg->tile == 0 || cfg->tile == NB) ||
-        cfg->precision < FBT_FP64 || cfg->precision > FBT_MIXED_BF16)
+        cfg->precision < FBT_FP64 || cfg->precision > FBT_MIXED_BF16_ALL)
         return FBT_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev)
@@ -1852,11 +1863,10 @@ fbt_status fbt_factor(fbt_ctx *ctx, const double theta[3], double *out, int64_t 
 
 fbt_status fbt_set_precision(fbt_ctx *ctx, int32_t precision)
 {
-    if (!ctx || precision < FBT_FP64 || precision > FBT_MIXED_BF16)
+    if (!ctx || precision < FBT_FP64 || precision > FBT_MIXED_BF16_ALL)
         return FBT_EINVAL;
-    // the factorisation's arithmetic differs only under FBT_MIXED_FP32_ALL
-    if (precision != ctx->precision &&
-        (precision == FBT_MIXED_FP32_ALL || ctx->precision == FBT_MIXED_FP32_ALL))
+    // the factorisation's arithmetic differs only under the _ALL forms
+    if (precision != ctx->precision && (low_factor(precision) || low_factor(ctx->precision)))
         ctx->factor_valid = false;
     ctx->precision = precision;
     return FBT_OK;

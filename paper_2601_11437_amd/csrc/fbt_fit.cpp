@@ -386,9 +386,10 @@ fbt_status fbt_fit(fbt_ctx *ctx, const fbt_fit_options *opt, fbt_fit_result *out
         return FBT_EINVAL;
     const int32_t prec = fbt::ctx_precision(ctx);
     // The line search's acceptance tests (Eq. (4)) take FP64 log-likelihoods;
-    // under FBT_MIXED_FP32_ALL fbt_loglik carries FP32 rounding of the
-    // factorisation, which no refinement of the solves removes.
-    if (prec == FBT_MIXED_FP32_ALL)
+    // under FBT_MIXED_FP32_ALL and _BF16_ALL fbt_loglik carries the low
+    // precision rounding of the factorisation, which no refinement of the
+    // solves removes.
+    if (prec == FBT_MIXED_FP32_ALL || prec == FBT_MIXED_BF16_ALL)
         return FBT_EINVAL;
     GpuFit g = {ctx, prec == FBT_FP64, opt->mixed_switch, 0, 0, 0, -1};
     fbt_evaluator ev = {&g, gpu_loglik, gpu_eval};

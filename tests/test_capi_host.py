@@ -54,7 +54,8 @@ def test_null_arguments_are_rejected():
     assert L.fbt_set_wphase(None, fbt.WPHASE_TWO_SIDED) == fbt.EINVAL
     assert L.fbt_set_refinement(None, 2) == fbt.EINVAL
     assert L.fbt_set_precision(None, 0) == fbt.EINVAL
-    assert (fbt.FP64, fbt.MIXED_FP32, fbt.MIXED_FP32_ALL, fbt.MIXED_BF16) == (0, 1, 2, 3)
+    assert (fbt.FP64, fbt.MIXED_FP32, fbt.MIXED_FP32_ALL, fbt.MIXED_BF16,
+            fbt.MIXED_BF16_ALL) == (0, 1, 2, 3, 4)
     L.fbt_destroy(None)                      # NULL-safe
     # batch entry points
     cfg = fbt.Config(0, 0, 0, None)

@@ -337,6 +337,60 @@ def test_mixed_fp32_all(ctx, oracle_mod, n, theta):
     assert e_ll > 0                                     # the FP32 factorisation really ran
 
 
+@pytest.mark.parametrize("n,theta", [(600, (1.0, 0.02, 0.5)), (1500, (1.2, 0.015, 0.8))])
+def test_mixed_bf16_all(ctx, oracle_mod, n, theta):
+    """FBT_MIXED_BF16_ALL: the Cholesky trailing updates with bfloat16
+    operands and FP32 sums too, on short-range (well-conditioned) covariances,
+    against the oracle.  Measured on MI355X at n = 600 / 1,500: loglik
+    5.5e-5 / 1.4e-5 relative, score up to 5.9e-4 / 1.2e-3 of its per-term
+    scale, Fisher 4.5e-3 / 1.4e-2 relative; the quadratic forms q and u_i
+    1e-4 / 0.13 unrefined, and after 2, 4, 8 refinement steps of w 6e-7,
+    7e-10, 7e-16 / 2.4e-3, 2.6e-4, 2.0e-7 (the log determinant and the
+    traces keep the factor's bfloat16 rounding).  Gates: loglik 1e-2, score
+    1e-1, Fisher 1e-1; refinement: two steps gain at least 20 times, more
+    steps never lose, eight reach 1e-6."""
+    say("bf16-all n=%d theta=%s" % (n, theta))
+    locs, z, _ = synth.dataset(n, (1.0, 0.1, 0.5), 3000 + n)
+    ctx.set_data(locs, z)
+    want = oracle_mod.evaluate(locs, z, theta)
+    ctx.set_precision(fbt.MIXED_BF16_ALL)
+    try:
+        ll, score, fisher = ctx.eval(theta)
+        t0 = ctx.eval_terms(theta)
+        tr = {}
+        for k in (2, 4, 8):
+            ctx.set_refinement(k)
+            tr[k] = ctx.eval_terms(theta)
+        with pytest.raises(fbt.FisherBTError) as e:
+            ctx.fit()
+        assert e.value.status == fbt.EINVAL
+    finally:
+        ctx.set_refinement(0)
+        ctx.set_precision(fbt.FP64)
+    scale = np.array([(want["quad"] + n) / (2 * theta[0]),
+                      0.5 * (abs(want["trace"]["a"]) + abs(want["wSw"]["a"])),
+                      0.5 * (abs(want["trace"]["n"]) + abs(want["wSw"]["n"]))])
+    e_ll = abs(ll - want["loglik"]) / abs(want["loglik"])
+    err = np.abs(score - want["score"]) / scale
+    I = want["fisher"]
+    d = np.sqrt(np.outer(np.diag(I), np.diag(I)))
+    e_f = np.max(np.abs(fisher - I) / d)
+    ref = np.array([want["quad"], want["wSw"]["a"], want["wSw"]["n"]])
+    q0 = np.abs(np.array([t0[1], t0[4], t0[5]]) - ref) / np.abs(ref)
+    qk = {k: np.abs(np.array([t[1], t[4], t[5]]) - ref) / np.abs(ref) for k, t in tr.items()}
+    say("against the oracle: loglik %.2e score/scale %s fisher %.2e; quadratic forms "
+        "unrefined %s, after 2/4/8 refinement steps %s %s %s"
+        % (e_ll, err, e_f, q0, qk[2], qk[4], qk[8]))
+    assert e_ll > 0                                     # the BF16 factorisation really ran
+    assert e_ll <= 1e-2 and np.all(err <= 1e-1) and e_f <= 1e-1
+    # refinement converges
+    assert np.all(qk[2] <= 0.05 * q0)
+    assert np.all(qk[8] <= np.maximum(qk[4], 1e-13)) and np.all(qk[4] <= np.maximum(qk[2], 1e-13))
+    assert np.all(qk[8] <= 1e-6)
+    for k in (2, 4, 8):                                 # log det and traces untouched
+        assert tr[k][0] == t0[0] and tr[k][2] == t0[2] and tr[k][3] == t0[3]
+
+
 @pytest.mark.parametrize("n,theta", [(2, (1.0, 0.1, 0.5)), (257, (0.8, 0.12, 0.9)),
                                      (600, (1.0, 0.1, 0.5)), (1500, (1.5, 0.07, 1.0))])
 def test_fp32_all_refinement(ctx, oracle_mod, n, theta):
