@@ -214,9 +214,9 @@ void fbt_fit_options_default(fbt_fit_options *o);
  * relaxed Armijo backtracking of Eq. (4), stop at ||grad|| <= grad_tol, shift
  * to Nelder-Mead when a call budget is exceeded, then one Fisher evaluation
  * at the result.  Every l and derivative evaluation runs on the GPU.
- * Errors: FBT_EINVAL (also for a context in FBT_MIXED_FP32_ALL: its
- * log-likelihood is not the FP64 one that the acceptance tests of Eq. (4)
- * take), FBT_ENODATA, FBT_ENOTPD (every L9 candidate failed),
+ * Errors: FBT_EINVAL (also for a context in FBT_MIXED_FP32_ALL or
+ * FBT_MIXED_BF16_ALL: its log-likelihood is not the FP64 one that the
+ * acceptance tests of Eq. (4) take), FBT_ENODATA, FBT_ENOTPD (every L9 candidate failed),
  * FBT_EBUDGET (budget exhausted with nelder_mead = 0; *out still holds the
  * last iterate), FBT_EDEVICE. */
 fbt_status fbt_fit(fbt_ctx *ctx, const fbt_fit_options *opt, fbt_fit_result *out);
@@ -292,7 +292,8 @@ const char *fbt_batch_last_error(const fbt_batch *b);
  * number of evaluation rounds.  opt->cb runs on the fits' host threads
  * (cb_user is shared).  Returns FBT_OK unless a
  * round failed as a whole (FBT_EDEVICE, FBT_ENOMEM; the fits then stop with
- * that status), or FBT_EINVAL for bad arguments. */
+ * that status), or FBT_EINVAL for bad arguments and for a batch in
+ * FBT_MIXED_FP32_ALL or FBT_MIXED_BF16_ALL (as fbt_fit). */
 fbt_status fbt_batch_fit(fbt_batch *b, const fbt_fit_options *opt, const double *theta0,
                          const int32_t *active, fbt_fit_result *res, int32_t *status,
                          int32_t *rounds);

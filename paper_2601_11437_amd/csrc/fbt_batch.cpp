@@ -422,6 +422,12 @@ fbt_status fbt_batch_fit(fbt_batch *b, const fbt_fit_options *opt, const double 
 {
     if (!b || !opt || !res || !status)
         return FBT_EINVAL;
+    // as fbt_fit: the acceptance tests of Eq. (4) take FP64 log-likelihoods
+    if (b->cfg.precision == FBT_MIXED_FP32_ALL || b->cfg.precision == FBT_MIXED_BF16_ALL) {
+        b->err = "batch fit: the FP32 and bfloat16 Cholesky forms change the log-likelihood that "
+                 "the acceptance tests of Eq. (4) take";
+        return FBT_EINVAL;
+    }
     const int32_t nf = (int32_t)b->n.size();
     FitShared S;
     std::vector<FitSlot> slot(nf);

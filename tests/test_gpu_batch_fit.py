@@ -109,3 +109,16 @@ def test_batch_fit_with_few_threads(fields):
     for x, y in zip(a, c):
         for k in ("theta", "loglik", "score", "fisher", "n_loglik_calls", "n_grad_calls"):
             np.testing.assert_array_equal(x[k], y[k])
+
+
+@pytest.mark.parametrize("precision", [fbt.MIXED_FP32_ALL, fbt.MIXED_BF16_ALL])
+def test_batch_fit_refuses_low_precision_cholesky(fields, precision):
+    """As fbt_fit, the batched fit refuses the forms whose log-likelihood
+    carries low-precision Cholesky rounding (FBT_EINVAL, with the reason)."""
+    data, _ = fields
+    b = fbt.Batch(1, precision=precision)
+    b.set_fields(data[:2])
+    with pytest.raises(fbt.FisherBTError) as e:
+        b.fit()
+    assert e.value.status == fbt.EINVAL and "Cholesky" in str(e.value)
+    b.close()
